@@ -1,0 +1,238 @@
+"""Benchmark of the interface-node Monte Carlo hot path on one MI355X.
+
+Headline workload (C5): 3-D unit ball, 1/2 Lap u - c u = -f with boundary data
+g = sum_{k<64} theta_k r^l Y_k and 16-term polynomial c, f; 4096 interface
+nodes on the three discs x_k = 0, |x| < 0.95; 1e5 paths per node; dt = 1e-3;
+FP32 stepping and transforms, FP64 accumulation.  One step = the batched
+forward pass at theta plus the adjoint of the loss sum_i (u_i - d_i)^2
+(persistent kernels replayed from a cached hipGraph).
+
+value = path-steps of the estimator (forward pass) per second of the whole
+forward + adjoint step.  Also reported: forward-only and adjoint-only rates,
+interface nodes per second at a standard error of 1e-3 (derived from the
+measured per-node variances and step counts), the speed-up over the plain
+FP64 one-node-per-launch kernel, the ALU roofline of the dominant kernel and
+the FP64 CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 compute units, 64 lanes each issue one VALU op per clock at 2.4 GHz
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# Algorithmic VALU lane-ops per path-step of the C5 walk (see the design notes
+# for the count): Philox4x32-10 = 10 rounds x (2 x 32x32->64 products at
+# quarter rate (8 slots) + 2 three-input xors) = 100 slots per block of 4
+# uniforms; QUAD24 + Box-Muller per pair = 2 conversions + log2, sqrt, sin,
+# cos at quarter rate (16) + 4 multiplies = 22.  A 3-D step uses 3/4 block and
+# 1.5 pairs: 75 + 33 = 108.  Then 20 cubic monomials (16 multiplies), f and c
+# (40 FMA), killing factor exp (1 multiply + exp2 at 4 = 5), Z/Y update (3),
+# X update (3 FMA), ball exit test (3 sub + 3 FMA + compare = 7): 74.
+# Forward: 182 per path-step.  Adjoint adds 3 x 20 tangent FMAs (F, S, A)
+# and two products (Y dt, f Y dt): 62, so 244 per path-step.
+OPS_PER_PS_FWD = 182.0
+OPS_PER_PS_ADJ = 244.0
+
+
+def run(args):
+    import torch
+    import paper_1705_03666_amd as pdd
+    from workloads import configs as CF
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = CF.c5(scale=args.scale, n_nodes=args.nodes)
+    P = w.problem_template
+    nodes = torch.tensor(w.nodes, device=dev)
+    paths = w.paths
+    n = len(paths)
+    sh = torch.tensor(w.sh_matrix, device=dev)
+    sel = torch.tensor(w.fc_matrix, device=dev)
+    theta = {k: torch.tensor(v, device=dev) for k, v in (("g", w.theta_g), ("f", w.theta_f), ("c", w.theta_c))}
+    coefs = {"g_poly": (sh @ theta["g"]).contiguous(), "f_poly": (sel @ theta["f"]).contiguous(),
+             "c_poly": (sel @ theta["c"]).contiguous()}
+    star = {k: torch.tensor(v, device=dev) for k, v in w.theta_star.items()}
+    coefs_star = {"g_poly": (sh @ star["g"]).contiguous(), "f_poly": (sel @ star["f"]).contiguous(),
+                  "c_poly": (sel @ star["c"]).contiguous()}
+    opts = dict(precision="fp32", schedule="graph")
+
+    log(f"bench: C5 {n} nodes x {int(paths[0])} paths, dt={w.dt}; synthetic data at theta* (seed {w.data_seed})")
+    t0 = time.time()
+    d = pdd.mc_interface(P, nodes, paths, w.dt, w.data_seed, coefs=coefs_star, **opts)["mean"].clone()
+    torch.cuda.synchronize()
+    log(f"bench: data ready ({time.time() - t0:.1f} s)")
+
+    grads = {}
+    stats = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def step():
+        r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts)
+        wgt = 2.0 * (r["mean"] - d)
+        g = pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, wgt, coefs=coefs, **opts)
+        stats["fwd"] = r
+        grads["g"] = g
+        return r, g
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"bench: warmup {i + 1}/{args.warmup} done")
+
+    fwd_ms, adj_ms = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ev[0].record()
+        r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts)
+        ev[1].record()
+        wgt = 2.0 * (r["mean"] - d)
+        pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, wgt, coefs=coefs, **opts)
+        ev[2].record()
+        torch.cuda.synchronize()
+        fwd_ms.append(ev[0].elapsed_time(ev[1]))
+        adj_ms.append(ev[1].elapsed_time(ev[2]))
+        stats["fwd"] = r
+        log(f"bench: step {i + 1}/{args.steps}: fwd {fwd_ms[-1]:.1f} ms, adj {adj_ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_step = wall * 1e3 / args.steps
+    r = stats["fwd"]
+    ps = float(r["steps"].sum().item())
+    mean_steps = r["steps"].double() / r["n"].double()
+    var = r["var"]
+    fwd_s, adj_s = np.median(fwd_ms) / 1e3, np.median(adj_ms) / 1e3
+    value = ps / (ms_step / 1e3)
+
+    # interface nodes per second at SE = 1e-3: budget N_i = s_i^2 / 1e-6 paths
+    # at the measured mean steps per path, run at the measured fwd+adj rate
+    need_ps = float((var / 1e-6 * mean_steps).sum().item())
+    nodes_per_s = n / (need_ps / value)
+
+    # plain FP64 one-node-per-launch forward on a node sample (same paths)
+    k = min(args.plain_nodes, n)
+    idx = np.linspace(0, n - 1, k).round().astype(int)
+    sub_nodes = nodes[torch.tensor(idx, device=dev)]
+    sub_coefs = coefs
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    rp = pdd.mc_interface(P, sub_nodes, paths[idx], w.dt, w.seed, precision="fp64_plain", coefs=sub_coefs)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ps_s = float(rp["steps"].sum().item()) / (e0.elapsed_time(e1) / 1e3)
+    log(f"bench: plain FP64 forward on {k} nodes: {plain_ps_s:.3e} path-steps/s")
+    fwd_ps_s = ps / fwd_s
+    adj_ps_s = ps / adj_s
+
+    # roofline of the dominant kernel (the adjoint walk), algorithmic ops
+    dominant = "adjoint" if adj_s >= fwd_s else "forward"
+    ops = ps * (OPS_PER_PS_ADJ if dominant == "adjoint" else OPS_PER_PS_FWD)
+    dur = adj_s if dominant == "adjoint" else fwd_s
+    achieved = ops / dur / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+
+    out = {
+        "metric": "path-steps/s (batched FP32 forward+adjoint, C5)",
+        "value": value,
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C5 3-D unit-ball adjoint: 4096 nodes x 1e5 paths, dt=1e-3, fwd+adjoint",
+                   "nodes": n, "paths_per_node": int(paths[0]), "dt": w.dt, "seed": w.seed,
+                   "schedule": "persistent+hipGraph", "accumulation": "f64"},
+        "forward_path_steps_per_s": fwd_ps_s,
+        "adjoint_path_steps_per_s": adj_ps_s,
+        "interface_nodes_per_s_at_se_1e-3": nodes_per_s,
+        "plain_fp64_forward_path_steps_per_s": plain_ps_s,
+        "speedup_batched_fwd_vs_plain_fp64_fwd": fwd_ps_s / plain_ps_s,
+        "mean_steps_per_path": float(mean_steps.mean().item()),
+        "roofline": {"bound": "alu", "kernel": f"k_walk ({dominant}, FP32, DIM 3)", "achieved": achieved,
+                     "peak": peak, "unit": "Tlane-op/s", "frac": achieved / peak, "traffic": None,
+                     "ops_per_path_step": OPS_PER_PS_ADJ if dominant == "adjoint" else OPS_PER_PS_FWD,
+                     "launch_ms": dur * 1e3},
+    }
+    if args.cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    return out
+
+
+def cpu_baseline(w, seconds):
+    """The FP64 oracle (forward + adjoint) on a bounded sample of the same
+    workload, timed on the host's cores."""
+    import oracle
+    from workloads import configs as CF
+    threads = oracle.default_threads()
+    P = w.problem_template
+    # calibrate on a tiny sample, then size the sample for ~`seconds`
+    nc = 2 * threads
+    idx = np.linspace(0, len(w.nodes) - 1, nc).round().astype(int)
+    pa = np.full(nc, 200, np.int64)
+    t = time.perf_counter()
+    r = oracle.walk_adjoint(P, w.nodes[idx], pa, w.dt, w.seed, np.ones(nc), layout=oracle.QUAD24,
+                            n_threads=threads)
+    rate = r["stats"]["steps"].sum() / (time.perf_counter() - t)
+    per_node = max(200, int(seconds * rate / (4 * threads) / 180.0))
+    nn = 4 * threads
+    idx = np.linspace(0, len(w.nodes) - 1, nn).round().astype(int)
+    pa = np.full(nn, per_node, np.int64)
+    log(f"bench: cpu baseline: oracle fwd+adjoint on {nn} nodes x {per_node} paths, {threads} threads")
+    t = time.perf_counter()
+    r = oracle.walk_adjoint(P, w.nodes[idx], pa, w.dt, w.seed, np.ones(nn), layout=oracle.QUAD24,
+                            n_threads=threads)
+    el = time.perf_counter() - t
+    ps = float(r["stats"]["steps"].sum())
+    return {"value": ps / el, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"C5 forward+adjoint, {nn} nodes x {per_node} paths ({ps:.3e} path-steps, {el:.1f} s), FP64",
+            "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=float, default=1.0, help="path budget scale (1 = 1e5 paths/node)")
+    ap.add_argument("--nodes", type=int, default=4096)
+    ap.add_argument("--plain-nodes", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    out = run(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * pdd.h -- C ABI of the MI355X (gfx950) library for the Monte Carlo hot path of
+ * Probabilistic Domain Decomposition (Bernal, dos Reis, Smith, arXiv 1705.03666).
+ *
+ * Two estimators are exposed:
+ *
+ *  1. The value of a linear elliptic Dirichlet problem at interface nodes
+ *     (Sec. 2.2, eqs. 2.3-2.9, elliptic and pure-Dirichlet limit):
+ *
+ *        0.5 sigma^2 Lap u + b . grad u - c u = -f   in D,     u = g on dD,
+ *
+ *     through the Feynman-Kac functional phi = g(X_tau) Y_tau + Z_tau with
+ *     dX = b dt + sigma dW, dY = -c Y dt, dZ = f Y dt.  The SDE is integrated by
+ *     Euler-Maruyama with a boundary test after each step and the exit point is
+ *     projected onto dD (Sec. 2.1, "ingredients of PDD"); the per-node output is
+ *     the sample mean and sum of squared deviations (Sec. 2, the Monte Carlo
+ *     estimator at every interfacing node).  The sign of c is that of a killing
+ *     rate (the paper's c is -c here).
+ *
+ *  2. The solution of the semilinear branching PDE (Sec. 3.1, eq. 3.1, and the
+ *     marked representation of Sec. 3.2)
+ *
+ *        u_t = 0.5 sigma^2 Lap u + beta ( sum_{i<=4} alpha_i u^i - u ),  u(.,0) = psi,
+ *
+ *     at time T, by branching Brownian particles with Exp(beta) lifetimes,
+ *     offspring counts drawn from q, weights alpha_I/q_I, and the product of psi
+ *     over the particles alive at T.
+ *
+ * plus the exact gradient of sum_i w_i u_i (the linear estimator) with respect
+ * to the coefficients of g, f and c, computed by re-simulating the same paths
+ * from their counters (nothing per path is stored).
+ *
+ * Conventions (all entry points):
+ *  - Host-callable; work is enqueued on `hip_stream` (a hipStream_t, NULL = the
+ *    null stream) and is asynchronous.  Argument validation is synchronous:
+ *    a negative status is returned before anything is enqueued and the reason
+ *    is available from pdd_last_error() (per thread).
+ *  - Pointers marked "device" must be device memory of the current HIP device,
+ *    "host" pointers host memory.  The caller owns every pointer; the library
+ *    never frees caller memory and keeps no caller pointer after the call
+ *    returns, except that device arrays must stay valid until the enqueued
+ *    work finishes.  Scratch memory is allocated stream-ordered per call, or
+ *    held by a cached launch plan until pdd_release_workspace().
+ *  - Results are a pure function of (problem, nodes, budgets, dt, seed,
+ *    precision, rng layout): independent of the schedule and bitwise
+ *    reproducible run to run.
+ *  - No exception or abort crosses the ABI.
+ */
+#ifndef PDD_H
+#define PDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDD_VERSION 1
+
+typedef enum {
+  PDD_OK = 0,
+  PDD_WARN_CENSORED = 1,      /* some paths hit max_steps (see pdd_query_warnings) */
+  PDD_WARN_REDRAWN = 2,       /* some branching trees were pruned and redrawn */
+  PDD_ERR_INVALID_ARG = -1,
+  PDD_ERR_UNSUPPORTED = -2,
+  PDD_ERR_NOT_ADMISSIBLE = -3, /* branching data violate Assumption 3.2 */
+  PDD_ERR_HIP = -4,
+  PDD_ERR_NO_MEMORY = -5
+} pdd_status;
+
+/* ---------------------------------------------------------------- problem data */
+
+typedef enum { PDD_DOM_BOX = 0, PDD_DOM_BALL = 1, PDD_DOM_FREE = 2 } pdd_domain_kind;
+
+/* Open set D in R^dim, dim in 1..3.  BOX: lo[k] < x_k < hi[k].  BALL:
+ * |x - center| < radius.  FREE: R^dim (branching only).  A point on dD counts
+ * as outside. */
+typedef struct {
+  int32_t kind, dim;
+  double lo[3], hi[3], center[3], radius;
+} pdd_domain;
+
+typedef enum { PDD_FN_POW = 0, PDD_FN_EXP = 1, PDD_FN_SIN = 2, PDD_FN_COS = 3, PDD_FN_TANH = 4 } pdd_fn;
+
+/* One factor fn(a * x[dim] + b)^power (POW means the identity, so
+ * (a x + b)^power; power 0 is the constant 1).  0 <= power <= 16. */
+typedef struct {
+  int32_t fn, dim, power, pad;
+  double a, b;
+} pdd_factor;
+
+/* A coefficient function:
+ *   F(x) = sum_{t<n_terms} coef[t] prod_{j<n_factors} factor[t*n_factors+j](x)
+ *        + sum_m poly[m] x^alpha_m
+ * The polynomial part is dense, in graded-lexicographic order of total degree
+ * <= poly_degree (-1: none) in `dim` variables: degree by degree, and within a
+ * degree the exponent tuples in decreasing lexicographic order (3-D: 1; x, y, z;
+ * x^2, xy, xz, y^2, yz, z^2; x^3, ...).  It has C(poly_degree + dim, dim)
+ * entries.  factors: host, read during the call.  coef, poly: device, read by
+ * the enqueued work (these are the differentiable parameters).
+ * Limits: n_factors <= 4; b, c, f: poly_degree <= 3, n_terms <= 16
+ * (<= 4 for c and f in pdd_mc_adjoint); g, psi: poly_degree <= 8, n_terms <= 64. */
+typedef struct {
+  int32_t n_terms, n_factors;
+  const pdd_factor* factors;
+  const double* coef;
+  int32_t poly_degree, pad;
+  const double* poly;
+} pdd_fun;
+
+/* 0.5 sigma^2 Lap u + b . grad u - c u = -f in D, u = g on dD (eqs. 2.3-2.4 with
+ * A = sigma^2 I; only b[0..dim-1] are read).  sigma > 0. */
+typedef struct {
+  pdd_domain domain;
+  double sigma;
+  pdd_fun b[3], c, f, g;
+} pdd_linear_problem;
+
+/* u_t = 0.5 sigma^2 Lap u + beta (sum_i alpha_i u^i - u), u(.,0) = psi, at time T
+ * in R^dim (eq. 3.1; marked form of Sec. 3.2).  q is the sampling law of the
+ * offspring count: q_i >= 0, sum q_i = 1, q_i > 0 wherever alpha_i != 0.
+ * psi_sup bounds |psi| and is used for the admissibility test of Assumption 3.2.
+ * A tree that needs more than max_segments particles (1..4096) is discarded and
+ * redrawn (pruning, remark before Algorithm 3.1). */
+typedef struct {
+  int32_t dim, max_segments;
+  double sigma, beta, T;
+  double alpha[5], q[5];
+  double psi_sup;
+  pdd_fun psi;
+} pdd_branching_problem;
+
+/* ---------------------------------------------------------------- options */
+
+typedef enum {
+  PDD_FP64_PLAIN = 0,  /* FP64; one launch per node, one path per thread, no refill (baseline) */
+  PDD_FP64 = 1,        /* FP64 stepping, batched persistent kernel */
+  PDD_FP32_STEP = 2    /* FP32 stepping and transforms, FP64 accumulation (QUAD24 only) */
+} pdd_precision;
+
+typedef enum { PDD_RNG_PAIR52 = 0, PDD_RNG_QUAD24 = 1 } pdd_rng_layout;
+
+typedef enum {
+  PDD_SCHED_AUTO = 0,             /* persistent + cached graph plan */
+  PDD_SCHED_PERSISTENT = 1,       /* persistent kernel, per-call scratch */
+  PDD_SCHED_PERSISTENT_GRAPH = 2  /* persistent kernel captured once into a hipGraph and replayed */
+} pdd_schedule;
+
+typedef struct {
+  int32_t precision;      /* pdd_precision */
+  int32_t rng_layout;     /* pdd_rng_layout; PDD_FP32_STEP requires QUAD24 */
+  int64_t max_steps;      /* censoring cap per path; 0 = ceil(100/dt) */
+  double* dump_phi;       /* device, optional [sum(paths)]: per-path value, node-major */
+  int64_t* dump_steps;    /* device, optional [sum(paths)]: per-path step (segment) count */
+  int32_t schedule;       /* pdd_schedule */
+  int32_t chunk_paths;    /* paths per work item; 0 = autotuned/default */
+  int32_t blocks_per_cu;  /* persistent grid size per compute unit; 0 = autotuned/default */
+  int32_t refill_groups;  /* step groups between lane refills; 0 = autotuned/default (1) */
+} pdd_options;
+
+/* Per-node result: mean and sum of squared deviations (variance = m2/(n-1),
+ * standard error = sqrt(variance/n)), path count, total steps (linear) or
+ * segments (branching), and censored paths / trees. 40 bytes. */
+typedef struct {
+  double mean, m2;
+  int64_t n, steps, censored;
+} pdd_node_stat;
+
+/* Gradient outputs for one function: dcoef[n_terms], dpoly[n_mono] (device,
+ * accumulated with +=; NULL skips that part). */
+typedef struct {
+  double* dcoef;
+  double* dpoly;
+} pdd_fun_grad;
+
+/* ---------------------------------------------------------------- entry points */
+
+/* Monte Carlo value at interface nodes (Sec. 2.2).
+ *  problem:   host struct; domain BOX or BALL.
+ *  nodes_dev: device [n_nodes][domain.dim] FP64.  A node outside D gets
+ *             tau = 0 and phi = g(projection of the node).
+ *  paths_host: host [n_nodes] path budget per node, 0 <= paths < 2^32.
+ *  dt > 0: Euler-Maruyama step.  seed: Philox key.
+ *  out_dev:   device [n_nodes] pdd_node_stat.
+ *  Errors: PDD_ERR_INVALID_ARG (bad sizes / domain / dt / options),
+ *          PDD_ERR_UNSUPPORTED (limits above exceeded), PDD_ERR_HIP. */
+pdd_status pdd_mc_interface(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                            const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
+                            pdd_node_stat* out_dev, void* hip_stream);
+
+/* Branching estimator (Sec. 3.1-3.2) at points_dev [n_points][dim] (device,
+ * FP64), trees_per_point trees each (< 2^32).  out_dev: device [n_points];
+ * steps = segments simulated, censored = trees that failed 16 draws (value 0).
+ * Returns PDD_ERR_NOT_ADMISSIBLE when Assumption 3.2 fails for alpha, beta,
+ * psi_sup and T. */
+pdd_status pdd_branching_eval(const pdd_branching_problem* problem, const double* points_dev,
+                              int64_t n_points, int64_t trees_per_point, uint64_t seed,
+                              const pdd_options* options, pdd_node_stat* out_dev, void* hip_stream);
+
+/* Gradient of sum_i w_i u_i with respect to the coefficient arrays of g, f and c
+ * (the exact derivative of the discrete estimator, same paths as
+ * pdd_mc_interface with the same arguments).  w_dev: device [n_nodes].
+ * grads_host: host array of three pdd_fun_grad {g, f, c}; the device arrays
+ * they point to are accumulated into (+=).  out_dev: optional per-node stats
+ * (NULL to skip).  Limits: c and f with n_terms <= 4. */
+pdd_status pdd_mc_adjoint(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                          const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
+                          const double* w_dev, const pdd_fun_grad* grads_host, pdd_node_stat* out_dev,
+                          void* hip_stream);
+
+/* Synchronizes hip_stream and reports (then clears) the censored-path and
+ * redrawn-tree counters of the work enqueued since the last query:
+ * PDD_WARN_CENSORED / PDD_WARN_REDRAWN if non-zero, else PDD_OK. */
+pdd_status pdd_query_warnings(void* hip_stream, int64_t* censored_out, int64_t* redrawn_out);
+
+/* Frees cached launch plans and their device memory (synchronizes the device). */
+pdd_status pdd_release_workspace(void);
+
+const char* pdd_status_string(pdd_status status);
+const char* pdd_last_error(void);
+int pdd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -85,7 +85,7 @@ def lib():
         L.orc_inside.argtypes = [C.POINTER(ODomain), dp]
         L.orc_project.argtypes = [C.POINTER(ODomain), dp, dp]
         L.orc_walk.argtypes = [C.POINTER(OLinear), dp, C.c_int64, ip, C.c_double, C.c_uint64, C.c_int,
-                               C.c_int64, C.c_int, C.POINTER(OStat), dp, ip]
+                               C.c_int64, C.c_int, C.POINTER(OStat), dp, ip, ip]
         L.orc_walk_adjoint.argtypes = [C.POINTER(OLinear), dp, C.c_int64, ip, C.c_double, C.c_uint64, C.c_int,
                                        C.c_int64, C.c_int, dp, dp, dp, dp, dp, dp, dp, C.POINTER(OStat)]
         L.orc_branching_dfs.argtypes = [C.POINTER(OBranching), dp, C.c_int64, C.c_int64, C.c_uint64, C.c_int,
@@ -217,9 +217,12 @@ def fun_eval(F: Fun, ndim: int, x) -> float:
 
 
 def walk(P: LinearProblem, nodes, paths, dt: float, seed: int, layout: int = PAIR52,
-         max_steps: Optional[int] = None, n_threads: Optional[int] = None, dump: bool = False) -> dict:
+         max_steps: Optional[int] = None, n_threads: Optional[int] = None, dump: bool = False,
+         node_ids=None) -> dict:
     """Per-node sample mean / variance of the Feynman-Kac walk (optionally the
-    per-path values and step counts, concatenated node after node)."""
+    per-path values and step counts, concatenated node after node).  node_ids
+    gives the node index used in the random-number counters (default: the
+    node's position), so a sample of a larger node set reproduces its paths."""
     keep = _Keep()
     o = _olinear(P, keep)
     nodes = keep.arr(nodes, np.float64)
@@ -232,7 +235,8 @@ def walk(P: LinearProblem, nodes, paths, dt: float, seed: int, layout: int = PAI
     rc = lib().orc_walk(C.byref(o), _ptr(nodes, C.c_double), n, _ptr(paths, C.c_int64), dt, seed, layout,
                         default_max_steps(dt) if max_steps is None else max_steps,
                         default_threads() if n_threads is None else n_threads, out,
-                        _ptr(phi, C.c_double) if dump else None, _ptr(st, C.c_int64) if dump else None)
+                        _ptr(phi, C.c_double) if dump else None, _ptr(st, C.c_int64) if dump else None,
+                        _ptr(keep.arr(node_ids, np.int64), C.c_int64) if node_ids is not None else None)
     if rc != 0:
         raise ValueError("oracle rejected the walk arguments")
     res = _stats(out[:n])

@@ -350,7 +350,10 @@ typedef struct {
   const double* w;
   double* grad_rows;   /* [n_nodes][n_grad] */
   int n_grad;
+  const int64_t* node_ids; /* counter word 3 per node (NULL: the node's position) */
 } walk_ctx;
+
+static uint32_t node_id(const walk_ctx* C, int64_t i) { return (uint32_t)(C->node_ids ? C->node_ids[i] : i); }
 
 static void walk_node(void* vctx, int64_t i, int worker) {
   (void)worker;
@@ -358,7 +361,7 @@ static void walk_node(void* vctx, int64_t i, int worker) {
   int d = C->P->dom.dim;
   orc_stat s = {0.0, 0.0, 0, 0, 0};
   for (int64_t p = 0; p < C->paths[i]; ++p) {
-    path_result R = walk_path(C->P, &C->nodes[i * d], C->key, C->layout, (uint32_t)i, (uint32_t)p,
+    path_result R = walk_path(C->P, &C->nodes[i * d], C->key, C->layout, node_id(C, i), (uint32_t)p,
                               C->dt, C->max_steps, NULL);
     welford_push(&s, R.phi);
     s.steps += R.steps;
@@ -378,12 +381,13 @@ static int64_t* prefix_offsets(const int64_t* paths, int64_t n) {
 
 int orc_walk(const orc_linear* P, const double* nodes, int64_t n_nodes, const int64_t* paths,
              double dt, uint64_t seed, int layout, int64_t max_steps, int n_threads,
-             orc_stat* out, double* dump_phi, int64_t* dump_steps) {
+             orc_stat* out, double* dump_phi, int64_t* dump_steps, const int64_t* node_ids) {
   if (P->dom.kind == ORC_FREE || P->dom.dim < 1 || P->dom.dim > 3 || !(dt > 0.0)) return -1;
   walk_ctx C;
   memset(&C, 0, sizeof(C));
   C.P = P; C.nodes = nodes; C.paths = paths; C.dt = dt; C.layout = layout;
   C.max_steps = max_steps; C.out = out; C.dump_phi = dump_phi; C.dump_steps = dump_steps;
+  C.node_ids = node_ids;
   make_key(seed, C.key);
   int64_t* off = prefix_offsets(paths, n_nodes);
   C.offsets = off;
@@ -409,7 +413,7 @@ static void adjoint_node(void* vctx, int64_t i, int worker) {
   orc_stat s = {0.0, 0.0, 0, 0, 0};
   double wN = C->w[i] / (double)C->paths[i];
   for (int64_t p = 0; p < C->paths[i]; ++p) {
-    path_result R = walk_path(P, &C->nodes[i * d], C->key, C->layout, (uint32_t)i, (uint32_t)p,
+    path_result R = walk_path(P, &C->nodes[i * d], C->key, C->layout, node_id(C, i), (uint32_t)p,
                               C->dt, C->max_steps, &tg);
     welford_push(&s, R.phi);
     s.steps += R.steps;

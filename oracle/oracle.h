@@ -92,7 +92,7 @@ void orc_project(const orc_domain* D, const double* x, double* out);
 /* ---- linear walk (Sec. 2.2) ---- */
 int orc_walk(const orc_linear* P, const double* nodes, int64_t n_nodes, const int64_t* paths,
              double dt, uint64_t seed, int layout, int64_t max_steps, int n_threads,
-             orc_stat* out, double* dump_phi, int64_t* dump_steps);
+             orc_stat* out, double* dump_phi, int64_t* dump_steps, const int64_t* node_ids);
 
 /* gradient of sum_i w_i * mean_i with respect to the coefficient arrays
    (accumulated into caller-zeroed arrays; NULL pointers are skipped) */

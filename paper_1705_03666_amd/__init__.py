@@ -1,0 +1,340 @@
+"""MI355X (gfx950) library for the Monte Carlo hot path of Probabilistic Domain
+Decomposition (Bernal, dos Reis, Smith, arXiv 1705.03666).
+
+Thin Python binding of libpdd.so (C ABI in include/pdd.h): it marshals
+arguments, hands over torch device pointers and the current stream, and turns
+status codes into exceptions.  Every step of the computation runs in the HIP
+kernels; there is no CPU fallback.  If the library or a GPU is missing the
+calls raise.
+
+Problem objects are duck-typed: a linear problem has `domain` (kind, ndim,
+lo, hi, center, radius), `sigma`, `b` (list of functions), `c`, `f`, `g`; a
+function has the term-table arrays `fn, dim, power, a, b, coef` and
+`poly_degree, poly` (graded-lex dense polynomial), as produced by the
+`workloads` package.  A branching problem has `ndim, sigma, beta, T, alpha,
+q, psi, psi_sup, max_segments`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import warnings
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+__all__ = ["mc_interface", "mc_adjoint", "branching_eval", "PDDInterface", "PddError", "release_workspace",
+           "query_warnings", "library", "version"]
+
+
+class PddError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def library():
+    """The loaded libpdd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(A.LIB_PATH):
+            raise RuntimeError(f"{A.LIB_PATH} is missing: build it with `python -m paper_1705_03666_amd.build`")
+        _lib = A.load(A.LIB_PATH)
+    return _lib
+
+
+def version() -> int:
+    return int(library().pdd_version())
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_1705_03666_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
+
+
+def _check(status: int, what: str):
+    L = library()
+    if status < 0:
+        msg = L.pdd_last_error().decode(errors="replace")
+        raise PddError(f"{what}: {L.pdd_status_string(status).decode()} ({msg})")
+    if status > 0:
+        warnings.warn(f"{what}: {L.pdd_status_string(status).decode()}")
+
+
+def _stream_handle() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+_PREC = {"fp64_plain": A.PDD_FP64_PLAIN, "fp64": A.PDD_FP64, "fp32": A.PDD_FP32_STEP}
+_LAYOUT = {"pair52": A.PDD_RNG_PAIR52, "quad24": A.PDD_RNG_QUAD24}
+_SCHED = {"auto": A.PDD_SCHED_AUTO, "persistent": A.PDD_SCHED_PERSISTENT, "graph": A.PDD_SCHED_PERSISTENT_GRAPH}
+
+
+def _options(precision: str, layout: Optional[str], max_steps: int, schedule: str, chunk_paths: int,
+             blocks_per_cu: int, refill_groups: int, dump_phi=None, dump_steps=None) -> A.pdd_options:
+    if precision not in _PREC:
+        raise ValueError(f"precision must be one of {list(_PREC)}")
+    if layout is None:
+        layout = "quad24" if precision == "fp32" else "pair52"
+    o = A.pdd_options()
+    o.precision = _PREC[precision]
+    o.rng_layout = _LAYOUT[layout]
+    o.max_steps = int(max_steps)
+    o.dump_phi = dump_phi.data_ptr() if dump_phi is not None else None
+    o.dump_steps = dump_steps.data_ptr() if dump_steps is not None else None
+    o.schedule = _SCHED[schedule]
+    o.chunk_paths = int(chunk_paths)
+    o.blocks_per_cu = int(blocks_per_cu)
+    o.refill_groups = int(refill_groups)
+    return o
+
+
+def _dev_f64(x) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        t = x.detach()
+        if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+            t = t.to(device="cuda", dtype=torch.float64).contiguous()
+        return t
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device="cuda")
+
+
+class _Keep(list):
+    pass
+
+
+def _fun(F, keep: _Keep, coef=None, poly=None) -> A.pdd_fun:
+    f = A.pdd_fun()
+    T = int(np.asarray(F.coef).shape[0])
+    nf = int(F.fn.shape[1]) if (T > 0 and np.asarray(F.fn).ndim == 2) else 0
+    f.n_terms = T
+    f.n_factors = nf
+    if T > 0 and nf > 0:
+        facs = (A.pdd_factor * (T * nf))()
+        for t in range(T):
+            for j in range(nf):
+                k = t * nf + j
+                facs[k].fn = int(F.fn[t, j]); facs[k].dim = int(F.dim[t, j]); facs[k].power = int(F.power[t, j])
+                facs[k].a = float(F.a[t, j]); facs[k].b = float(F.b[t, j])
+        keep.append(facs)
+        f.factors = C.cast(facs, C.POINTER(A.pdd_factor))
+    if T > 0:
+        ct = _dev_f64(F.coef if coef is None else coef)
+        if ct.numel() != T:
+            raise ValueError("coefficient count does not match the term table")
+        keep.append(ct)
+        f.coef = ct.data_ptr()
+    f.poly_degree = int(F.poly_degree)
+    if F.poly_degree >= 0:
+        pt = _dev_f64(F.poly if poly is None else poly)
+        keep.append(pt)
+        f.poly = pt.data_ptr()
+    return f
+
+
+def _zero_fun() -> A.pdd_fun:
+    f = A.pdd_fun()
+    f.poly_degree = -1
+    return f
+
+
+def _linear(P, keep: _Keep, coefs: Optional[Dict[str, torch.Tensor]] = None) -> A.pdd_linear_problem:
+    coefs = coefs or {}
+    p = A.pdd_linear_problem()
+    D = P.domain
+    p.domain.kind = int(D.kind)
+    p.domain.dim = int(D.ndim)
+    for k in range(3):
+        p.domain.lo[k] = float(D.lo[k]); p.domain.hi[k] = float(D.hi[k]); p.domain.center[k] = float(D.center[k])
+    p.domain.radius = float(D.radius)
+    p.sigma = float(P.sigma)
+    for k in range(3):
+        p.b[k] = _fun(P.b[k], keep) if k < len(P.b) else _zero_fun()
+    for name in ("c", "f", "g"):
+        setattr(p, name, _fun(getattr(P, name), keep, coefs.get(name + "_coef"), coefs.get(name + "_poly")))
+    return p
+
+
+def _stats(raw: torch.Tensor) -> Dict[str, torch.Tensor]:
+    ints = raw[:, 2:].contiguous().view(torch.int64)
+    n = ints[:, 0]
+    mean, m2 = raw[:, 0], raw[:, 1]
+    nf = n.to(torch.float64)
+    var = torch.where(n > 1, m2 / torch.clamp(nf - 1.0, min=1.0), torch.zeros_like(m2))
+    return {"mean": mean, "m2": m2, "n": n, "steps": ints[:, 1], "censored": ints[:, 2], "var": var,
+            "se": torch.sqrt(var / torch.clamp(nf, min=1.0))}
+
+
+def _nodes_tensor(nodes, ndim: int) -> torch.Tensor:
+    t = _dev_f64(nodes)
+    if t.dim() != 2 or t.shape[1] != ndim:
+        raise ValueError(f"nodes must have shape (n, {ndim})")
+    return t
+
+
+def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str = "fp32",
+                 layout: Optional[str] = None, max_steps: int = 0, dump: bool = False, schedule: str = "auto",
+                 chunk_paths: int = 0, blocks_per_cu: int = 0, refill_groups: int = 0,
+                 coefs: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+    """Monte Carlo value of the linear problem at every node (pdd_mc_interface).
+    Returns device tensors mean, m2, n, steps, censored, var, se (and, with
+    dump=True, the per-path values `phi` and step counts `path_steps`,
+    node-major)."""
+    _need_gpu()
+    keep = _Keep()
+    p = _linear(problem, keep, coefs)
+    nt = _nodes_tensor(nodes, problem.domain.ndim)
+    n = nt.shape[0]
+    ph = np.ascontiguousarray(np.asarray(paths, dtype=np.int64).reshape(-1))
+    if ph.shape[0] != n:
+        raise ValueError("paths must have one entry per node")
+    raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
+    dphi = dst = None
+    if dump:
+        total = int(ph.sum())
+        dphi = torch.empty(max(total, 1), dtype=torch.float64, device="cuda")
+        dst = torch.empty(max(total, 1), dtype=torch.int64, device="cuda")
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups, dphi, dst)
+    st = library().pdd_mc_interface(C.byref(p), nt.data_ptr() if n else None, n,
+                                    ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt), int(seed) & (2 ** 64 - 1),
+                                    C.byref(o), raw.data_ptr(), _stream_handle())
+    _check(st, "pdd_mc_interface")
+    res = _stats(raw[:n])
+    if dump:
+        total = int(ph.sum())
+        res["phi"], res["path_steps"] = dphi[:total], dst[:total]
+    res["_keep"] = keep
+    return res
+
+
+def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = "fp32",
+               layout: Optional[str] = None, max_steps: int = 0, schedule: str = "auto", chunk_paths: int = 0,
+               blocks_per_cu: int = 0, refill_groups: int = 0, coefs: Optional[Dict[str, torch.Tensor]] = None,
+               with_stats: bool = False) -> Dict[str, torch.Tensor]:
+    """Gradient of sum_i w_i u_i with respect to the coefficient arrays of g, f
+    and c (pdd_mc_adjoint).  Returns device tensors g_coef, g_poly, f_coef,
+    f_poly, c_coef, c_poly (and the per-node statistics with with_stats)."""
+    _need_gpu()
+    keep = _Keep()
+    p = _linear(problem, keep, coefs)
+    nt = _nodes_tensor(nodes, problem.domain.ndim)
+    n = nt.shape[0]
+    ph = np.ascontiguousarray(np.asarray(paths, dtype=np.int64).reshape(-1))
+    if ph.shape[0] != n:
+        raise ValueError("paths must have one entry per node")
+    wt = _dev_f64(w).reshape(-1)
+    if wt.numel() != n:
+        raise ValueError("w must have one entry per node")
+    ndim = problem.domain.ndim
+    grads = {}
+    gstruct = (A.pdd_fun_grad * 3)()
+    for k, name in enumerate(("g", "f", "c")):
+        F = getattr(problem, name)
+        T = int(np.asarray(F.coef).shape[0])
+        from math import comb
+        M = comb(F.poly_degree + ndim, ndim) if F.poly_degree >= 0 else 0
+        grads[name + "_coef"] = torch.zeros(max(T, 1), dtype=torch.float64, device="cuda")
+        grads[name + "_poly"] = torch.zeros(max(M, 1), dtype=torch.float64, device="cuda")
+        gstruct[k].dcoef = grads[name + "_coef"].data_ptr() if T else None
+        gstruct[k].dpoly = grads[name + "_poly"].data_ptr() if M else None
+        grads[name + "_coef"] = grads[name + "_coef"][:T]
+        grads[name + "_poly"] = grads[name + "_poly"][:M]
+    raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda") if with_stats else None
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups)
+    st = library().pdd_mc_adjoint(C.byref(p), nt.data_ptr() if n else None, n,
+                                  ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt), int(seed) & (2 ** 64 - 1),
+                                  C.byref(o), wt.data_ptr() if n else None, gstruct,
+                                  raw.data_ptr() if raw is not None else None, _stream_handle())
+    _check(st, "pdd_mc_adjoint")
+    if with_stats:
+        grads["stats"] = _stats(raw[:n])
+    grads["_keep"] = (keep, wt)
+    return grads
+
+
+def branching_eval(problem, points, trees: int, seed: int = 0, precision: str = "fp32",
+                   layout: Optional[str] = None, dump: bool = False, schedule: str = "persistent",
+                   chunk_paths: int = 0, blocks_per_cu: int = 0) -> Dict[str, torch.Tensor]:
+    """Marked branching estimator at every point (pdd_branching_eval).  With
+    dump=True also the per-tree values `value` [n, trees] and segment counts."""
+    _need_gpu()
+    keep = _Keep()
+    b = A.pdd_branching_problem()
+    b.dim = int(problem.ndim)
+    b.max_segments = int(problem.max_segments)
+    b.sigma, b.beta, b.T = float(problem.sigma), float(problem.beta), float(problem.T)
+    for k in range(5):
+        b.alpha[k] = float(problem.alpha[k]) if k < len(problem.alpha) else 0.0
+        b.q[k] = float(problem.q[k]) if k < len(problem.q) else 0.0
+    b.psi_sup = float(problem.psi_sup)
+    b.psi = _fun(problem.psi, keep)
+    pt = _nodes_tensor(points, b.dim)
+    n = pt.shape[0]
+    raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
+    dv = ds = None
+    if dump:
+        dv = torch.empty(max(n * trees, 1), dtype=torch.float64, device="cuda")
+        ds = torch.empty(max(n * trees, 1), dtype=torch.int64, device="cuda")
+    o = _options(precision, layout, 0, schedule, chunk_paths, blocks_per_cu, 0, dv, ds)
+    st = library().pdd_branching_eval(C.byref(b), pt.data_ptr() if n else None, n, int(trees),
+                                      int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(), _stream_handle())
+    _check(st, "pdd_branching_eval")
+    res = _stats(raw[:n])
+    if dump:
+        res["value"] = dv[:n * trees].reshape(n, trees)
+        res["segments"] = ds[:n * trees].reshape(n, trees)
+    res["_keep"] = keep
+    return res
+
+
+def query_warnings():
+    """Synchronizes the current stream; returns (censored paths, redrawn trees)
+    since the last query."""
+    c, r = C.c_int64(0), C.c_int64(0)
+    st = library().pdd_query_warnings(_stream_handle(), C.byref(c), C.byref(r))
+    if st < 0:
+        _check(st, "pdd_query_warnings")
+    return int(c.value), int(r.value)
+
+
+def release_workspace():
+    _check(library().pdd_release_workspace(), "pdd_release_workspace")
+
+
+_COEF_KEYS = ("g_coef", "g_poly", "f_coef", "f_poly", "c_coef", "c_poly")
+
+
+class PDDInterface(torch.autograd.Function):
+    """u = PDDInterface.apply(problem, nodes, paths, dt, seed, opts,
+    g_coef, g_poly, f_coef, f_poly, c_coef, c_poly): interface values,
+    differentiable in the six coefficient tensors (None = take the problem's
+    own array, not differentiated).  Backward re-simulates the same paths
+    (pdd_mc_adjoint) with w = grad_u."""
+
+    @staticmethod
+    def forward(ctx, problem, nodes, paths, dt, seed, opts, *coef_tensors):
+        coefs = {k: v for k, v in zip(_COEF_KEYS, coef_tensors) if v is not None}
+        opts = dict(opts or {})
+        r = mc_interface(problem, nodes, paths, dt, seed, coefs=coefs, **opts)
+        ctx.problem, ctx.nodes, ctx.paths, ctx.dt, ctx.seed, ctx.opts = problem, nodes, paths, dt, seed, opts
+        ctx.present = [v is not None for v in coef_tensors]
+        ctx.save_for_backward(*[v for v in coef_tensors if v is not None])
+        return r["mean"].clone()
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        saved = list(ctx.saved_tensors)
+        coefs = {}
+        for k, present in zip(_COEF_KEYS, ctx.present):
+            if present:
+                coefs[k] = saved.pop(0)
+        opts = {k: v for k, v in ctx.opts.items() if k not in ("dump",)}
+        g = mc_adjoint(ctx.problem, ctx.nodes, ctx.paths, ctx.dt, ctx.seed, grad_u.detach(), coefs=coefs, **opts)
+        out = [None] * 6
+        for i, k in enumerate(_COEF_KEYS):
+            if ctx.present[i] and ctx.needs_input_grad[6 + i]:
+                out[i] = g[k].to(coefs[k].dtype)
+        return (None, None, None, None, None, None, *out)

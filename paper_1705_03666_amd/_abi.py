@@ -1,0 +1,85 @@
+"""ctypes mirror of include/pdd.h (structures, enums, function prototypes)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdd.so")
+
+PDD_OK, PDD_WARN_CENSORED, PDD_WARN_REDRAWN = 0, 1, 2
+PDD_ERR_INVALID_ARG, PDD_ERR_UNSUPPORTED, PDD_ERR_NOT_ADMISSIBLE, PDD_ERR_HIP, PDD_ERR_NO_MEMORY = -1, -2, -3, -4, -5
+
+PDD_DOM_BOX, PDD_DOM_BALL, PDD_DOM_FREE = 0, 1, 2
+PDD_FP64_PLAIN, PDD_FP64, PDD_FP32_STEP = 0, 1, 2
+PDD_RNG_PAIR52, PDD_RNG_QUAD24 = 0, 1
+PDD_SCHED_AUTO, PDD_SCHED_PERSISTENT, PDD_SCHED_PERSISTENT_GRAPH = 0, 1, 2
+
+EXPORTED = ["pdd_mc_interface", "pdd_branching_eval", "pdd_mc_adjoint", "pdd_query_warnings",
+            "pdd_release_workspace", "pdd_status_string", "pdd_last_error", "pdd_version"]
+
+
+class pdd_domain(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("center", C.c_double * 3), ("radius", C.c_double)]
+
+
+class pdd_factor(C.Structure):
+    _fields_ = [("fn", C.c_int32), ("dim", C.c_int32), ("power", C.c_int32), ("pad", C.c_int32),
+                ("a", C.c_double), ("b", C.c_double)]
+
+
+class pdd_fun(C.Structure):
+    _fields_ = [("n_terms", C.c_int32), ("n_factors", C.c_int32), ("factors", C.POINTER(pdd_factor)),
+                ("coef", C.c_void_p), ("poly_degree", C.c_int32), ("pad", C.c_int32), ("poly", C.c_void_p)]
+
+
+class pdd_linear_problem(C.Structure):
+    _fields_ = [("domain", pdd_domain), ("sigma", C.c_double), ("b", pdd_fun * 3), ("c", pdd_fun),
+                ("f", pdd_fun), ("g", pdd_fun)]
+
+
+class pdd_branching_problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("max_segments", C.c_int32), ("sigma", C.c_double), ("beta", C.c_double),
+                ("T", C.c_double), ("alpha", C.c_double * 5), ("q", C.c_double * 5), ("psi_sup", C.c_double),
+                ("psi", pdd_fun)]
+
+
+class pdd_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("rng_layout", C.c_int32), ("max_steps", C.c_int64),
+                ("dump_phi", C.c_void_p), ("dump_steps", C.c_void_p), ("schedule", C.c_int32),
+                ("chunk_paths", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill_groups", C.c_int32)]
+
+
+class pdd_node_stat(C.Structure):
+    _fields_ = [("mean", C.c_double), ("m2", C.c_double), ("n", C.c_int64), ("steps", C.c_int64),
+                ("censored", C.c_int64)]
+
+
+class pdd_fun_grad(C.Structure):
+    _fields_ = [("dcoef", C.c_void_p), ("dpoly", C.c_void_p)]
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    L = C.CDLL(path)
+    L.pdd_mc_interface.argtypes = [C.POINTER(pdd_linear_problem), C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
+                                   C.c_double, C.c_uint64, C.POINTER(pdd_options), C.c_void_p, C.c_void_p]
+    L.pdd_mc_interface.restype = C.c_int
+    L.pdd_branching_eval.argtypes = [C.POINTER(pdd_branching_problem), C.c_void_p, C.c_int64, C.c_int64, C.c_uint64,
+                                     C.POINTER(pdd_options), C.c_void_p, C.c_void_p]
+    L.pdd_branching_eval.restype = C.c_int
+    L.pdd_mc_adjoint.argtypes = [C.POINTER(pdd_linear_problem), C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
+                                 C.c_double, C.c_uint64, C.POINTER(pdd_options), C.c_void_p,
+                                 C.POINTER(pdd_fun_grad), C.c_void_p, C.c_void_p]
+    L.pdd_mc_adjoint.restype = C.c_int
+    L.pdd_query_warnings.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.pdd_query_warnings.restype = C.c_int
+    L.pdd_release_workspace.argtypes = []
+    L.pdd_release_workspace.restype = C.c_int
+    L.pdd_status_string.argtypes = [C.c_int]
+    L.pdd_status_string.restype = C.c_char_p
+    L.pdd_last_error.argtypes = []
+    L.pdd_last_error.restype = C.c_char_p
+    L.pdd_version.argtypes = []
+    L.pdd_version.restype = C.c_int
+    return L

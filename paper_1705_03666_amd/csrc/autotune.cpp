@@ -1,0 +1,39 @@
+// Default launch schedules.  The search over schedules lives in the Python
+// autotuner (paper_1705_03666_amd/autotune.py), which times candidates through
+// the option overrides and caches the winner per device and problem shape;
+// whatever it passes in pdd_options takes precedence here.
+#include "pdd_tuning.hpp"
+
+#include <algorithm>
+
+namespace pdd {
+
+Tuning choose_tuning(int dim, bool fp32, bool adjoint, const pdd_options& o, int n_cus) {
+  (void)dim;
+  (void)n_cus;
+  Tuning t;
+  t.chunk_paths = adjoint ? 4096 : 4096;
+  t.blocks_per_cu = fp32 ? 2 : 2;
+  t.refill_groups = 1;
+  if (o.chunk_paths > 0) t.chunk_paths = o.chunk_paths;
+  if (o.blocks_per_cu > 0) t.blocks_per_cu = o.blocks_per_cu;
+  if (o.refill_groups > 0) t.refill_groups = o.refill_groups;
+  t.chunk_paths = std::max(1, t.chunk_paths);
+  return t;
+}
+
+Tuning choose_branch_tuning(int dim, bool fp32, const pdd_options& o, int n_cus) {
+  (void)dim;
+  (void)fp32;
+  (void)n_cus;
+  Tuning t;
+  t.chunk_paths = 2048;
+  t.blocks_per_cu = 2;
+  t.refill_groups = 1;
+  if (o.chunk_paths > 0) t.chunk_paths = o.chunk_paths;
+  if (o.blocks_per_cu > 0) t.blocks_per_cu = o.blocks_per_cu;
+  t.chunk_paths = std::max(1, t.chunk_paths);
+  return t;
+}
+
+}  // namespace pdd

@@ -1,0 +1,989 @@
+// Host layer of the C ABI declared in include/pdd.h: argument validation,
+// staging of coefficient tables, work-item construction (longest first),
+// launch of the HIP kernels on the caller's stream, cached hipGraph launch
+// plans, and warning counters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "pdd.h"
+#include "pdd_internal.hpp"
+#include "pdd_kernels.hpp"
+#include "pdd_tuning.hpp"
+
+using namespace pdd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pdd_status fail(pdd_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define PDD_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return fail(PDD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ----------------------------------------------------------------------------- monomials
+int n_mono(int dim, int deg) {
+  if (deg < 0) return 0;
+  int r = 1;
+  for (int i = 1; i <= dim; ++i) r = r * (deg + i) / i;
+  return r;
+}
+
+std::vector<std::array<int, 3>> graded_lex(int dim, int deg) {
+  std::vector<std::array<int, 3>> out;
+  for (int k = 0; k <= deg; ++k) {
+    if (dim == 1) {
+      out.push_back({k, 0, 0});
+    } else if (dim == 2) {
+      for (int a = k; a >= 0; --a) out.push_back({a, k - a, 0});
+    } else {
+      for (int a = k; a >= 0; --a)
+        for (int b = k - a; b >= 0; --b) out.push_back({a, b, k - a - b});
+    }
+  }
+  return out;
+}
+
+// nested order (a outer, b middle, c inner) -> graded-lex index
+std::vector<int32_t> nested_to_graded(int dim, int deg) {
+  auto gl = graded_lex(dim, deg);
+  std::vector<int32_t> out;
+  for (int a = 0; a <= deg; ++a)
+    for (int b = 0; b <= (dim >= 2 ? deg - a : 0); ++b)
+      for (int c = 0; c <= (dim >= 3 ? deg - a - b : 0); ++c) {
+        std::array<int, 3> e = {a, b, c};
+        for (size_t i = 0; i < gl.size(); ++i)
+          if (gl[i] == e) { out.push_back((int32_t)i); break; }
+      }
+  return out;
+}
+
+// ----------------------------------------------------------------------------- validation
+pdd_status check_fun(const pdd_fun& F, int dim, const char* name, int max_terms, int max_deg) {
+  const std::string n(name);
+  if (F.n_terms < 0 || F.n_terms > max_terms)
+    return fail(F.n_terms < 0 ? PDD_ERR_INVALID_ARG : PDD_ERR_UNSUPPORTED,
+                n + ": n_terms out of range (max " + std::to_string(max_terms) + ")");
+  if (F.n_terms > 0) {
+    if (F.n_factors < 0 || F.n_factors > kMaxFactors) return fail(PDD_ERR_UNSUPPORTED, n + ": n_factors must be 0..4");
+    if (F.n_factors > 0 && F.factors == nullptr) return fail(PDD_ERR_INVALID_ARG, n + ": factors is NULL");
+    if (F.coef == nullptr) return fail(PDD_ERR_INVALID_ARG, n + ": coef is NULL");
+    for (int i = 0; i < F.n_terms * F.n_factors; ++i) {
+      const pdd_factor& fa = F.factors[i];
+      if (fa.fn < PDD_FN_POW || fa.fn > PDD_FN_TANH) return fail(PDD_ERR_INVALID_ARG, n + ": unknown factor kind");
+      if (fa.dim < 0 || fa.dim >= dim) return fail(PDD_ERR_INVALID_ARG, n + ": factor dimension out of range");
+      if (fa.power < 0 || fa.power > 16) return fail(PDD_ERR_INVALID_ARG, n + ": factor power must be 0..16");
+      if (!std::isfinite(fa.a) || !std::isfinite(fa.b)) return fail(PDD_ERR_INVALID_ARG, n + ": non-finite factor");
+    }
+  }
+  if (F.poly_degree < -1) return fail(PDD_ERR_INVALID_ARG, n + ": poly_degree < -1");
+  if (F.poly_degree > max_deg)
+    return fail(PDD_ERR_UNSUPPORTED, n + ": poly_degree above " + std::to_string(max_deg));
+  if (F.poly_degree >= 0 && F.poly == nullptr) return fail(PDD_ERR_INVALID_ARG, n + ": poly is NULL");
+  return PDD_OK;
+}
+
+bool is_zero_fun(const pdd_fun& F) { return F.n_terms == 0 && F.poly_degree < 0; }
+
+pdd_status check_device_ptr(const void* p, const char* name) {
+  if (p == nullptr) return fail(PDD_ERR_INVALID_ARG, std::string(name) + " is NULL");
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PDD_ERR_INVALID_ARG, std::string(name) + " is not device memory");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(PDD_ERR_INVALID_ARG, std::string(name) + " is not device memory");
+  return PDD_OK;
+}
+
+// ----------------------------------------------------------------------------- tables
+struct Tables {
+  std::vector<DevFactor> fac;
+  std::vector<StageJob> jobs;
+  std::vector<int32_t> perm;
+  int ncoef = 0;
+
+  DevFun add(const pdd_fun& F, int dim, int pad_deg, bool nested) {
+    DevFun d{};
+    d.n_terms = F.n_terms;
+    d.n_factors = F.n_terms > 0 ? F.n_factors : 0;
+    d.fac_off = (int)fac.size();
+    for (int i = 0; i < F.n_terms * d.n_factors; ++i) {
+      const pdd_factor& s = F.factors[i];
+      DevFactor t{};
+      t.fn = s.fn; t.dim = s.dim; t.power = s.power;
+      t.ad = s.a; t.bd = s.b; t.af = (float)s.a; t.bf = (float)s.b;
+      fac.push_back(t);
+    }
+    d.coef_off = ncoef;
+    if (F.n_terms > 0) {
+      jobs.push_back(StageJob{F.coef, ncoef, F.n_terms, -1, 0});
+      ncoef += F.n_terms;
+    }
+    d.poly_deg = -1;
+    d.n_mono = 0;
+    d.poly_off = ncoef;
+    if (F.poly_degree >= 0) {
+      const int own = n_mono(dim, F.poly_degree);
+      if (nested) {
+        auto p = nested_to_graded(dim, F.poly_degree);
+        const int poff = (int)perm.size();
+        perm.insert(perm.end(), p.begin(), p.end());
+        jobs.push_back(StageJob{F.poly, ncoef, own, poff, 0});
+        d.poly_deg = F.poly_degree;
+        d.n_mono = own;
+        ncoef += own;
+      } else {
+        const int deg = std::max(pad_deg, F.poly_degree);
+        const int tot = n_mono(dim, deg);
+        jobs.push_back(StageJob{F.poly, ncoef, own, -1, 0});
+        if (tot > own) jobs.push_back(StageJob{nullptr, ncoef + own, tot - own, -1, 0});
+        d.poly_deg = deg;
+        d.n_mono = tot;
+        ncoef += tot;
+      }
+    }
+    return d;
+  }
+};
+
+// ----------------------------------------------------------------------------- device arena
+// One allocation carved into aligned pieces.
+struct Arena {
+  std::vector<std::pair<size_t, size_t>> parts;  // offset, size
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    const size_t off = (total + 255) & ~(size_t)255;
+    total = off + std::max<size_t>(bytes, 1);
+    return off;
+  }
+};
+
+int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+// per-device warning counters (censored paths, redrawn trees)
+std::mutex g_mu;
+unsigned long long* g_counters[64] = {nullptr};
+
+pdd_status counters(unsigned long long** out) {
+  int dev = 0;
+  PDD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(PDD_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_counters[dev] == nullptr) {
+    PDD_HIP(hipMalloc((void**)&g_counters[dev], 2 * sizeof(unsigned long long)));
+    PDD_HIP(hipMemset(g_counters[dev], 0, 2 * sizeof(unsigned long long)));
+  }
+  *out = g_counters[dev];
+  return PDD_OK;
+}
+
+// ----------------------------------------------------------------------------- plans
+// Everything a call enqueues, with its device buffers.  `enqueue` issues only
+// kernel launches (no memset, no copies), so it can be captured in a graph.
+struct Plan {
+  int device = 0;
+  void* arena = nullptr;
+  bool owned = false;   // hipMalloc'd (graph plan) vs stream-ordered
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+
+  LinearParams lp{};
+  BranchParams bp{};
+  bool branch = false;
+  bool plain = false;
+  bool adjoint = false;
+  WalkLaunch wl{};
+  BranchLaunch bl{};
+  std::vector<PlainLaunch> pl;
+
+  StageJob* d_jobs = nullptr;
+  int n_jobs = 0;
+  int32_t* d_perm = nullptr;
+  double* d_cd = nullptr;
+  float* d_cf = nullptr;
+  uint32_t* d_qhead = nullptr;
+  ItemStat* d_istat = nullptr;
+  int64_t* d_first = nullptr;
+  int64_t n_nodes = 0;
+  void* out = nullptr;
+  unsigned long long* ctr = nullptr;
+
+  // adjoint reduction
+  double* d_igrad = nullptr;
+  int grad_stride = 0;
+  int n_items = 0;
+  int32_t* d_slot_node = nullptr;
+  double* d_inv_n = nullptr;
+  const double* w = nullptr;
+  double* d_colsum = nullptr;
+  int32_t* d_gmap = nullptr;
+  struct Scatter { int col, count; bool gmap; double* dst; };
+  std::vector<Scatter> scatters;
+
+  hipError_t enqueue(hipStream_t st) const {
+    hipError_t e;
+    if ((e = launch_stage(d_jobs, n_jobs, d_perm, d_cd, d_cf, st)) != hipSuccess) return e;
+    if (plain) {
+      for (const auto& L : pl)
+        if ((e = launch_plain(L, st)) != hipSuccess) return e;
+      return launch_finalize_nodes(d_istat, d_first, n_nodes, out, ctr, st);
+    }
+    if ((e = launch_fill_u32(d_qhead, 1, 0u, st)) != hipSuccess) return e;
+    if (branch) {
+      if ((e = launch_branch(bl, st)) != hipSuccess) return e;
+    } else {
+      if ((e = launch_walk(wl, st)) != hipSuccess) return e;
+    }
+    if (out != nullptr)
+      if ((e = launch_finalize_nodes(d_istat, d_first, n_nodes, out, ctr, st)) != hipSuccess) return e;
+    if (adjoint) {
+      if ((e = launch_finalize_grad(d_igrad, grad_stride, grad_stride, n_items, d_slot_node, w, d_inv_n, d_colsum,
+                                    st)) != hipSuccess)
+        return e;
+      for (const auto& s : scatters)
+        if ((e = launch_scatter_add(d_colsum + s.col, s.gmap ? d_gmap : nullptr, s.count, s.dst, st)) != hipSuccess)
+          return e;
+    }
+    return hipSuccess;
+  }
+
+  ~Plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (owned && arena) (void)hipFree(arena);
+  }
+};
+
+std::unordered_map<std::string, std::unique_ptr<Plan>> g_plans;
+
+// Host-side staging buffer: copies are stream-ordered; the host vector is
+// pageable, which makes hipMemcpyAsync take its own copy before returning.
+struct Upload {
+  size_t off;
+  std::vector<char> bytes;
+};
+
+template <typename T>
+void put(std::vector<Upload>& ups, size_t off, const std::vector<T>& v) {
+  Upload u;
+  u.off = off;
+  u.bytes.resize(v.size() * sizeof(T));
+  if (!v.empty()) std::memcpy(u.bytes.data(), v.data(), u.bytes.size());
+  ups.push_back(std::move(u));
+}
+
+template <typename T>
+void key_add(std::string& k, const T& v) {
+  k.append(reinterpret_cast<const char*>(&v), sizeof(T));
+}
+
+void key_fun(std::string& k, const pdd_fun& F) {
+  key_add(k, F.n_terms);
+  key_add(k, F.n_factors);
+  if (F.n_terms > 0 && F.n_factors > 0)
+    k.append(reinterpret_cast<const char*>(F.factors), sizeof(pdd_factor) * (size_t)F.n_terms * F.n_factors);
+  key_add(k, F.coef);
+  key_add(k, F.poly_degree);
+  key_add(k, F.poly);
+}
+
+// Estimated mean exit time (in steps) from a node; used only to order work
+// items longest first.
+double est_steps(const pdd_linear_problem& P, const double* x, double dt) {
+  const pdd_domain& D = P.domain;
+  const double s2 = P.sigma * P.sigma;
+  double tau;
+  if (D.kind == PDD_DOM_BALL) {
+    double r2 = 0;
+    for (int k = 0; k < D.dim; ++k) r2 += (x[k] - D.center[k]) * (x[k] - D.center[k]);
+    tau = std::max(0.0, D.radius * D.radius - r2) / (D.dim * s2);
+  } else {
+    tau = 1e300;
+    for (int k = 0; k < D.dim; ++k) tau = std::min(tau, std::max(0.0, (x[k] - D.lo[k]) * (D.hi[k] - x[k])) / s2);
+  }
+  return 1.0 + tau / dt;
+}
+
+struct Items {
+  std::vector<WorkItem> q;        // queue order
+  std::vector<int64_t> first;     // per node: first slot
+  std::vector<int32_t> slot_node; // per slot: node
+};
+
+Items make_items(int64_t n_nodes, const int64_t* counts, int64_t count_all, int chunk, const std::vector<double>& cost) {
+  Items r;
+  r.first.resize((size_t)n_nodes + 1);
+  std::vector<WorkItem> slots;
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    r.first[(size_t)i] = (int64_t)slots.size();
+    const int64_t N = counts ? counts[i] : count_all;
+    for (int64_t p0 = 0; p0 < N; p0 += chunk) {
+      WorkItem w;
+      w.node = (int32_t)i;
+      w.p0 = (uint32_t)p0;
+      w.count = (uint32_t)std::min<int64_t>(chunk, N - p0);
+      w.slot = (int32_t)slots.size();
+      slots.push_back(w);
+      r.slot_node.push_back((int32_t)i);
+    }
+  }
+  r.first[(size_t)n_nodes] = (int64_t)slots.size();
+  r.q = slots;
+  if (!cost.empty()) {
+    std::stable_sort(r.q.begin(), r.q.end(), [&](const WorkItem& a, const WorkItem& b) {
+      return cost[(size_t)a.node] * a.count > cost[(size_t)b.node] * b.count;
+    });
+  }
+  return r;
+}
+
+}  // namespace
+
+// ============================================================================= linear walk
+namespace {
+
+struct LinearPlanArgs {
+  const pdd_linear_problem* P;
+  const double* nodes;
+  int64_t n_nodes;
+  const int64_t* paths;
+  double dt;
+  uint64_t seed;
+  pdd_options opt;
+  pdd_node_stat* out;
+  bool adjoint;
+  const double* w;
+  const pdd_fun_grad* grads;
+};
+
+pdd_status validate_linear(const LinearPlanArgs& a) {
+  if (a.P == nullptr) return fail(PDD_ERR_INVALID_ARG, "problem is NULL");
+  const pdd_linear_problem& P = *a.P;
+  const pdd_domain& D = P.domain;
+  if (D.dim < 1 || D.dim > 3) return fail(PDD_ERR_INVALID_ARG, "domain.dim must be 1..3");
+  if (D.kind == PDD_DOM_FREE) return fail(PDD_ERR_INVALID_ARG, "the linear walk needs a bounded domain (BOX or BALL)");
+  if (D.kind != PDD_DOM_BOX && D.kind != PDD_DOM_BALL) return fail(PDD_ERR_INVALID_ARG, "unknown domain kind");
+  if (D.kind == PDD_DOM_BOX)
+    for (int k = 0; k < D.dim; ++k)
+      if (!(D.lo[k] < D.hi[k]) || !std::isfinite(D.lo[k]) || !std::isfinite(D.hi[k]))
+        return fail(PDD_ERR_INVALID_ARG, "box needs finite lo < hi");
+  if (D.kind == PDD_DOM_BALL && !(D.radius > 0.0 && std::isfinite(D.radius)))
+    return fail(PDD_ERR_INVALID_ARG, "ball radius must be positive");
+  if (!(P.sigma > 0.0) || !std::isfinite(P.sigma)) return fail(PDD_ERR_INVALID_ARG, "sigma must be positive");
+  if (!(a.dt > 0.0) || !std::isfinite(a.dt)) return fail(PDD_ERR_INVALID_ARG, "dt must be positive");
+  if (a.n_nodes < 0 || a.n_nodes > (int64_t)1 << 30) return fail(PDD_ERR_INVALID_ARG, "n_nodes out of range");
+  if (a.n_nodes > 0 && a.paths == nullptr) return fail(PDD_ERR_INVALID_ARG, "paths_host is NULL");
+  for (int64_t i = 0; i < a.n_nodes; ++i)
+    if (a.paths[i] < 0 || a.paths[i] > (int64_t)0x7FFFFFFF)
+      return fail(PDD_ERR_INVALID_ARG, "paths per node must be in [0, 2^31)");
+  pdd_status s;
+  const int mt_bcf = a.adjoint ? kAdjTerms : 16;
+  for (int k = 0; k < D.dim; ++k)
+    if ((s = check_fun(P.b[k], D.dim, "b", 16, kMaxPolyBCF)) != PDD_OK) return s;
+  if ((s = check_fun(P.c, D.dim, "c", mt_bcf, kMaxPolyBCF)) != PDD_OK) return s;
+  if ((s = check_fun(P.f, D.dim, "f", mt_bcf, kMaxPolyBCF)) != PDD_OK) return s;
+  if ((s = check_fun(P.g, D.dim, "g", a.adjoint ? kAdjTerms : kMaxTerms, kMaxPolyG)) != PDD_OK) return s;
+  const pdd_options& o = a.opt;
+  if (o.precision < PDD_FP64_PLAIN || o.precision > PDD_FP32_STEP) return fail(PDD_ERR_INVALID_ARG, "unknown precision");
+  if (o.rng_layout != PDD_RNG_PAIR52 && o.rng_layout != PDD_RNG_QUAD24) return fail(PDD_ERR_INVALID_ARG, "unknown rng layout");
+  if (o.precision == PDD_FP32_STEP && o.rng_layout != PDD_RNG_QUAD24)
+    return fail(PDD_ERR_INVALID_ARG, "FP32 stepping requires the QUAD24 layout");
+  if (o.max_steps < 0 || o.max_steps > 0x7FFFFFFF) return fail(PDD_ERR_INVALID_ARG, "max_steps out of range");
+  if (o.chunk_paths < 0 || o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.refill_groups < 0 || o.refill_groups > 64)
+    return fail(PDD_ERR_INVALID_ARG, "schedule override out of range");
+  if (o.schedule < PDD_SCHED_AUTO || o.schedule > PDD_SCHED_PERSISTENT_GRAPH) return fail(PDD_ERR_INVALID_ARG, "unknown schedule");
+  if (a.n_nodes > 0) {
+    if ((s = check_device_ptr(a.nodes, "nodes_dev")) != PDD_OK) return s;
+    if (!a.adjoint || a.out) if ((s = check_device_ptr(a.out, "out_dev")) != PDD_OK) return s;
+    if (a.adjoint && (s = check_device_ptr(a.w, "w_dev")) != PDD_OK) return s;
+  }
+  if ((o.dump_phi || o.dump_steps) && a.adjoint)
+    return fail(PDD_ERR_UNSUPPORTED, "per-path dumps are not produced by the adjoint");
+  if (o.dump_steps && !o.dump_phi) return fail(PDD_ERR_INVALID_ARG, "dump_steps needs dump_phi");
+  if (a.adjoint) {
+    if (a.grads == nullptr) return fail(PDD_ERR_INVALID_ARG, "grads_host is NULL");
+    if (o.precision == PDD_FP64_PLAIN) return fail(PDD_ERR_UNSUPPORTED, "the adjoint has no plain FP64 variant; use PDD_FP64");
+  }
+  return PDD_OK;
+}
+
+pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
+  pdd_status s = validate_linear(a);
+  if (s != PDD_OK) return s;
+  if (a.n_nodes == 0) return PDD_OK;  // nothing to enqueue (gradients stay as they are)
+  const pdd_linear_problem& P = *a.P;
+  const int dim = P.domain.dim;
+  const pdd_options& o = a.opt;
+  const bool plain = o.precision == PDD_FP64_PLAIN;
+  const bool fp32 = o.precision == PDD_FP32_STEP;
+  const bool graph = !plain && (o.schedule == PDD_SCHED_AUTO || o.schedule == PDD_SCHED_PERSISTENT_GRAPH) &&
+                     o.dump_phi == nullptr;
+
+  // ---- plan cache lookup
+  std::string key;
+  if (graph) {
+    key_add(key, a.adjoint ? 2 : 1);
+    int dev = 0;
+    PDD_HIP(hipGetDevice(&dev));
+    key_add(key, dev);
+    key_add(key, P.domain);
+    key_add(key, P.sigma);
+    for (int k = 0; k < 3; ++k) key_fun(key, P.b[k]);
+    key_fun(key, P.c);
+    key_fun(key, P.f);
+    key_fun(key, P.g);
+    key_add(key, a.nodes);
+    key_add(key, a.n_nodes);
+    key.append(reinterpret_cast<const char*>(a.paths), sizeof(int64_t) * (size_t)a.n_nodes);
+    key_add(key, a.dt);
+    key_add(key, a.seed);
+    key_add(key, o);
+    key_add(key, a.out);
+    key_add(key, a.w);
+    if (a.adjoint)
+      for (int k = 0; k < 3; ++k) key_add(key, a.grads[k]);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+      PDD_HIP(hipGraphLaunch(it->second->exec, st));
+      return PDD_OK;
+    }
+  }
+
+  std::unique_ptr<Plan> plan(new Plan());
+  Plan& pl = *plan;
+  pl.plain = plain;
+  pl.adjoint = a.adjoint;
+  PDD_HIP(hipGetDevice(&pl.device));
+  if ((s = counters(&pl.ctr)) != PDD_OK) return s;
+
+  // ---- tables
+  const bool any_poly = P.c.poly_degree >= 0 || P.f.poly_degree >= 0 || P.b[0].poly_degree >= 0 ||
+                        (dim > 1 && P.b[1].poly_degree >= 0) || (dim > 2 && P.b[2].poly_degree >= 0);
+  const int dfc = any_poly ? kMaxPolyBCF : -1;
+  Tables T;
+  LinearParams& lp = pl.lp;
+  lp.dim = dim;
+  lp.dom_kind = P.domain.kind;
+  lp.layout = o.rng_layout;
+  for (int k = 0; k < 3; ++k) {
+    lp.lo[k] = P.domain.lo[k]; lp.hi[k] = P.domain.hi[k]; lp.ctr[k] = P.domain.center[k];
+    lp.lof[k] = (float)lp.lo[k]; lp.hif[k] = (float)lp.hi[k]; lp.ctrf[k] = (float)lp.ctr[k];
+  }
+  lp.rad = P.domain.radius;
+  lp.rad2 = P.domain.radius * P.domain.radius;
+  lp.radf = (float)lp.rad;
+  lp.rad2f = (float)lp.rad2;
+  lp.dt = a.dt;
+  lp.sdt = P.sigma * std::sqrt(a.dt);
+  lp.dtf = (float)lp.dt;
+  lp.sdtf = (float)lp.sdt;
+  lp.max_steps = o.max_steps > 0 ? o.max_steps : (int64_t)std::ceil(100.0 / a.dt);
+  if (lp.max_steps > 0x7FFFFFFF) lp.max_steps = 0x7FFFFFFF;
+  lp.key0 = (uint32_t)a.seed;
+  lp.key1 = (uint32_t)(a.seed >> 32);
+  pdd_fun zero{};
+  zero.poly_degree = -1;
+  for (int k = 0; k < 3; ++k) lp.b[k] = T.add(k < dim ? P.b[k] : zero, dim, dfc, false);
+  lp.c = T.add(P.c, dim, dfc, false);
+  lp.f = T.add(P.f, dim, dfc, false);
+  lp.g = T.add(P.g, dim, 0, true);
+  lp.n_fac = (int)T.fac.size();
+
+  // ---- work items
+  const Tuning tune = choose_tuning(dim, fp32, a.adjoint, o, device_cus());
+  std::vector<double> cost((size_t)a.n_nodes);
+  for (int64_t i = 0; i < a.n_nodes; ++i) cost[(size_t)i] = 0.0;
+  std::vector<double> hnodes((size_t)a.n_nodes * dim);
+  if (a.n_nodes > 0) {
+    PDD_HIP(hipMemcpyAsync(hnodes.data(), a.nodes, hnodes.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    PDD_HIP(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < a.n_nodes; ++i) cost[(size_t)i] = est_steps(P, &hnodes[(size_t)i * dim], a.dt);
+  }
+  Items items;
+  std::vector<int64_t> plain_first;
+  std::vector<PlainLaunch> plain_launches;
+  if (!plain) {
+    items = make_items(a.n_nodes, a.paths, 0, tune.chunk_paths, cost);
+  }
+  const int n_items = (int)items.q.size();
+  pl.n_items = n_items;
+  pl.n_nodes = a.n_nodes;
+
+  // ---- arena layout
+  Arena A;
+  const size_t o_jobs = A.add(sizeof(StageJob) * std::max<size_t>(1, T.jobs.size()));
+  const size_t o_perm = A.add(sizeof(int32_t) * std::max<size_t>(1, T.perm.size()));
+  const size_t o_fac = A.add(sizeof(DevFactor) * std::max<size_t>(1, T.fac.size()));
+  const size_t o_cd = A.add(sizeof(double) * std::max(1, T.ncoef));
+  const size_t o_cf = A.add(sizeof(float) * std::max(1, T.ncoef));
+  const size_t o_q = A.add(sizeof(uint32_t) * 4);
+  size_t o_items = 0, o_istat = 0, o_first = 0, o_doff = 0;
+  std::vector<int64_t> doff((size_t)a.n_nodes + 1, 0);
+  for (int64_t i = 0; i < a.n_nodes; ++i) doff[(size_t)i + 1] = doff[(size_t)i] + a.paths[i];
+  int64_t n_stat = 0;
+  if (plain) {
+    plain_first.resize((size_t)a.n_nodes + 1);
+    for (int64_t i = 0; i < a.n_nodes; ++i) {
+      plain_first[(size_t)i] = n_stat;
+      const int64_t N = a.paths[i];
+      const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((N + kBlock - 1) / kBlock, 4096));
+      n_stat += nb;
+    }
+    plain_first[(size_t)a.n_nodes] = n_stat;
+  } else {
+    n_stat = n_items;
+    o_items = A.add(sizeof(WorkItem) * std::max(1, n_items));
+  }
+  o_istat = A.add(sizeof(ItemStat) * std::max<int64_t>(1, n_stat));
+  o_first = A.add(sizeof(int64_t) * ((size_t)a.n_nodes + 1));
+  o_doff = A.add(sizeof(int64_t) * ((size_t)a.n_nodes + 1));
+  // adjoint buffers
+  const int NM = dfc >= 0 ? n_mono(dim, dfc) : 0;
+  const int nt = (P.c.n_terms > 0 || P.f.n_terms > 0 || P.g.n_terms > 0) ? kAdjTerms : 0;
+  const int NP = nt + NM;
+  const int ngm = lp.g.poly_deg >= 0 ? lp.g.n_mono : 0;
+  size_t o_igrad = 0, o_slot = 0, o_invn = 0, o_col = 0, o_gmap = 0;
+  std::vector<int32_t> gmap;
+  if (a.adjoint) {
+    pl.grad_stride = nt + ngm + 2 * NP;
+    o_igrad = A.add(sizeof(double) * (size_t)std::max(1, n_items) * (size_t)pl.grad_stride);
+    o_slot = A.add(sizeof(int32_t) * std::max(1, n_items));
+    o_invn = A.add(sizeof(double) * std::max<int64_t>(1, a.n_nodes));
+    o_col = A.add(sizeof(double) * std::max(1, pl.grad_stride));
+    if (ngm > 0) gmap = nested_to_graded(dim, lp.g.poly_deg);
+    o_gmap = A.add(sizeof(int32_t) * std::max<size_t>(1, gmap.size()));
+  }
+
+  // ---- allocate
+  if (graph) {
+    PDD_HIP(hipMalloc(&pl.arena, A.total));
+    pl.owned = true;
+  } else {
+    PDD_HIP(hipMallocAsync(&pl.arena, A.total, st));
+  }
+  char* base = (char*)pl.arena;
+  pl.d_jobs = (StageJob*)(base + o_jobs);
+  pl.n_jobs = (int)T.jobs.size();
+  pl.d_perm = (int32_t*)(base + o_perm);
+  DevFactor* d_fac = (DevFactor*)(base + o_fac);
+  pl.d_cd = (double*)(base + o_cd);
+  pl.d_cf = (float*)(base + o_cf);
+  pl.d_qhead = (uint32_t*)(base + o_q);
+  pl.d_istat = (ItemStat*)(base + o_istat);
+  pl.d_first = (int64_t*)(base + o_first);
+  int64_t* d_doff = (int64_t*)(base + o_doff);
+  pl.out = a.out;
+  lp.fac = d_fac;
+  lp.cd = pl.d_cd;
+  lp.cf = pl.d_cf;
+  lp.nodes = a.nodes;
+
+  std::vector<Upload> ups;
+  put(ups, o_jobs, T.jobs);
+  put(ups, o_perm, T.perm);
+  put(ups, o_fac, T.fac);
+  put(ups, o_doff, doff);
+  if (plain) {
+    put(ups, o_first, plain_first);
+  } else {
+    put(ups, o_first, items.first);
+    put(ups, o_items, items.q);
+  }
+  if (a.adjoint) {
+    std::vector<double> invn((size_t)std::max<int64_t>(1, a.n_nodes), 0.0);
+    for (int64_t i = 0; i < a.n_nodes; ++i) invn[(size_t)i] = a.paths[i] > 0 ? 1.0 / (double)a.paths[i] : 0.0;
+    put(ups, o_slot, items.slot_node);
+    put(ups, o_invn, invn);
+    if (!gmap.empty()) put(ups, o_gmap, gmap);
+    pl.d_igrad = (double*)(base + o_igrad);
+    pl.d_slot_node = (int32_t*)(base + o_slot);
+    pl.d_inv_n = (double*)(base + o_invn);
+    pl.d_colsum = (double*)(base + o_col);
+    pl.d_gmap = (int32_t*)(base + o_gmap);
+    pl.w = a.w;
+    // scatter of reduced columns into the caller's arrays
+    const pdd_fun_grad& gg = a.grads[0];
+    const pdd_fun_grad& gf = a.grads[1];
+    const pdd_fun_grad& gc = a.grads[2];
+    int col = 0;
+    if (gg.dcoef && P.g.n_terms > 0) pl.scatters.push_back({col, P.g.n_terms, false, gg.dcoef});
+    col += nt;
+    if (gg.dpoly && ngm > 0) pl.scatters.push_back({col, ngm, true, gg.dpoly});
+    col += ngm;
+    if (gf.dcoef && P.f.n_terms > 0) pl.scatters.push_back({col, P.f.n_terms, false, gf.dcoef});
+    if (gf.dpoly && P.f.poly_degree >= 0) pl.scatters.push_back({col + nt, n_mono(dim, P.f.poly_degree), false, gf.dpoly});
+    col += NP;
+    if (gc.dcoef && P.c.n_terms > 0) pl.scatters.push_back({col, P.c.n_terms, false, gc.dcoef});
+    if (gc.dpoly && P.c.poly_degree >= 0) pl.scatters.push_back({col + nt, n_mono(dim, P.c.poly_degree), false, gc.dpoly});
+  }
+  for (const auto& u : ups)
+    if (!u.bytes.empty()) PDD_HIP(hipMemcpyAsync(base + u.off, u.bytes.data(), u.bytes.size(), hipMemcpyHostToDevice, st));
+
+  // ---- launch descriptors
+  if (plain) {
+    for (int64_t i = 0; i < a.n_nodes; ++i) {
+      PlainLaunch L{};
+      L.P = &pl.lp;
+      L.dfc = dfc;
+      L.grid = (int)(plain_first[(size_t)i + 1] - plain_first[(size_t)i]);
+      L.node = (int)i;
+      L.n_paths = (uint32_t)a.paths[i];
+      L.bstat = pl.d_istat + plain_first[(size_t)i];
+      L.dump_phi = o.dump_phi;
+      L.dump_steps = o.dump_steps;
+      L.dump_base = doff[(size_t)i];
+      pl.pl.push_back(L);
+    }
+  } else {
+    WalkLaunch& L = pl.wl;
+    L.P = &pl.lp;
+    L.dfc = dfc;
+    L.nt = nt;
+    L.fp32 = fp32;
+    L.adjoint = a.adjoint;
+    const int max_blocks = tune.blocks_per_cu * device_cus();
+    const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
+    L.grid = std::max(1, std::min(max_blocks, need));
+    L.items = (const WorkItem*)(base + o_items);
+    L.n_items = n_items;
+    L.qhead = pl.d_qhead;
+    L.istat = pl.d_istat;
+    L.igrad = pl.d_igrad;
+    L.grad_stride = pl.grad_stride;
+    L.dump_phi = o.dump_phi;
+    L.dump_steps = o.dump_steps;
+    L.dump_off = d_doff;
+    L.refill_groups = tune.refill_groups;
+  }
+
+  // ---- run
+  if (!graph) {
+    hipError_t e = pl.enqueue(st);
+    if (e != hipSuccess) {
+      (void)hipFreeAsync(pl.arena, st);
+      return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    PDD_HIP(hipFreeAsync(pl.arena, st));
+    return PDD_OK;
+  }
+  // graph: uploads are ordered before capture on the caller's stream; the
+  // capture runs on a private stream that first waits for them
+  hipStream_t cap;
+  PDD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipEvent_t ready;
+  PDD_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  PDD_HIP(hipEventRecord(ready, st));
+  PDD_HIP(hipStreamWaitEvent(cap, ready, 0));
+  PDD_HIP(hipStreamSynchronize(cap));
+  PDD_HIP(hipEventDestroy(ready));
+  PDD_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = pl.enqueue(cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cap, &g);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(PDD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  pl.graph = g;
+  PDD_HIP(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
+  PDD_HIP(hipGraphLaunch(pl.exec, st));
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_plans[key] = std::move(plan);
+  return PDD_OK;
+}
+
+}  // namespace
+
+// ============================================================================= branching
+namespace {
+
+// Assumption 3.2 with l0(s) = sum |alpha_k| s^k, l(s) = beta (l0(s psi_sup)/psi_sup - s):
+// admissible if l(1) <= 0, or l has a zero beyond 1, or int_1^inf ds / l(s) > T.
+bool admissible(const pdd_branching_problem& B, std::string* why) {
+  const double ps = B.psi_sup;
+  auto l = [&](double s) {
+    double l0 = 0.0, p = 1.0;
+    for (int k = 0; k < 5; ++k) {
+      l0 += std::fabs(B.alpha[k]) * p;
+      p *= s * ps;
+    }
+    return B.beta * (l0 / ps - s);
+  };
+  if (l(1.0) <= 0.0) return true;
+  // scan for a zero on (1, 1e12] on a log grid; integrate 1/l meanwhile
+  const int n = 200000;
+  const double lmax = std::log(1e12);
+  double integral = 0.0;
+  double prev_t = 0.0, prev_f = 1.0 / l(1.0);
+  for (int i = 1; i <= n; ++i) {
+    const double t = lmax * i / n;
+    const double s = std::exp(t);
+    const double v = l(s);
+    if (v <= 0.0) return true;
+    const double f = s / v;  // integrand in t = ln s (ds = s dt)
+    integral += 0.5 * (f + prev_f) * (t - prev_t);
+    prev_t = t;
+    prev_f = f;
+  }
+  // tail beyond s = 1e12: for l growing at least quadratically it is at most
+  // s / l(s) at the last grid point
+  integral += prev_f;
+  if (integral > B.T) return true;
+  if (why) *why = "the branching representation may blow up before T (Assumption 3.2: l(1) > 0 and int 1/l = " +
+                  std::to_string(integral) + " <= T)";
+  return false;
+}
+
+pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, int64_t n_points, int64_t trees,
+                         uint64_t seed, const pdd_options* op, pdd_node_stat* out, hipStream_t st) {
+  if (Bp == nullptr || op == nullptr) return fail(PDD_ERR_INVALID_ARG, "problem or options is NULL");
+  const pdd_branching_problem& B = *Bp;
+  const pdd_options& o = *op;
+  if (B.dim < 1 || B.dim > 3) return fail(PDD_ERR_INVALID_ARG, "dim must be 1..3");
+  if (!(B.sigma >= 0.0) || !std::isfinite(B.sigma)) return fail(PDD_ERR_INVALID_ARG, "sigma must be >= 0");
+  if (!(B.beta > 0.0) || !std::isfinite(B.beta)) return fail(PDD_ERR_INVALID_ARG, "beta must be positive");
+  if (!(B.T >= 0.0) || !std::isfinite(B.T)) return fail(PDD_ERR_INVALID_ARG, "T must be >= 0");
+  if (B.max_segments < 1 || B.max_segments > 4096) return fail(PDD_ERR_INVALID_ARG, "max_segments must be 1..4096");
+  double qs = 0.0;
+  for (int k = 0; k < 5; ++k) {
+    if (!(B.q[k] >= 0.0) || !std::isfinite(B.alpha[k])) return fail(PDD_ERR_INVALID_ARG, "q must be >= 0, alpha finite");
+    if (B.alpha[k] != 0.0 && !(B.q[k] > 0.0)) return fail(PDD_ERR_INVALID_ARG, "q_i must be > 0 where alpha_i != 0");
+    qs += B.q[k];
+  }
+  if (std::fabs(qs - 1.0) > 1e-12) return fail(PDD_ERR_INVALID_ARG, "q must sum to 1");
+  if (!(B.psi_sup > 0.0) || !std::isfinite(B.psi_sup)) return fail(PDD_ERR_INVALID_ARG, "psi_sup must be positive");
+  if (trees < 0 || trees > (int64_t)0x7FFFFFFF) return fail(PDD_ERR_INVALID_ARG, "trees_per_point must be in [0, 2^31)");
+  if (n_points < 0 || n_points > (int64_t)1 << 30) return fail(PDD_ERR_INVALID_ARG, "n_points out of range");
+  if (o.precision < PDD_FP64_PLAIN || o.precision > PDD_FP32_STEP) return fail(PDD_ERR_INVALID_ARG, "unknown precision");
+  if (o.rng_layout != PDD_RNG_PAIR52 && o.rng_layout != PDD_RNG_QUAD24) return fail(PDD_ERR_INVALID_ARG, "unknown rng layout");
+  if (o.precision == PDD_FP32_STEP && o.rng_layout != PDD_RNG_QUAD24)
+    return fail(PDD_ERR_INVALID_ARG, "FP32 positions require the QUAD24 layout");
+  if (o.dump_steps && !o.dump_phi) return fail(PDD_ERR_INVALID_ARG, "dump_steps needs dump_phi");
+  pdd_status s;
+  if ((s = check_fun(B.psi, B.dim, "psi", kMaxTerms, kMaxPolyG)) != PDD_OK) return s;
+  std::string why;
+  if (!admissible(B, &why)) return fail(PDD_ERR_NOT_ADMISSIBLE, why);
+  if (n_points > 0) {
+    if ((s = check_device_ptr(points, "points_dev")) != PDD_OK) return s;
+    if ((s = check_device_ptr(out, "out_dev")) != PDD_OK) return s;
+  }
+  if (n_points == 0) return PDD_OK;
+  const bool fp32 = o.precision == PDD_FP32_STEP;
+
+  std::unique_ptr<Plan> plan(new Plan());
+  Plan& pl = *plan;
+  pl.branch = true;
+  PDD_HIP(hipGetDevice(&pl.device));
+  if ((s = counters(&pl.ctr)) != PDD_OK) return s;
+  Tables T;
+  BranchParams& bp = pl.bp;
+  bp.dim = B.dim;
+  bp.max_segments = B.max_segments;
+  int L = 0;
+  for (int k = 0; k < 5; ++k)
+    if (B.q[k] > 0.0) L = k;
+  bp.label_base = std::max(2, L);
+  bp.sigma = B.sigma;
+  bp.beta = B.beta;
+  bp.T = B.T;
+  bp.sigmaf = (float)B.sigma;
+  bp.betaf = (float)B.beta;
+  bp.Tf = (float)B.T;
+  double cum = 0.0;
+  for (int k = 0; k < 5; ++k) {
+    bp.alpha[k] = B.alpha[k];
+    bp.q[k] = B.q[k];
+    bp.ratio[k] = B.q[k] > 0.0 ? B.alpha[k] / B.q[k] : 0.0;
+    cum += B.q[k];
+    bp.qcum[k] = cum;
+    bp.qcumf[k] = (float)cum;
+  }
+  bp.key0 = (uint32_t)seed;
+  bp.key1 = (uint32_t)(seed >> 32);
+  bp.psi = T.add(B.psi, B.dim, 0, true);
+  bp.n_fac = (int)T.fac.size();
+
+  const Tuning tune = choose_branch_tuning(B.dim, fp32, o, device_cus());
+  Items items = make_items(n_points, nullptr, trees, tune.chunk_paths, {});
+  const int n_items = (int)items.q.size();
+  const int max_blocks = tune.blocks_per_cu * device_cus();
+  const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
+  const int grid = std::max(1, std::min(max_blocks, need));
+  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32));
+
+  Arena A;
+  const size_t o_jobs = A.add(sizeof(StageJob) * std::max<size_t>(1, T.jobs.size()));
+  const size_t o_perm = A.add(sizeof(int32_t) * std::max<size_t>(1, T.perm.size()));
+  const size_t o_fac = A.add(sizeof(DevFactor) * std::max<size_t>(1, T.fac.size()));
+  const size_t o_cd = A.add(sizeof(double) * std::max(1, T.ncoef));
+  const size_t o_cf = A.add(sizeof(float) * std::max(1, T.ncoef));
+  const size_t o_q = A.add(sizeof(uint32_t) * 4);
+  const size_t o_items = A.add(sizeof(WorkItem) * std::max(1, n_items));
+  const size_t o_istat = A.add(sizeof(ItemStat) * std::max(1, n_items));
+  const size_t o_first = A.add(sizeof(int64_t) * ((size_t)n_points + 1));
+  const size_t o_spill =
+      A.add(branch_stack_entry_bytes(fp32) * (size_t)std::max<int64_t>(1, spill_entries) * (size_t)grid * kBlock);
+  PDD_HIP(hipMallocAsync(&pl.arena, A.total, st));
+  char* base = (char*)pl.arena;
+  pl.d_jobs = (StageJob*)(base + o_jobs);
+  pl.n_jobs = (int)T.jobs.size();
+  pl.d_perm = (int32_t*)(base + o_perm);
+  pl.d_cd = (double*)(base + o_cd);
+  pl.d_cf = (float*)(base + o_cf);
+  pl.d_qhead = (uint32_t*)(base + o_q);
+  pl.d_istat = (ItemStat*)(base + o_istat);
+  pl.d_first = (int64_t*)(base + o_first);
+  pl.n_nodes = n_points;
+  pl.out = out;
+  bp.fac = (const DevFactor*)(base + o_fac);
+  bp.cd = pl.d_cd;
+  bp.cf = pl.d_cf;
+  bp.points = points;
+  std::vector<Upload> ups;
+  put(ups, o_jobs, T.jobs);
+  put(ups, o_perm, T.perm);
+  put(ups, o_fac, T.fac);
+  put(ups, o_first, items.first);
+  put(ups, o_items, items.q);
+  for (const auto& u : ups)
+    if (!u.bytes.empty()) PDD_HIP(hipMemcpyAsync(base + u.off, u.bytes.data(), u.bytes.size(), hipMemcpyHostToDevice, st));
+  BranchLaunch& BL = pl.bl;
+  BL.P = &pl.bp;
+  BL.fp32 = fp32;
+  BL.layout = o.rng_layout;
+  BL.grid = grid;
+  BL.items = (const WorkItem*)(base + o_items);
+  BL.n_items = n_items;
+  BL.qhead = pl.d_qhead;
+  BL.istat = pl.d_istat;
+  BL.dump_val = o.dump_phi;
+  BL.dump_segs = o.dump_steps;
+  BL.trees = trees;
+  BL.stack = base + o_spill;
+  BL.stack_entries = spill_entries;
+  hipError_t e = pl.enqueue(st);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(pl.arena, st);
+    return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+  PDD_HIP(hipFreeAsync(pl.arena, st));
+  return PDD_OK;
+}
+
+}  // namespace
+
+// ============================================================================= C ABI
+extern "C" {
+
+pdd_status pdd_mc_interface(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                            const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
+                            pdd_node_stat* out_dev, void* hip_stream) {
+  try {
+    if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
+    LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, false, nullptr, nullptr};
+    return run_linear(a, (hipStream_t)hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_branching_eval(const pdd_branching_problem* problem, const double* points_dev, int64_t n_points,
+                              int64_t trees_per_point, uint64_t seed, const pdd_options* options,
+                              pdd_node_stat* out_dev, void* hip_stream) {
+  try {
+    return run_branching(problem, points_dev, n_points, trees_per_point, seed, options, out_dev,
+                         (hipStream_t)hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_mc_adjoint(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                          const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
+                          const double* w_dev, const pdd_fun_grad* grads_host, pdd_node_stat* out_dev,
+                          void* hip_stream) {
+  try {
+    if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
+    LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, true, w_dev, grads_host};
+    return run_linear(a, (hipStream_t)hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_query_warnings(void* hip_stream, int64_t* censored_out, int64_t* redrawn_out) {
+  unsigned long long* c = nullptr;
+  pdd_status s = counters(&c);
+  if (s != PDD_OK) return s;
+  PDD_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+  unsigned long long h[2] = {0, 0}, z[2] = {0, 0};
+  PDD_HIP(hipMemcpy(h, c, sizeof(h), hipMemcpyDeviceToHost));
+  PDD_HIP(hipMemcpy(c, z, sizeof(z), hipMemcpyHostToDevice));
+  if (censored_out) *censored_out = (int64_t)h[0];
+  if (redrawn_out) *redrawn_out = (int64_t)h[1];
+  if (h[0] > 0) return PDD_WARN_CENSORED;
+  if (h[1] > 0) return PDD_WARN_REDRAWN;
+  return PDD_OK;
+}
+
+pdd_status pdd_release_workspace(void) {
+  PDD_HIP(hipDeviceSynchronize());
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_plans.clear();
+  return PDD_OK;
+}
+
+const char* pdd_status_string(pdd_status status) {
+  switch (status) {
+    case PDD_OK: return "ok";
+    case PDD_WARN_CENSORED: return "some paths were censored at max_steps";
+    case PDD_WARN_REDRAWN: return "some trees were pruned and redrawn";
+    case PDD_ERR_INVALID_ARG: return "invalid argument";
+    case PDD_ERR_UNSUPPORTED: return "unsupported problem or option";
+    case PDD_ERR_NOT_ADMISSIBLE: return "branching data not admissible (Assumption 3.2)";
+    case PDD_ERR_HIP: return "HIP runtime error";
+    case PDD_ERR_NO_MEMORY: return "out of memory";
+  }
+  return "unknown status";
+}
+
+const char* pdd_last_error(void) { return g_last_error.c_str(); }
+
+int pdd_version(void) { return PDD_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Structures shared by the host layer (capi.cpp) and the HIP kernels.
+#pragma once
+#include <stdint.h>
+
+namespace pdd {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;                 // 4 waves per workgroup
+constexpr int kMaxFactors = 4;
+constexpr int kMaxPolyBCF = 3;              // dense-polynomial degree limit for b, c, f
+constexpr int kMaxPolyG = 8;                // dense-polynomial degree limit for g and psi
+constexpr int kAdjTerms = 4;                // generic terms of g, f, c with tangents in the adjoint
+constexpr int kMaxTerms = 64;
+
+enum : int { FN_POW = 0, FN_EXP = 1, FN_SIN = 2, FN_COS = 3, FN_TANH = 4 };
+enum : int { DOM_BOX = 0, DOM_BALL = 1, DOM_FREE = 2 };
+enum : int { RNG_PAIR52 = 0, RNG_QUAD24 = 1 };
+
+// Factor fn(a x[dim] + b)^power, in both precisions.
+struct DevFactor {
+  int32_t fn, dim, power, pad;
+  float af, bf;
+  double ad, bd;
+};
+
+// Where a function's data live inside the staged tables.  Coefficients are in
+// one table (double and float copies); the dense polynomial of b, c, f is in
+// graded-lex order, that of g and psi in "nested" order
+// (for a: for b: for c, total degree <= deg) so that it can be evaluated by
+// three running products.
+struct DevFun {
+  int32_t n_terms, n_factors, fac_off, coef_off;
+  int32_t poly_deg, n_mono, poly_off, pad;
+};
+
+struct LinearParams {
+  int32_t dim, dom_kind, layout, n_fac;
+  double lo[3], hi[3], ctr[3], rad, rad2;
+  float lof[3], hif[3], ctrf[3], radf, rad2f;
+  double dt, sdt;                 // sdt = sigma * sqrt(dt)
+  float dtf, sdtf;
+  int64_t max_steps;
+  uint32_t key0, key1;
+  DevFun b[3], c, f, g;
+  const DevFactor* fac;
+  const double* cd;
+  const float* cf;
+  const double* nodes;
+};
+
+struct BranchParams {
+  int32_t dim, max_segments, label_base, n_fac;
+  double sigma, beta, T;
+  float sigmaf, betaf, Tf, pad0;
+  double alpha[5], q[5], ratio[5], qcum[5];
+  float qcumf[5], pad1[3];
+  uint32_t key0, key1;
+  DevFun psi;
+  const DevFactor* fac;
+  const double* cd;
+  const float* cf;
+  const double* points;
+};
+
+// One unit of work for a wavefront: `count` consecutive paths (trees) of one
+// node starting at path index p0.  `slot` is the item's position in
+// node-major order, where its partial result is written.
+struct WorkItem {
+  int32_t node;
+  uint32_t p0;
+  uint32_t count;
+  int32_t slot;
+};
+
+// Partial statistics of one work item (Welford triple + counters).
+struct ItemStat {
+  double mean, m2;
+  int64_t n, steps, censored, redrawn;
+};
+
+// Copy job for the coefficient staging kernel: dst[dst_off + k] = src[perm ? perm[k] : k].
+struct StageJob {
+  const double* src;
+  int32_t dst_off, count, perm_off, pad;
+};
+
+}  // namespace pdd

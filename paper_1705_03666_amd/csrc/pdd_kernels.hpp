@@ -1,0 +1,78 @@
+// Launch descriptors and launcher entry points of the HIP kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pdd_internal.hpp"
+
+namespace pdd {
+
+// Device mirror of pdd_node_stat (40 bytes).
+struct pdd_node_stat_dev {
+  double mean, m2;
+  int64_t n, steps, censored;
+};
+
+struct WalkLaunch {
+  const LinearParams* P;
+  int dfc;                   // -1: no polynomial part in b, c, f; else 3
+  int nt;                    // adjoint: generic-term tangent slots (0 or kAdjTerms)
+  bool fp32;
+  bool adjoint;
+  int grid;
+  const WorkItem* items;
+  int n_items;
+  uint32_t* qhead;
+  ItemStat* istat;
+  double* igrad;
+  int grad_stride;
+  double* dump_phi;
+  int64_t* dump_steps;
+  const int64_t* dump_off;
+  int refill_groups;
+};
+
+struct PlainLaunch {
+  const LinearParams* P;
+  int dfc;
+  int grid;
+  int node;
+  uint32_t n_paths;
+  ItemStat* bstat;
+  double* dump_phi;
+  int64_t* dump_steps;
+  int64_t dump_base;
+};
+
+struct BranchLaunch {
+  const BranchParams* P;
+  bool fp32;
+  int layout;
+  int grid;
+  const WorkItem* items;
+  int n_items;
+  uint32_t* qhead;
+  ItemStat* istat;
+  double* dump_val;
+  int64_t* dump_segs;
+  int64_t trees;
+  void* stack;               // spill stack for deep trees
+  int64_t stack_entries;     // entries per lane
+};
+
+hipError_t launch_walk(const WalkLaunch& L, hipStream_t st);
+hipError_t launch_plain(const PlainLaunch& L, hipStream_t st);
+hipError_t launch_branch(const BranchLaunch& L, hipStream_t st);
+size_t branch_stack_entry_bytes(bool fp32);
+int branch_lds_depth(bool fp32);
+hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, int64_t n_nodes, void* out,
+                                 unsigned long long* counters, hipStream_t st);
+hipError_t launch_finalize_grad(const double* igrad, int stride, int n_cols, int n_items, const int32_t* slot_node,
+                                const double* w, const double* inv_n, double* colsum, hipStream_t st);
+hipError_t launch_scatter_add(const double* src, const int32_t* map, int count, double* dst, hipStream_t st);
+hipError_t launch_stage(const StageJob* jobs, int n_jobs, const int32_t* perm, double* cd, float* cf,
+                        hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t st);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
+
+}  // namespace pdd

@@ -1,0 +1,133 @@
+// Reduction, staging and fill kernels shared by all entry points, and the
+// dispatch of the walk launch to its instantiation unit.
+#include <hip/hip_runtime.h>
+
+#include "pdd_device.hpp"
+#include "pdd_kernels.hpp"
+
+namespace pdd {
+
+// ---------------------------------------------------------------------------
+// Merge item partials into per-node statistics in item-slot order (fixed).
+__global__ void k_finalize_nodes(const ItemStat* __restrict__ istat, const int64_t* __restrict__ first,
+                                 int64_t n_nodes, pdd_node_stat_dev* __restrict__ out,
+                                 unsigned long long* __restrict__ counters) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes) return;
+  double n = 0.0, m = 0.0, q = 0.0;
+  int64_t st = 0, ce = 0, rd = 0;
+  for (int64_t s = first[i]; s < first[i + 1]; ++s) {
+    const ItemStat v = istat[s];
+    chan_merge(n, m, q, (double)v.n, v.mean, v.m2);
+    st += v.steps;
+    ce += v.censored;
+    rd += v.redrawn;
+  }
+  pdd_node_stat_dev r;
+  r.mean = m; r.m2 = q; r.n = (int64_t)n; r.steps = st; r.censored = ce;
+  out[i] = r;
+  if (counters != nullptr && (ce != 0 || rd != 0)) {
+    if (ce) atomicAdd(&counters[0], (unsigned long long)ce);
+    if (rd) atomicAdd(&counters[1], (unsigned long long)rd);
+  }
+}
+
+// Adjoint reduction: grad[k] = sum over items s (in slot order) of
+// (w[node_s] / N[node_s]) * row_s[k]; one block per column, fixed tree order.
+__global__ void k_finalize_grad(const double* __restrict__ igrad, int stride, int n_items,
+                                const int32_t* __restrict__ slot_node, const double* __restrict__ w,
+                                const double* __restrict__ inv_n, double* __restrict__ colsum) {
+  const int col = blockIdx.x;
+  __shared__ double part[kBlock];
+  double acc = 0.0;
+  for (int s = threadIdx.x; s < n_items; s += blockDim.x) {
+    const int nd = slot_node[s];
+    acc += (w[nd] * inv_n[nd]) * igrad[(size_t)s * stride + col];
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) colsum[col] = part[0];
+}
+
+// dst[map[k]] += src[k] for the gradient columns of one coefficient array.
+__global__ void k_scatter_add(const double* __restrict__ src, const int32_t* __restrict__ map, int count,
+                              double* __restrict__ dst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) dst[map ? map[k] : k] += src[k];
+}
+
+// Copy the caller's coefficient arrays into the staged FP64/FP32 tables.
+__global__ void k_stage(const StageJob* __restrict__ jobs, int n_jobs, const int32_t* __restrict__ perm,
+                        double* __restrict__ cd, float* __restrict__ cf) {
+  for (int j = 0; j < n_jobs; ++j) {
+    const StageJob J = jobs[j];
+    for (int k = threadIdx.x; k < J.count; k += blockDim.x) {
+      const int src = J.perm_off >= 0 ? perm[J.perm_off + k] : k;
+      const double v = J.src != nullptr ? J.src[src] : 0.0;
+      cd[J.dst_off + k] = v;
+      cf[J.dst_off + k] = (float)v;
+    }
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_walk_fwd(const WalkLaunch& L, hipStream_t st);
+hipError_t launch_walk_adj_f32(const WalkLaunch& L, hipStream_t st);
+hipError_t launch_walk_adj_f64(const WalkLaunch& L, hipStream_t st);
+
+hipError_t launch_walk(const WalkLaunch& L, hipStream_t st) {
+  if (!L.adjoint) return launch_walk_fwd(L, st);
+  return L.fp32 ? launch_walk_adj_f32(L, st) : launch_walk_adj_f64(L, st);
+}
+
+hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, int64_t n_nodes, void* out,
+                                 unsigned long long* counters, hipStream_t st) {
+  const int64_t blocks = (n_nodes + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_finalize_nodes, dim3((unsigned)blocks), dim3(kBlock), 0, st, istat, first, n_nodes,
+                     (pdd_node_stat_dev*)out, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_grad(const double* igrad, int stride, int n_cols, int n_items, const int32_t* slot_node,
+                                const double* w, const double* inv_n, double* colsum, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_grad, dim3(n_cols), dim3(kBlock), 0, st, igrad, stride, n_items, slot_node, w,
+                     inv_n, colsum);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_add(const double* src, const int32_t* map, int count, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_add, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, map, count, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const StageJob* jobs, int n_jobs, const int32_t* perm, double* cd, float* cf,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_stage, dim3(1), dim3(kBlock), 0, st, jobs, n_jobs, perm, cd, cf);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kBlock), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace pdd

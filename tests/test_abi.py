@@ -1,0 +1,142 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, and rejects malformed arguments before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pdd.h")
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1705_03666_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("libpdd.so not built (run __graft_entry__.build())")
+    return _abi
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:pdd_status|const char\*|int)\s+(pdd_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("pdd_mc_interface", "pdd_branching_eval", "pdd_mc_adjoint"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(abi):
+    lib = C.CDLL(abi.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert sorted(declared_functions()) == sorted(abi.EXPORTED)
+
+
+def test_struct_sizes_match_header_layout(abi):
+    assert C.sizeof(abi.pdd_node_stat) == 40
+    assert C.sizeof(abi.pdd_factor) == 32
+    assert C.sizeof(abi.pdd_fun) == 40
+    assert C.sizeof(abi.pdd_domain) == 8 + 10 * 8
+    assert C.sizeof(abi.pdd_options) == 48
+
+
+def _problem(abi, **kw):
+    p = abi.pdd_linear_problem()
+    p.domain.kind = kw.get("kind", abi.PDD_DOM_BALL)
+    p.domain.dim = kw.get("dim", 2)
+    p.domain.radius = kw.get("radius", 1.0)
+    p.sigma = kw.get("sigma", 1.0)
+    for f in (p.b[0], p.b[1], p.b[2], p.c, p.f, p.g):
+        f.poly_degree = -1
+    return p
+
+
+def _opts(abi, **kw):
+    o = abi.pdd_options()
+    o.precision = kw.get("precision", abi.PDD_FP32_STEP)
+    o.rng_layout = kw.get("layout", abi.PDD_RNG_QUAD24)
+    o.schedule = kw.get("schedule", abi.PDD_SCHED_PERSISTENT)
+    return o
+
+
+@pytest.mark.parametrize("case", ["dt", "sigma", "dim", "free", "layout", "radius", "nodes_null", "paths_neg",
+                                  "poly_deg", "factor_dim"])
+def test_invalid_linear_arguments_are_rejected_on_the_host(abi, case):
+    lib = abi.load()
+    p = _problem(abi)
+    o = _opts(abi)
+    dt = 1e-3
+    paths = (C.c_int64 * 1)(10)
+    n = 1
+    keep = []
+    if case == "dt":
+        dt = 0.0
+    elif case == "sigma":
+        p.sigma = -1.0
+    elif case == "dim":
+        p.domain.dim = 4
+    elif case == "free":
+        p.domain.kind = abi.PDD_DOM_FREE
+    elif case == "layout":
+        o.rng_layout = abi.PDD_RNG_PAIR52      # FP32 stepping needs QUAD24
+    elif case == "radius":
+        p.domain.radius = 0.0
+    elif case == "nodes_null":
+        pass                                   # nodes pointer NULL with n = 1
+    elif case == "paths_neg":
+        paths[0] = -5
+    elif case == "poly_deg":
+        p.g.poly_degree = 9
+        p.g.poly = 1
+    elif case == "factor_dim":
+        fac = (abi.pdd_factor * 1)()
+        fac[0].fn = 1
+        fac[0].dim = 2                         # only x0, x1 exist in 2-D
+        fac[0].power = 1
+        keep.append(fac)
+        p.g.n_terms = 1
+        p.g.n_factors = 1
+        p.g.factors = C.cast(fac, C.POINTER(abi.pdd_factor))
+        p.g.coef = 1
+    st = lib.pdd_mc_interface(C.byref(p), None, n, paths, dt, 0, C.byref(o), None, None)
+    assert st in (abi.PDD_ERR_INVALID_ARG, abi.PDD_ERR_UNSUPPORTED), case
+    assert len(lib.pdd_last_error()) > 0
+
+
+def test_branching_admissibility_is_checked_on_the_host(abi):
+    """Assumption 3.2: binary branching with |psi| <= 2 blows up at
+    T* = ln(psi/(psi-1))/beta = ln 2; T = 1 is rejected, T = 0.5 passes the check
+    (then fails only on the NULL points pointer)."""
+    lib = abi.load()
+    b = abi.pdd_branching_problem()
+    b.dim, b.max_segments = 1, 127
+    b.sigma, b.beta = 1.0, 1.0
+    b.alpha[2] = 1.0
+    b.q[2] = 1.0
+    b.psi_sup = 2.0
+    b.psi.poly_degree = 0
+    b.psi.poly = 1
+    o = _opts(abi)
+    b.T = 1.0
+    st = lib.pdd_branching_eval(C.byref(b), None, 1, 10, 0, C.byref(o), None, None)
+    assert st == abi.PDD_ERR_NOT_ADMISSIBLE
+    b.T = 0.5
+    st = lib.pdd_branching_eval(C.byref(b), None, 1, 10, 0, C.byref(o), None, None)
+    assert st == abi.PDD_ERR_INVALID_ARG
+    # q must be positive wherever alpha is not zero
+    b.T = 0.5
+    b.alpha[0] = 0.1
+    st = lib.pdd_branching_eval(C.byref(b), None, 1, 10, 0, C.byref(o), None, None)
+    assert st == abi.PDD_ERR_INVALID_ARG
+
+
+def test_status_strings(abi):
+    lib = abi.load()
+    for s in (0, 1, 2, -1, -2, -3, -4, -5):
+        assert len(lib.pdd_status_string(s)) > 0
+    assert lib.pdd_version() == 1

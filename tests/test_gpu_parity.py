@@ -1,0 +1,319 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+identical seeded inputs.
+
+FP64 modes must match the oracle path by path (same Philox counters) to
+1e-12 relative; FP32 stepping must agree node by node within
+4 sqrt(SE_gpu^2 + SE_oracle^2) + 1e-5.  Sizes span several work items per
+node, partial wavefronts and ragged tails."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import configs as CF
+from workloads.problem import (BranchingProblem, LinearProblem, ball, box, const_fun, factor, make_fun,
+                               zero_fun)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pdd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_03666_amd as P
+    P.library()
+    return P
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def per_path_close(gpu_phi, orc_phi, rel=1e-12):
+    g = np.asarray(gpu_phi)
+    o = np.asarray(orc_phi)
+    scale = np.maximum(1.0, np.abs(o))
+    bad = np.abs(g - o) > rel * scale
+    return int(bad.sum()), float(np.max(np.abs(g - o) / scale)) if len(g) else 0.0
+
+
+def stats_close(gpu, orc, rel=1e-12):
+    gm = gpu["mean"].cpu().numpy()
+    assert np.all(gpu["n"].cpu().numpy() == orc["n"])
+    assert np.allclose(gm, orc["mean"], rtol=rel, atol=rel)
+    assert np.allclose(gpu["m2"].cpu().numpy(), orc["m2"], rtol=1e-9, atol=1e-12)
+    assert np.all(gpu["steps"].cpu().numpy() == orc["steps"])
+    assert np.all(gpu["censored"].cpu().numpy() == orc["censored"])
+
+
+# ----------------------------------------------------------------------------- linear, FP64 per path
+def _c5_small(seed=0, n_nodes=5, deg_terms=True):
+    rng = np.random.default_rng(seed)
+    sh = CF.real_solid_harmonics_poly(7)
+    tg, tf, tc = rng.standard_normal(64), rng.standard_normal(16), 0.1 * rng.standard_normal(16)
+    tc[0] += 1.0
+    P = CF.c5_problem(tg, tf, tc, sh)
+    if deg_terms:
+        P.f = make_fun([(0.7, [factor("sin", 1, a=2.0)])], poly_degree=3, poly=P.f.poly)
+        P.c = make_fun([(0.3, [factor("cos", 0)])], poly_degree=3, poly=P.c.poly)
+        P.g = make_fun([(0.5, [factor("tanh", 0), factor("pow", 1, power=2)])], poly_degree=7, poly=P.g.poly)
+    return P, CF.c5_nodes(n_nodes)
+
+
+CASES = {
+    "c1": lambda: (CF.c1().problem, CF.c1().nodes, 1e-3),
+    "c2": lambda: (CF.c2_problem(), CF.c2_nodes()[::64], 1e-3),
+    "c5": lambda: (*_c5_small(), 2e-3),
+    "box1d": lambda: (LinearProblem(box((0.0,), (1.0,)), 1.0, [make_fun([(0.3, [])])],
+                                    make_fun([(0.5, []), (1.0, [factor("pow", 0)])]),
+                                    make_fun([(1.0, []), (1.0, [factor("pow", 0)])]),
+                                    make_fun([(1.0, [factor("exp", 0)])])), np.array([[0.2], [0.5], [0.77]]), 1e-2),
+    "ball3_c3": lambda: (CF.c3(scale=0.01)[7].problem, CF.c3(scale=0.01)[7].nodes[:6], 1e-3),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("layout", ["pair52", "quad24"])
+def test_fp64_matches_oracle_per_path(pdd, orc, case, layout):
+    P, nodes, dt = CASES[case]()
+    paths = np.array([(97 + 61 * i) % 400 + 130 for i in range(len(nodes))], np.int64)
+    log(f"fp64 per-path: case={case} layout={layout} nodes={len(nodes)} paths={paths.sum()}")
+    o = orc.walk(P, nodes, paths, dt, 7, layout=orc.PAIR52 if layout == "pair52" else orc.QUAD24, dump=True)
+    for sched, chunk in (("persistent", 100), ("graph", 0)):
+        g = pdd.mc_interface(P, nodes, paths, dt, 7, precision="fp64", layout=layout, dump=True,
+                             schedule=sched, chunk_paths=chunk)
+        torch.cuda.synchronize()
+        assert np.all(g["path_steps"].cpu().numpy() == o["path_steps"]), "exit step differs"
+        nbad, worst = per_path_close(g["phi"].cpu().numpy(), o["phi"])
+        assert nbad == 0, (nbad, worst)
+        stats_close(g, o)
+    g = pdd.mc_interface(P, nodes, paths, dt, 7, precision="fp64_plain", layout=layout, dump=True)
+    torch.cuda.synchronize()
+    assert np.all(g["path_steps"].cpu().numpy() == o["path_steps"])
+    nbad, worst = per_path_close(g["phi"].cpu().numpy(), o["phi"])
+    assert nbad == 0, (nbad, worst)
+    stats_close(g, o)
+
+
+def test_degenerate_nodes_and_budgets(pdd, orc):
+    w = CF.c1()
+    nodes = np.array([[1.2, 0.3], [0.0, 0.5], [0.5, 0.5], [0.3, 0.3], [0.5, 1e-9]])
+    paths = np.array([70, 3, 0, 1, 65], np.int64)
+    o = orc.walk(w.problem, nodes, paths, 1e-3, 3, dump=True)
+    for prec in ("fp64", "fp64_plain"):
+        g = pdd.mc_interface(w.problem, nodes, paths, 1e-3, 3, precision=prec, dump=True, schedule="persistent")
+        torch.cuda.synchronize()
+        assert np.all(g["path_steps"].cpu().numpy() == o["path_steps"])
+        assert per_path_close(g["phi"].cpu().numpy(), o["phi"])[0] == 0
+        stats_close(g, o)
+    # empty call
+    g = pdd.mc_interface(w.problem, np.zeros((0, 2)), np.zeros(0, np.int64), 1e-3, 3, precision="fp32")
+    assert g["mean"].numel() == 0
+
+
+def test_censoring_matches_oracle_and_is_reported(pdd, orc):
+    w = CF.c1()
+    nodes = w.nodes[:4]
+    paths = np.full(4, 150, np.int64)
+    o = orc.walk(w.problem, nodes, paths, 1e-3, 5, max_steps=40, dump=True)
+    pdd.query_warnings()
+    g = pdd.mc_interface(w.problem, nodes, paths, 1e-3, 5, precision="fp64", max_steps=40, dump=True,
+                         schedule="persistent")
+    torch.cuda.synchronize()
+    assert per_path_close(g["phi"].cpu().numpy(), o["phi"])[0] == 0
+    stats_close(g, o)
+    cens, _ = pdd.query_warnings()
+    assert cens == int(o["censored"].sum()) > 0
+
+
+# ----------------------------------------------------------------------------- linear, FP32
+@pytest.mark.parametrize("case", ["c1", "c2", "c5", "ball3_c3"])
+def test_fp32_statistical_parity(pdd, orc, case):
+    P, nodes, dt = CASES[case]()
+    paths = np.full(len(nodes), 3000, np.int64)
+    log(f"fp32 statistical: case={case} nodes={len(nodes)}")
+    o = orc.walk(P, nodes, paths, dt, 11, layout=orc.QUAD24, dump=True)
+    g = pdd.mc_interface(P, nodes, paths, dt, 11, precision="fp32", dump=True, schedule="persistent",
+                         chunk_paths=700)
+    torch.cuda.synchronize()
+    gm, gs = g["mean"].cpu().numpy(), g["se"].cpu().numpy()
+    bound = 4.0 * np.sqrt(gs ** 2 + o["se"] ** 2) + 1e-5
+    err = np.abs(gm - o["mean"])
+    log(f"  max |err|/bound = {np.max(err / bound):.3f}; max err {np.max(err):.2e}")
+    assert np.all(err <= bound)
+    # same uniforms: nearly every path takes the same number of steps
+    flips = np.mean(g["path_steps"].cpu().numpy() != o["path_steps"])
+    log(f"  exit-step mismatch fraction {flips:.2e}")
+    assert flips < 0.02
+
+
+def test_schedule_independence_and_determinism(pdd):
+    P, nodes, dt = CASES["c5"]()
+    paths = np.array([333, 1000, 64, 65, 700], np.int64)
+    ref = pdd.mc_interface(P, nodes, paths, dt, 3, precision="fp32", dump=True, schedule="persistent")
+    torch.cuda.synchronize()
+    for kw in (dict(chunk_paths=64), dict(chunk_paths=129, blocks_per_cu=1), dict(refill_groups=3),
+               dict(chunk_paths=4096, blocks_per_cu=4)):
+        g = pdd.mc_interface(P, nodes, paths, dt, 3, precision="fp32", dump=True, schedule="persistent", **kw)
+        torch.cuda.synchronize()
+        # identical per-path arithmetic whatever the schedule
+        assert torch.equal(g["phi"], ref["phi"]), kw
+        assert torch.equal(g["path_steps"], ref["path_steps"]), kw
+        assert np.allclose(g["mean"].cpu().numpy(), ref["mean"].cpu().numpy(), rtol=1e-13, atol=1e-15)
+    again = pdd.mc_interface(P, nodes, paths, dt, 3, precision="fp32", dump=True, schedule="persistent")
+    torch.cuda.synchronize()
+    assert torch.equal(again["mean"], ref["mean"]) and torch.equal(again["m2"], ref["m2"])
+
+
+def test_graph_replay_reads_current_coefficients(pdd):
+    P, nodes, dt = CASES["c5"]()
+    paths = np.full(len(nodes), 500, np.int64)
+    gp = torch.tensor(P.g.poly, device="cuda", dtype=torch.float64)
+    coefs = {"g_poly": gp}
+    a = pdd.mc_interface(P, nodes, paths, dt, 1, precision="fp32", schedule="graph", coefs=coefs)["mean"].clone()
+    for rep in range(3):
+        b = pdd.mc_interface(P, nodes, paths, dt, 1, precision="fp32", schedule="graph", coefs=coefs)["mean"].clone()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), rep
+    gp.mul_(2.0)   # in place: the cached graph must see the new values
+    c = pdd.mc_interface(P, nodes, paths, dt, 1, precision="fp32", schedule="graph", coefs=coefs)["mean"].clone()
+    d = pdd.mc_interface(P, nodes, paths, dt, 1, precision="fp32", schedule="persistent", coefs=coefs)["mean"]
+    torch.cuda.synchronize()
+    assert torch.equal(c, d)
+    assert not torch.equal(a, c)
+
+
+# ----------------------------------------------------------------------------- full-size sampled parity
+def test_c5_full_size_sampled_nodes(pdd, orc):
+    """The benchmark's launch configuration (4096 nodes, 1e5 paths, FP32 graph
+    schedule); 4 sampled nodes recomputed by the oracle at the same budget."""
+    w = CF.c5()
+    log("C5 full size forward (4096 x 1e5)")
+    g = pdd.mc_interface(w.problem_template, w.nodes, w.paths, w.dt, w.seed, precision="fp32", schedule="graph")
+    torch.cuda.synchronize()
+    idx = np.array([0, 1234, 2999, 4095])
+    # the oracle runs the first 1e4 paths of each sampled node on the same streams
+    o = orc.walk(w.problem_template, w.nodes[idx], np.full(4, 10000), w.dt, w.seed, layout=orc.QUAD24,
+                 node_ids=idx)
+    gm, gs = g["mean"].cpu().numpy()[idx], g["se"].cpu().numpy()[idx]
+    bound = 4.0 * np.sqrt(gs ** 2 + o["se"] ** 2) + 1e-5
+    assert np.all(np.abs(gm - o["mean"]) <= bound)
+    assert np.all(g["n"].cpu().numpy() == 100000)
+    assert int(g["censored"].sum()) == 0
+
+
+# ----------------------------------------------------------------------------- branching
+BR_CASES = {
+    "c4": lambda: (CF.c4_problem("tanh"), np.array([[-1.0, 0.0, 0.5], [0.3, 1.0, -1.0], [1.9, -2.0, 0.0]])),
+    "kpp1d": lambda: (CF.kpp_travelling_wave_problem(), np.array([[-2.0], [0.0], [1.0], [2.0]])),
+    "death": lambda: (BranchingProblem(2, 1.0, 1.0, 1.0, (0.5, 0, 0.5, 0, 0), (0.5, 0, 0.5, 0, 0),
+                                       make_fun([(0.3, []), (0.2, [factor("cos", 1)])]), 0.5),
+                      np.array([[0.0, 0.0], [1.0, -1.0]])),
+    "marked": lambda: (BranchingProblem(1, 1.0, 1.0, 0.5, (0.0586, 0.5, 0.8199, 0.0, -0.4095),
+                                        (0.25, 0.25, 0.25, 0.0, 0.25), make_fun([(0.6, [factor("tanh", 0)])]), 0.6),
+                       np.array([[0.5], [-0.5]])),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BR_CASES))
+@pytest.mark.parametrize("layout", ["pair52", "quad24"])
+def test_branching_fp64_matches_oracle_per_tree(pdd, orc, case, layout):
+    B, pts = BR_CASES[case]()
+    trees = 777
+    log(f"branching fp64 per-tree: case={case} layout={layout}")
+    o = orc.branching(B, pts, trees, 9, layout=orc.PAIR52 if layout == "pair52" else orc.QUAD24, dump=True)
+    g = pdd.branching_eval(B, pts, trees, 9, precision="fp64", layout=layout, dump=True, chunk_paths=300)
+    torch.cuda.synchronize()
+    assert np.all(g["segments"].cpu().numpy() == o["segments"])
+    nbad, worst = per_path_close(g["value"].cpu().numpy().ravel(), o["value"].ravel())
+    assert nbad == 0, (nbad, worst)
+    stats_close(g, o)
+
+
+def test_branching_deep_trees_spill_and_redraw(pdd, orc):
+    """Long horizon: stacks deeper than the LDS part spill to global memory and
+    some trees hit the segment cap and are redrawn."""
+    B = BranchingProblem(1, 1.0, 1.0, 2.5, (0, 0, 1, 0, 0), (0, 0, 1, 0, 0), const_fun(0.5), 0.5, max_segments=60)
+    pts = np.zeros((2, 1))
+    o = orc.branching(B, pts, 500, 4, dump=True)
+    assert o["redrawn"] > 0
+    g = pdd.branching_eval(B, pts, 500, 4, precision="fp64", dump=True)
+    torch.cuda.synchronize()
+    assert np.all(g["segments"].cpu().numpy() == o["segments"])
+    assert per_path_close(g["value"].cpu().numpy().ravel(), o["value"].ravel())[0] == 0
+    stats_close(g, o)
+
+
+@pytest.mark.parametrize("case", ["c4", "kpp1d", "marked"])
+def test_branching_fp32_statistical(pdd, orc, case):
+    B, pts = BR_CASES[case]()
+    o = orc.branching(B, pts, 20000, 13, layout=orc.QUAD24)
+    g = pdd.branching_eval(B, pts, 20000, 13, precision="fp32")
+    torch.cuda.synchronize()
+    gm, gs = g["mean"].cpu().numpy(), g["se"].cpu().numpy()
+    assert np.all(np.abs(gm - o["mean"]) <= 4.0 * np.sqrt(gs ** 2 + o["se"] ** 2) + 1e-5)
+
+
+# ----------------------------------------------------------------------------- adjoint
+def test_adjoint_fp64_matches_oracle(pdd, orc):
+    P, nodes = _c5_small(1, 4)
+    paths = np.array([150, 64, 201, 90], np.int64)
+    dt = 1e-2
+    w = np.array([0.5, -1.0, 2.0, 0.25])
+    o = orc.walk_adjoint(P, nodes, paths, dt, 21, w)
+    for layout in ("pair52",):
+        g = pdd.mc_adjoint(P, nodes, paths, dt, 21, w, precision="fp64", layout=layout, schedule="persistent",
+                           chunk_paths=50, with_stats=True)
+        torch.cuda.synchronize()
+        for k in ("g_coef", "g_poly", "f_coef", "f_poly", "c_coef", "c_poly"):
+            got = g[k].cpu().numpy()
+            want = o[k]
+            assert got.shape == want.shape, k
+            assert np.allclose(got, want, rtol=1e-10, atol=1e-12 * max(1.0, np.abs(want).max())), k
+        stats_close(g["stats"], o["stats"])
+
+
+def test_adjoint_fp32_matches_crn_finite_differences(pdd):
+    P, nodes = _c5_small(2, 6, deg_terms=False)
+    paths = np.full(6, 2000, np.int64)
+    dt, seed = 2e-3, 5
+    w = np.random.default_rng(1).standard_normal(6)
+    adj = pdd.mc_adjoint(P, nodes, paths, dt, seed, w, precision="fp32", schedule="persistent")
+
+    def J(name, j, h):
+        F = getattr(P, name)
+        vals = []
+        for s in (1, -1):
+            poly = F.poly.copy()
+            poly[j] += s * h
+            coefs = {name + "_poly": torch.tensor(poly, device="cuda")}
+            vals.append(float(np.dot(w, pdd.mc_interface(P, nodes, paths, dt, seed, precision="fp32",
+                                                          schedule="persistent", coefs=coefs)["mean"].cpu().numpy())))
+        return (vals[0] - vals[1]) / (2 * h)
+
+    for name, h, tol in (("g", 1.0, 2e-5), ("f", 1.0, 2e-5), ("c", 1e-2, 2e-3)):
+        for j in (0, 3, 7):
+            fd = J(name, j, h)
+            got = float(adj[name + "_poly"][j])
+            assert abs(got - fd) <= tol * max(1.0, abs(fd)), (name, j, got, fd)
+
+
+def test_autograd_function_backward(pdd):
+    P, nodes = _c5_small(3, 4, deg_terms=False)
+    paths = np.full(4, 800, np.int64)
+    sh = torch.tensor(CF.real_solid_harmonics_poly(7), device="cuda")
+    theta = torch.tensor(np.random.default_rng(0).standard_normal(64), device="cuda", requires_grad=True)
+    d = torch.tensor([0.1, 0.2, 0.3, 0.4], device="cuda", dtype=torch.float64)
+    opts = dict(precision="fp32", schedule="persistent")
+    u = pdd.PDDInterface.apply(P, nodes, paths, 2e-3, 0, opts, None, sh @ theta, None, None, None, None)
+    loss = ((u - d) ** 2).sum()
+    loss.backward()
+    w = (2.0 * (u.detach() - d)).cpu().numpy()
+    direct = pdd.mc_adjoint(P, nodes, paths, 2e-3, 0, w, **opts)["g_poly"]
+    want = sh.T @ direct
+    assert torch.allclose(theta.grad, want, rtol=1e-12, atol=1e-12)
