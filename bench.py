@@ -84,14 +84,23 @@ def run(args):
     torch.cuda.synchronize()
     log(f"bench: data ready ({time.time() - t0:.1f} s)")
 
+    from paper_1705_03666_amd import autotune
+    if args.tune:
+        t0 = time.time()
+        sched_f = autotune.tune(P, nodes, paths, w.dt, w.seed, "fp32", False, coefs, log=log)
+        sched_a = autotune.tune(P, nodes, paths, w.dt, w.seed, "fp32", True, coefs, log=log)
+        log(f"bench: autotuned in {time.time() - t0:.1f} s: forward {sched_f}, adjoint {sched_a}")
+    else:
+        sched_f = sched_a = dict(autotune.DEFAULT)
+
     grads = {}
     stats = {}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
     def step():
-        r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts)
+        r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_f)
         wgt = 2.0 * (r["mean"] - d)
-        g = pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, wgt, coefs=coefs, **opts)
+        g = pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, wgt, coefs=coefs, **opts, **sched_a)
         stats["fwd"] = r
         grads["g"] = g
         return r, g
@@ -106,10 +115,10 @@ def run(args):
     t_start = time.perf_counter()
     for i in range(args.steps):
         ev[0].record()
-        r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts)
+        r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_f)
         ev[1].record()
         wgt = 2.0 * (r["mean"] - d)
-        pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, wgt, coefs=coefs, **opts)
+        pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, wgt, coefs=coefs, **opts, **sched_a)
         ev[2].record()
         torch.cuda.synchronize()
         fwd_ms.append(ev[0].elapsed_time(ev[1]))
@@ -169,7 +178,8 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": "C5 3-D unit-ball adjoint: 4096 nodes x 1e5 paths, dt=1e-3, fwd+adjoint",
                    "nodes": n, "paths_per_node": int(paths[0]), "dt": w.dt, "seed": w.seed,
-                   "schedule": "persistent+hipGraph", "accumulation": "f64"},
+                   "schedule": "persistent+hipGraph", "accumulation": "f64",
+                   "tuned_forward": sched_f, "tuned_adjoint": sched_a},
         "forward_path_steps_per_s": fwd_ps_s,
         "adjoint_path_steps_per_s": adj_ps_s,
         "interface_nodes_per_s_at_se_1e-3": nodes_per_s,
@@ -226,6 +236,7 @@ def main():
     ap.add_argument("--plain-nodes", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--no-tune", dest="tune", action="store_false", help="use the default schedule")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 256 MiB (reference for the FETCH/WRITE counters)")
     args = ap.parse_args()

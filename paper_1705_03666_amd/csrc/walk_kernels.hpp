@@ -113,6 +113,11 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   const int wid = (int)(threadIdx.x / kWave);
   __shared__ R rec_x[ADJ ? kBlock / kWave : 1][ADJ ? kWave : 1][3];
   __shared__ R rec_y[ADJ ? kBlock / kWave : 1][ADJ ? kWave : 1];
+  // Per-item sums of the path derivatives, one private column per lane
+  // (rows: f parameters, c parameters, generic g terms).  Keeping them in LDS
+  // rather than registers leaves room for the per-path tangents.
+  constexpr int kAccRows = ADJ ? 2 * NP + NT : 1;
+  __shared__ R acc[ADJ ? kBlock / kWave : 1][kAccRows > 0 ? kAccRows : 1][ADJ ? kWave : 1];
 
   const Dom<R> D = make_dom<R>(P);
   const R dt = dt_of<R>(P);
@@ -147,14 +152,12 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
     int64_t lsteps = 0, lcens = 0;
 
     Tangents<R, NT, NM> T;
-    R dF[ADJ && NP > 0 ? NP : 1], dC[ADJ && NP > 0 ? NP : 1], dGt[ADJ && NT > 0 ? NT : 1];
     double gacc[ADJ ? kGAcc : 1];
     int nrec = 0;
     if constexpr (ADJ) {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) { T.F[j] = T.S[j] = T.A[j] = (R)0; dF[j] = dC[j] = (R)0; }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) dGt[t] = (R)0;
+      for (int j = 0; j < NP; ++j) T.F[j] = T.S[j] = T.A[j] = (R)0;
+      for (int j = 0; j < kAccRows; ++j) acc[wid][j][lane] = (R)0;
 #pragma unroll
       for (int r = 0; r < kGAcc; ++r) gacc[r] = 0.0;
     }
@@ -298,12 +301,12 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
         if constexpr (ADJ) {
 #pragma unroll
           for (int j = 0; j < NP; ++j) {
-            dF[j] += T.F[j];
-            dC[j] += -gv * Y * T.S[j] - T.A[j];
+            acc[wid][j][lane] += T.F[j];
+            acc[wid][NP + j][lane] += -gv * Y * T.S[j] - T.A[j];
           }
 #pragma unroll
           for (int t = 0; t < NT; ++t)
-            if (t < P.g.n_terms) dGt[t] += Y * term_value<R, DIM>(P.fac, P.g, t, xp);
+            if (t < P.g.n_terms) acc[wid][2 * NP + t][lane] += Y * term_value<R, DIM>(P.fac, P.g, t, xp);
           const int slot = nrec + lane_rank(fmask);
 #pragma unroll
           for (int k = 0; k < DIM; ++k) rec_x[wid][slot][k] = xp[k];
@@ -361,7 +364,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
       int col = 0;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const double v = wave_sum((double)dGt[t]);
+        const double v = wave_sum((double)acc[wid][2 * NP + t][lane]);
         if (lane == 0) row[col + t] = v;
       }
       col += NT;
@@ -374,13 +377,13 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
       col += ngm;
 #pragma unroll
       for (int j = 0; j < NP; ++j) {
-        const double v = wave_sum((double)dF[j]);
+        const double v = wave_sum((double)acc[wid][j][lane]);
         if (lane == 0) row[col + j] = v;
       }
       col += NP;
 #pragma unroll
       for (int j = 0; j < NP; ++j) {
-        const double v = wave_sum((double)dC[j]);
+        const double v = wave_sum((double)acc[wid][NP + j][lane]);
         if (lane == 0) row[col + j] = v;
       }
     }
