@@ -93,46 +93,61 @@ def run(args):
     else:
         sched_f = sched_a = dict(autotune.DEFAULT)
 
-    grads = {}
     stats = {}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
     def step():
+        # forward + adjoint in one pass: values and per-node Jacobian, then
+        # the loss gradient J^T w with w = dL/du = 2 (u - d)
+        r = pdd.mc_value_jacobian(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_a)
+        grad = (2.0 * (r["mean"] - d)) @ r["jac"]
+        return r, grad
+
+    def step_recompute():
         r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_f)
-        wgt = 2.0 * (r["mean"] - d)
-        g = pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, wgt, coefs=coefs, **opts, **sched_a)
-        stats["fwd"] = r
-        grads["g"] = g
+        ev[1].record()
+        g = pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, 2.0 * (r["mean"] - d), coefs=coefs, **opts, **sched_a)
         return r, g
 
     for i in range(args.warmup):
         step()
+        step_recompute()
         torch.cuda.synchronize()
         log(f"bench: warmup {i + 1}/{args.warmup} done")
 
-    fwd_ms, adj_ms = [], []
+    step_ms = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
         ev[0].record()
-        r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_f)
-        ev[1].record()
-        wgt = 2.0 * (r["mean"] - d)
-        pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, wgt, coefs=coefs, **opts, **sched_a)
+        r, grad = step()
+        ev[2].record()
+        torch.cuda.synchronize()
+        step_ms.append(ev[0].elapsed_time(ev[2]))
+        stats["fwd"] = r
+        log(f"bench: step {i + 1}/{args.steps}: value+jacobian+gradient {step_ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_step = wall * 1e3 / args.steps
+
+    # the path-recomputing route (forward kernel, then adjoint kernel), timed
+    # separately with the same schedule
+    fwd_ms, adj_ms = [], []
+    for i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        ev[0].record()
+        step_recompute()
         ev[2].record()
         torch.cuda.synchronize()
         fwd_ms.append(ev[0].elapsed_time(ev[1]))
         adj_ms.append(ev[1].elapsed_time(ev[2]))
-        stats["fwd"] = r
-        log(f"bench: step {i + 1}/{args.steps}: fwd {fwd_ms[-1]:.1f} ms, adj {adj_ms[-1]:.1f} ms")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    ms_step = wall * 1e3 / args.steps
+        log(f"bench: recompute route {i + 1}: forward {fwd_ms[-1]:.1f} ms, adjoint {adj_ms[-1]:.1f} ms")
     r = stats["fwd"]
     ps = float(r["steps"].sum().item())
     mean_steps = r["steps"].double() / r["n"].double()
     var = r["var"]
     fwd_s, adj_s = np.median(fwd_ms) / 1e3, np.median(adj_ms) / 1e3
+    vj_s = np.median(step_ms) / 1e3
     value = ps / (ms_step / 1e3)
 
     # interface nodes per second at SE = 1e-3: budget N_i = s_i^2 / 1e-6 paths
@@ -156,10 +171,11 @@ def run(args):
     fwd_ps_s = ps / fwd_s
     adj_ps_s = ps / adj_s
 
-    # roofline of the dominant kernel (the adjoint walk), algorithmic ops
-    dominant = "adjoint" if adj_s >= fwd_s else "forward"
-    ops = ps * (OPS_PER_PS_ADJ if dominant == "adjoint" else OPS_PER_PS_FWD)
-    dur = adj_s if dominant == "adjoint" else fwd_s
+    # roofline of the dominant kernel: the adjoint walk run by the value+Jacobian
+    # call (the call's other kernels take microseconds), algorithmic ops
+    dominant = "adjoint"
+    ops = ps * OPS_PER_PS_ADJ
+    dur = vj_s
     achieved = ops / dur / 1e12
     peak = PEAK_LANE_OPS / 1e12
 
@@ -180,8 +196,10 @@ def run(args):
                    "nodes": n, "paths_per_node": int(paths[0]), "dt": w.dt, "seed": w.seed,
                    "schedule": "persistent+hipGraph", "accumulation": "f64",
                    "tuned_forward": sched_f, "tuned_adjoint": sched_a},
+        "step": "one value+Jacobian pass (pdd_mc_value_jacobian) + J^T w",
         "forward_path_steps_per_s": fwd_ps_s,
         "adjoint_path_steps_per_s": adj_ps_s,
+        "forward_plus_recomputing_adjoint_path_steps_per_s": ps / (fwd_s + adj_s),
         "interface_nodes_per_s_at_se_1e-3": nodes_per_s,
         "plain_fp64_forward_path_steps_per_s": plain_ps_s,
         "speedup_batched_fwd_vs_plain_fp64_fwd": fwd_ps_s / plain_ps_s,

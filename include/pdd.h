@@ -208,6 +208,25 @@ pdd_status pdd_mc_adjoint(const pdd_linear_problem* problem, const double* nodes
                           const double* w_dev, const pdd_fun_grad* grads_host, pdd_node_stat* out_dev,
                           void* hip_stream);
 
+/* Value and Jacobian in one pass: the per-node statistics of pdd_mc_interface
+ * and, for every node i, the derivative of its sample mean u_i with respect to
+ * every coefficient of g, f and c (same paths, same derivative as
+ * pdd_mc_adjoint, which equals sum_i w_i * row_i).  Lets a caller form
+ * the gradient of any loss of the u_i after this single pass (e.g. J^T w with
+ * w = dL/du computed from out_dev) instead of re-simulating the paths.
+ *  jac_dev: device [n_nodes][jac_ld] FP64, overwritten; columns in the order
+ *           g.coef[n_terms], g.poly[n_mono], f.coef, f.poly, c.coef, c.poly
+ *           (pdd_param_count gives their number; jac_ld >= that count).
+ *  out_dev: device [n_nodes] pdd_node_stat (required).
+ *  Limits and errors as for pdd_mc_adjoint. */
+pdd_status pdd_mc_value_jacobian(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                                 const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
+                                 pdd_node_stat* out_dev, double* jac_dev, int64_t jac_ld, void* hip_stream);
+
+/* Number of differentiable coefficients of g, f and c (the Jacobian width);
+ * -1 if the problem is malformed. */
+int64_t pdd_param_count(const pdd_linear_problem* problem);
+
 /* Synchronizes hip_stream and reports (then clears) the censored-path and
  * redrawn-tree counters of the work enqueued since the last query:
  * PDD_WARN_CENSORED / PDD_WARN_REDRAWN if non-zero, else PDD_OK. */

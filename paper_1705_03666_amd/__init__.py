@@ -26,8 +26,8 @@ import torch
 
 from . import _abi as A
 
-__all__ = ["mc_interface", "mc_adjoint", "branching_eval", "PDDInterface", "PddError", "release_workspace",
-           "query_warnings", "library", "version"]
+__all__ = ["mc_interface", "mc_adjoint", "mc_value_jacobian", "branching_eval", "PDDInterface", "PddError",
+           "release_workspace", "query_warnings", "library", "version", "param_layout", "jacobian_blocks"]
 
 
 class PddError(RuntimeError):
@@ -255,6 +255,59 @@ def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = 
     return grads
 
 
+def param_layout(problem):
+    """(name, count) of the Jacobian column blocks, in column order."""
+    from math import comb
+    ndim = problem.domain.ndim
+    out = []
+    for name in ("g", "f", "c"):
+        F = getattr(problem, name)
+        out.append((name + "_coef", int(np.asarray(F.coef).shape[0])))
+        out.append((name + "_poly", comb(F.poly_degree + ndim, ndim) if F.poly_degree >= 0 else 0))
+    return out
+
+
+def mc_value_jacobian(problem, nodes, paths, dt: float, seed: int = 0, precision: str = "fp32",
+                      layout: Optional[str] = None, max_steps: int = 0, schedule: str = "auto", chunk_paths: int = 0,
+                      blocks_per_cu: int = 0, refill_groups: int = 0,
+                      coefs: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+    """Per-node statistics and the Jacobian d mean_i / d coefficients in one
+    pass (pdd_mc_value_jacobian).  Returns the statistics of mc_interface plus
+    `jac` [n, n_params] (column blocks in `param_layout(problem)` order)."""
+    _need_gpu()
+    keep = _Keep()
+    p = _linear(problem, keep, coefs)
+    nt = _nodes_tensor(nodes, problem.domain.ndim)
+    n = nt.shape[0]
+    ph = np.ascontiguousarray(np.asarray(paths, dtype=np.int64).reshape(-1))
+    if ph.shape[0] != n:
+        raise ValueError("paths must have one entry per node")
+    npar = int(library().pdd_param_count(C.byref(p)))
+    if npar < 0:
+        raise PddError("pdd_param_count rejected the problem")
+    raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
+    jac = torch.zeros((max(n, 1), max(npar, 1)), dtype=torch.float64, device="cuda")
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups)
+    st = library().pdd_mc_value_jacobian(C.byref(p), nt.data_ptr() if n else None, n,
+                                         ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt),
+                                         int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(), jac.data_ptr(),
+                                         max(npar, 1), _stream_handle())
+    _check(st, "pdd_mc_value_jacobian")
+    res = _stats(raw[:n])
+    res["jac"] = jac[:n, :npar]
+    res["_keep"] = keep
+    return res
+
+
+def jacobian_blocks(problem, jac: torch.Tensor) -> Dict[str, torch.Tensor]:
+    """Split Jacobian columns (or a gradient vector) into per-array blocks."""
+    out, c = {}, 0
+    for name, k in param_layout(problem):
+        out[name] = jac[..., c:c + k]
+        c += k
+    return out
+
+
 def branching_eval(problem, points, trees: int, seed: int = 0, precision: str = "fp32",
                    layout: Optional[str] = None, dump: bool = False, schedule: str = "persistent",
                    chunk_paths: int = 0, blocks_per_cu: int = 0) -> Dict[str, torch.Tensor]:
@@ -311,14 +364,28 @@ class PDDInterface(torch.autograd.Function):
     """u = PDDInterface.apply(problem, nodes, paths, dt, seed, opts,
     g_coef, g_poly, f_coef, f_poly, c_coef, c_poly): interface values,
     differentiable in the six coefficient tensors (None = take the problem's
-    own array, not differentiated).  Backward re-simulates the same paths
-    (pdd_mc_adjoint) with w = grad_u."""
+    own array, not differentiated).
+
+    opts["gradient"] selects how the backward pass is formed:
+      "recompute" (default): backward re-simulates the same paths from their
+          counters with w = grad_u (pdd_mc_adjoint); nothing per path is kept.
+      "jacobian": forward runs pdd_mc_value_jacobian, keeping the per-node
+          Jacobian (n x n_params FP64); backward is J^T grad_u (no second pass).
+    Both give the same derivative of the same discrete estimator."""
 
     @staticmethod
     def forward(ctx, problem, nodes, paths, dt, seed, opts, *coef_tensors):
         coefs = {k: v for k, v in zip(_COEF_KEYS, coef_tensors) if v is not None}
         opts = dict(opts or {})
-        r = mc_interface(problem, nodes, paths, dt, seed, coefs=coefs, **opts)
+        mode = opts.pop("gradient", "recompute")
+        if mode not in ("recompute", "jacobian"):
+            raise ValueError("opts['gradient'] must be 'recompute' or 'jacobian'")
+        ctx.jac = None
+        if mode == "jacobian" and any(ctx.needs_input_grad[6:]):
+            r = mc_value_jacobian(problem, nodes, paths, dt, seed, coefs=coefs, **opts)
+            ctx.jac = r["jac"]
+        else:
+            r = mc_interface(problem, nodes, paths, dt, seed, coefs=coefs, **opts)
         ctx.problem, ctx.nodes, ctx.paths, ctx.dt, ctx.seed, ctx.opts = problem, nodes, paths, dt, seed, opts
         ctx.present = [v is not None for v in coef_tensors]
         ctx.save_for_backward(*[v for v in coef_tensors if v is not None])
@@ -331,8 +398,11 @@ class PDDInterface(torch.autograd.Function):
         for k, present in zip(_COEF_KEYS, ctx.present):
             if present:
                 coefs[k] = saved.pop(0)
-        opts = {k: v for k, v in ctx.opts.items() if k not in ("dump",)}
-        g = mc_adjoint(ctx.problem, ctx.nodes, ctx.paths, ctx.dt, ctx.seed, grad_u.detach(), coefs=coefs, **opts)
+        if ctx.jac is not None:
+            g = jacobian_blocks(ctx.problem, grad_u.detach().to(torch.float64) @ ctx.jac)
+        else:
+            opts = {k: v for k, v in ctx.opts.items() if k not in ("dump",)}
+            g = mc_adjoint(ctx.problem, ctx.nodes, ctx.paths, ctx.dt, ctx.seed, grad_u.detach(), coefs=coefs, **opts)
         out = [None] * 6
         for i, k in enumerate(_COEF_KEYS):
             if ctx.present[i] and ctx.needs_input_grad[6 + i]:

@@ -15,8 +15,9 @@ PDD_FP64_PLAIN, PDD_FP64, PDD_FP32_STEP = 0, 1, 2
 PDD_RNG_PAIR52, PDD_RNG_QUAD24 = 0, 1
 PDD_SCHED_AUTO, PDD_SCHED_PERSISTENT, PDD_SCHED_PERSISTENT_GRAPH = 0, 1, 2
 
-EXPORTED = ["pdd_mc_interface", "pdd_branching_eval", "pdd_mc_adjoint", "pdd_query_warnings",
-            "pdd_release_workspace", "pdd_status_string", "pdd_last_error", "pdd_version"]
+EXPORTED = ["pdd_mc_interface", "pdd_branching_eval", "pdd_mc_adjoint", "pdd_mc_value_jacobian",
+            "pdd_param_count", "pdd_query_warnings", "pdd_release_workspace", "pdd_status_string", "pdd_last_error",
+            "pdd_version"]
 
 
 class pdd_domain(C.Structure):
@@ -72,6 +73,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                  C.c_double, C.c_uint64, C.POINTER(pdd_options), C.c_void_p,
                                  C.POINTER(pdd_fun_grad), C.c_void_p, C.c_void_p]
     L.pdd_mc_adjoint.restype = C.c_int
+    L.pdd_mc_value_jacobian.argtypes = [C.POINTER(pdd_linear_problem), C.c_void_p, C.c_int64,
+                                        C.POINTER(C.c_int64), C.c_double, C.c_uint64, C.POINTER(pdd_options),
+                                        C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    L.pdd_mc_value_jacobian.restype = C.c_int
+    L.pdd_param_count.argtypes = [C.POINTER(pdd_linear_problem)]
+    L.pdd_param_count.restype = C.c_int64
     L.pdd_query_warnings.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.pdd_query_warnings.restype = C.c_int
     L.pdd_release_workspace.argtypes = []

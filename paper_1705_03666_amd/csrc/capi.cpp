@@ -248,6 +248,11 @@ struct Plan {
   int32_t* d_gmap = nullptr;
   struct Scatter { int col, count; bool gmap; double* dst; };
   std::vector<Scatter> scatters;
+  // value+Jacobian mode
+  double* jac = nullptr;
+  int64_t jac_ld = 0;
+  int32_t* d_colmap = nullptr;
+  int n_jcols = 0;
 
   hipError_t enqueue(hipStream_t st) const {
     hipError_t e;
@@ -265,13 +270,18 @@ struct Plan {
     }
     if (out != nullptr)
       if ((e = launch_finalize_nodes(d_istat, d_first, n_nodes, out, ctr, st)) != hipSuccess) return e;
-    if (adjoint) {
+    if (adjoint && w != nullptr) {
       if ((e = launch_finalize_grad(d_igrad, grad_stride, grad_stride, n_items, d_slot_node, w, d_inv_n, d_colsum,
                                     st)) != hipSuccess)
         return e;
       for (const auto& s : scatters)
         if ((e = launch_scatter_add(d_colsum + s.col, s.gmap ? d_gmap : nullptr, s.count, s.dst, st)) != hipSuccess)
           return e;
+    }
+    if (adjoint && jac != nullptr && n_jcols > 0) {
+      if ((e = launch_node_jacobian(d_igrad, grad_stride, d_first, n_nodes, d_inv_n, d_colmap, n_jcols, jac, jac_ld,
+                                    st)) != hipSuccess)
+        return e;
     }
     return hipSuccess;
   }
@@ -383,7 +393,15 @@ struct LinearPlanArgs {
   bool adjoint;
   const double* w;
   const pdd_fun_grad* grads;
+  double* jac;          // value+Jacobian mode: [n_nodes][jac_ld]
+  int64_t jac_ld;
 };
+
+int64_t param_count(const pdd_linear_problem& P) {
+  const int d = P.domain.dim;
+  return (int64_t)P.g.n_terms + n_mono(d, P.g.poly_degree) + P.f.n_terms + n_mono(d, P.f.poly_degree) +
+         P.c.n_terms + n_mono(d, P.c.poly_degree);
+}
 
 pdd_status validate_linear(const LinearPlanArgs& a) {
   if (a.P == nullptr) return fail(PDD_ERR_INVALID_ARG, "problem is NULL");
@@ -423,14 +441,16 @@ pdd_status validate_linear(const LinearPlanArgs& a) {
   if (o.schedule < PDD_SCHED_AUTO || o.schedule > PDD_SCHED_PERSISTENT_GRAPH) return fail(PDD_ERR_INVALID_ARG, "unknown schedule");
   if (a.n_nodes > 0) {
     if ((s = check_device_ptr(a.nodes, "nodes_dev")) != PDD_OK) return s;
-    if (!a.adjoint || a.out) if ((s = check_device_ptr(a.out, "out_dev")) != PDD_OK) return s;
-    if (a.adjoint && (s = check_device_ptr(a.w, "w_dev")) != PDD_OK) return s;
+    if (!a.adjoint || a.out || a.jac) if ((s = check_device_ptr(a.out, "out_dev")) != PDD_OK) return s;
+    if (a.adjoint && !a.jac && (s = check_device_ptr(a.w, "w_dev")) != PDD_OK) return s;
+    if (a.jac && (s = check_device_ptr(a.jac, "jac_dev")) != PDD_OK) return s;
   }
+  if (a.jac && a.jac_ld < param_count(P)) return fail(PDD_ERR_INVALID_ARG, "jac_ld is smaller than pdd_param_count");
   if ((o.dump_phi || o.dump_steps) && a.adjoint)
     return fail(PDD_ERR_UNSUPPORTED, "per-path dumps are not produced by the adjoint");
   if (o.dump_steps && !o.dump_phi) return fail(PDD_ERR_INVALID_ARG, "dump_steps needs dump_phi");
   if (a.adjoint) {
-    if (a.grads == nullptr) return fail(PDD_ERR_INVALID_ARG, "grads_host is NULL");
+    if (a.grads == nullptr && a.jac == nullptr) return fail(PDD_ERR_INVALID_ARG, "grads_host is NULL");
     if (o.precision == PDD_FP64_PLAIN) return fail(PDD_ERR_UNSUPPORTED, "the adjoint has no plain FP64 variant; use PDD_FP64");
   }
   return PDD_OK;
@@ -469,7 +489,9 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     key_add(key, o);
     key_add(key, a.out);
     key_add(key, a.w);
-    if (a.adjoint)
+    key_add(key, a.jac);
+    key_add(key, a.jac_ld);
+    if (a.adjoint && a.grads)
       for (int k = 0; k < 3; ++k) key_add(key, a.grads[k]);
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_plans.find(key);
@@ -583,6 +605,20 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     if (ngm > 0) gmap = nested_to_graded(dim, lp.g.poly_deg);
     o_gmap = A.add(sizeof(int32_t) * std::max<size_t>(1, gmap.size()));
   }
+  // Jacobian columns (caller order) -> per-item row columns
+  std::vector<int32_t> colmap;
+  size_t o_colmap = 0;
+  if (a.jac) {
+    std::vector<int32_t> graded_to_nested(gmap.size());
+    for (size_t j = 0; j < gmap.size(); ++j) graded_to_nested[(size_t)gmap[j]] = (int32_t)j;
+    for (int t = 0; t < P.g.n_terms; ++t) colmap.push_back(t);
+    for (int m = 0; m < ngm; ++m) colmap.push_back(nt + graded_to_nested[(size_t)m]);
+    for (int t = 0; t < P.f.n_terms; ++t) colmap.push_back(nt + ngm + t);
+    for (int m = 0; m < n_mono(dim, P.f.poly_degree); ++m) colmap.push_back(nt + ngm + nt + m);
+    for (int t = 0; t < P.c.n_terms; ++t) colmap.push_back(nt + ngm + NP + t);
+    for (int m = 0; m < n_mono(dim, P.c.poly_degree); ++m) colmap.push_back(nt + ngm + NP + nt + m);
+    o_colmap = A.add(sizeof(int32_t) * std::max<size_t>(1, colmap.size()));
+  }
 
   // ---- allocate
   if (graph) {
@@ -631,6 +667,15 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     pl.d_colsum = (double*)(base + o_col);
     pl.d_gmap = (int32_t*)(base + o_gmap);
     pl.w = a.w;
+    if (a.jac) {
+      put(ups, o_colmap, colmap);
+      pl.d_colmap = (int32_t*)(base + o_colmap);
+      pl.jac = a.jac;
+      pl.jac_ld = a.jac_ld;
+      pl.n_jcols = (int)colmap.size();
+    }
+  }
+  if (a.adjoint && a.grads != nullptr && a.w != nullptr) {
     // scatter of reduced columns into the caller's arrays
     const pdd_fun_grad& gg = a.grads[0];
     const pdd_fun_grad& gf = a.grads[1];
@@ -909,7 +954,8 @@ pdd_status pdd_mc_interface(const pdd_linear_problem* problem, const double* nod
                             pdd_node_stat* out_dev, void* hip_stream) {
   try {
     if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
-    LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, false, nullptr, nullptr};
+    LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, false, nullptr, nullptr,
+                     nullptr, 0};
     return run_linear(a, (hipStream_t)hip_stream);
   } catch (const std::bad_alloc&) {
     return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
@@ -937,13 +983,36 @@ pdd_status pdd_mc_adjoint(const pdd_linear_problem* problem, const double* nodes
                           void* hip_stream) {
   try {
     if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
-    LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, true, w_dev, grads_host};
+    LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, true, w_dev, grads_host,
+                     nullptr, 0};
     return run_linear(a, (hipStream_t)hip_stream);
   } catch (const std::bad_alloc&) {
     return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
   } catch (...) {
     return fail(PDD_ERR_HIP, "unexpected exception");
   }
+}
+
+pdd_status pdd_mc_value_jacobian(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                                 const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
+                                 pdd_node_stat* out_dev, double* jac_dev, int64_t jac_ld, void* hip_stream) {
+  try {
+    if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
+    if (problem == nullptr) return fail(PDD_ERR_INVALID_ARG, "problem is NULL");
+    if (n_nodes > 0 && jac_dev == nullptr) return fail(PDD_ERR_INVALID_ARG, "jac_dev is NULL");
+    LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, true, nullptr, nullptr,
+                     jac_dev, jac_ld};
+    return run_linear(a, (hipStream_t)hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+int64_t pdd_param_count(const pdd_linear_problem* problem) {
+  if (problem == nullptr || problem->domain.dim < 1 || problem->domain.dim > 3) return -1;
+  return param_count(*problem);
 }
 
 pdd_status pdd_query_warnings(void* hip_stream, int64_t* censored_out, int64_t* redrawn_out) {

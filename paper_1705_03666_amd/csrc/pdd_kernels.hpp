@@ -69,6 +69,9 @@ hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, in
                                  unsigned long long* counters, hipStream_t st);
 hipError_t launch_finalize_grad(const double* igrad, int stride, int n_cols, int n_items, const int32_t* slot_node,
                                 const double* w, const double* inv_n, double* colsum, hipStream_t st);
+hipError_t launch_node_jacobian(const double* igrad, int stride, const int64_t* first, int64_t n_nodes,
+                                const double* inv_n, const int32_t* colmap, int n_cols, double* jac, int64_t jac_ld,
+                                hipStream_t st);
 hipError_t launch_scatter_add(const double* src, const int32_t* map, int count, double* dst, hipStream_t st);
 hipError_t launch_stage(const StageJob* jobs, int n_jobs, const int32_t* perm, double* cd, float* cf,
                         hipStream_t st);

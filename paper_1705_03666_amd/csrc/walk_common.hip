@@ -53,6 +53,20 @@ __global__ void k_finalize_grad(const double* __restrict__ igrad, int stride, in
   if (threadIdx.x == 0) colsum[col] = part[0];
 }
 
+// Per-node Jacobian: jac[i][c] = (1/N_i) * sum over the items of node i (slot
+// order) of row_s[colmap[c]].  One block per node.
+__global__ void k_node_jacobian(const double* __restrict__ igrad, int stride, const int64_t* __restrict__ first,
+                                const double* __restrict__ inv_n, const int32_t* __restrict__ colmap, int n_cols,
+                                double* __restrict__ jac, int64_t jac_ld) {
+  const int64_t i = blockIdx.x;
+  for (int c = threadIdx.x; c < n_cols; c += blockDim.x) {
+    const int src = colmap[c];
+    double acc = 0.0;
+    for (int64_t s = first[i]; s < first[i + 1]; ++s) acc += igrad[(size_t)s * stride + src];
+    jac[(size_t)i * jac_ld + c] = acc * inv_n[i];
+  }
+}
+
 // dst[map[k]] += src[k] for the gradient columns of one coefficient array.
 __global__ void k_scatter_add(const double* __restrict__ src, const int32_t* __restrict__ map, int count,
                               double* __restrict__ dst) {
@@ -105,6 +119,14 @@ hipError_t launch_finalize_grad(const double* igrad, int stride, int n_cols, int
                                 const double* w, const double* inv_n, double* colsum, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize_grad, dim3(n_cols), dim3(kBlock), 0, st, igrad, stride, n_items, slot_node, w,
                      inv_n, colsum);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_jacobian(const double* igrad, int stride, const int64_t* first, int64_t n_nodes,
+                                const double* inv_n, const int32_t* colmap, int n_cols, double* jac, int64_t jac_ld,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_node_jacobian, dim3((unsigned)n_nodes), dim3(kBlock), 0, st, igrad, stride, first, inv_n, colmap,
+                     n_cols, jac, jac_ld);
   return hipGetLastError();
 }
 

@@ -118,6 +118,9 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   // rather than registers leaves room for the per-path tangents.
   constexpr int kAccRows = ADJ ? 2 * NP + NT : 1;
   __shared__ R acc[ADJ ? kBlock / kWave : 1][kAccRows > 0 ? kAccRows : 1][ADJ ? kWave : 1];
+  // Forward: exit records (x_tau[3], Y, Z) and (path, steps | censored << 31).
+  __shared__ R frec[ADJ ? 1 : kBlock / kWave][ADJ ? 1 : kWave][5];
+  __shared__ uint32_t frec_i[ADJ ? 1 : kBlock / kWave][ADJ ? 1 : kWave][2];
 
   const Dom<R> D = make_dom<R>(P);
   const R dt = dt_of<R>(P);
@@ -154,6 +157,40 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
     Tangents<R, NT, NM> T;
     double gacc[ADJ ? kGAcc : 1];
     int nrec = 0;
+    int nfrec = 0;
+
+    // Forward exit batch: lane l takes record l, evaluates g there, and folds
+    // phi = g Y + Z into its own Welford triple (every path of the item
+    // belongs to the same node, so any lane may take any path).
+    auto flush_exits = [&]() {
+      if constexpr (!ADJ) {
+        if (nfrec == 0) return;
+        // records written by other lanes are read here and the slots are
+        // reused right after: keep these LDS accesses in program order
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nfrec) {
+          R xp[3] = {(R)0, (R)0, (R)0};
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) xp[k] = frec[wid][lane][k];
+          const R yr = frec[wid][lane][3], zr = frec[wid][lane][4];
+          const uint32_t pr = frec_i[wid][lane][0], nr = frec_i[wid][lane][1];
+          const double ph = (double)(g_value<R, DIM>(P, xp) * yr + zr);
+          wn += 1.0;
+          const double d1 = ph - wmean;
+          wmean += d1 / wn;
+          wm2 += d1 * (ph - wmean);
+          lsteps += (int64_t)(nr & 0x7FFFFFFFu);
+          lcens += (int64_t)(nr >> 31);
+          if (dump_phi != nullptr) {
+            const int64_t o = dump_off[node] + (int64_t)pr;
+            dump_phi[o] = ph;
+            if (dump_steps != nullptr) dump_steps[o] = (int64_t)(nr & 0x7FFFFFFFu);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        nfrec = 0;
+      }
+    };
     if constexpr (ADJ) {
 #pragma unroll
       for (int j = 0; j < NP; ++j) T.F[j] = T.S[j] = T.A[j] = (R)0;
@@ -168,6 +205,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
     auto flush_records = [&]() {
       if constexpr (ADJ) {
         if (nrec == 0 || P.g.poly_deg < 0) { nrec = 0; return; }
+        __builtin_amdgcn_wave_barrier();
         const bool have = lane < nrec;
         R xr[3] = {(R)0, (R)0, (R)0};
         R yr = (R)0;
@@ -197,6 +235,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           }
           xa *= xr[0];
         }
+        __builtin_amdgcn_wave_barrier();
         nrec = 0;
       }
     };
@@ -276,12 +315,30 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
         continue;
       }
 
-      // ---- exits: value, statistics, tangents
+      // ---- exits.  Forward: park (exit point, Y, Z, path, steps) in LDS and
+      // evaluate g for 64 of them at a time, one per lane.  Adjoint: the
+      // tangents need g at once, so the exiting lanes evaluate it here.
+      if constexpr (!ADJ) {
+        const int nf = __popcll(fmask);
+        if (nfrec + nf > kWave) flush_exits();
+        if (fin) {
+          R xp[3];
+          project<R, DIM>(D, X, xp);
+          const int slot = nfrec + lane_rank(fmask);
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) frec[wid][slot][k] = xp[k];
+          frec[wid][slot][3] = Y;
+          frec[wid][slot][4] = Z;
+          frec_i[wid][slot][0] = path;
+          frec_i[wid][slot][1] = n | (cens ? 0x80000000u : 0u);
+        }
+        nfrec += nf;
+      }
       if constexpr (ADJ) {
         const int nf = __popcll(fmask);
         if (nrec + nf > kWave) flush_records();
       }
-      if (fin) {
+      if (ADJ && fin) {
         R xp[3];
         project<R, DIM>(D, X, xp);
         const R gv = g_value<R, DIM>(P, xp);
@@ -345,6 +402,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
 
     // ---- item results
     if constexpr (ADJ) flush_records();
+    if constexpr (!ADJ) flush_exits();
     wave_welford(wn, wmean, wm2);
     lsteps = wave_sum(lsteps);
     lcens = wave_sum(lcens);

@@ -21,7 +21,7 @@ def abi():
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:pdd_status|const char\*|int)\s+(pdd_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:pdd_status|const char\*|int|int64_t)\s+(pdd_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_entry_points():

@@ -317,3 +317,57 @@ def test_autograd_function_backward(pdd):
     direct = pdd.mc_adjoint(P, nodes, paths, 2e-3, 0, w, **opts)["g_poly"]
     want = sh.T @ direct
     assert torch.allclose(theta.grad, want, rtol=1e-12, atol=1e-12)
+
+
+def test_value_jacobian_matches_adjoint_and_oracle(pdd, orc):
+    """One pass giving u and d u_i / d coefficients: J^T w equals the
+    path-recomputing adjoint, its rows equal the oracle's adjoint with unit
+    weights, and the statistics equal the forward pass."""
+    P, nodes = _c5_small(4, 5)
+    paths = np.array([150, 64, 201, 90, 33], np.int64)
+    dt, seed = 1e-2, 17
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-9)):
+        r = pdd.mc_value_jacobian(P, nodes, paths, dt, seed, precision=prec, schedule="persistent", chunk_paths=50)
+        w = np.array([0.5, -1.0, 2.0, 0.25, 1.5])
+        # same schedule: identical per-item sums, only the final FP64 reductions differ
+        adj = pdd.mc_adjoint(P, nodes, paths, dt, seed, w, precision=prec, schedule="persistent", chunk_paths=50)
+        g = pdd.jacobian_blocks(P, torch.tensor(w, device="cuda") @ r["jac"])
+        for k in ("g_coef", "g_poly", "f_coef", "f_poly", "c_coef", "c_poly"):
+            a, b = g[k].cpu().numpy(), adj[k].cpu().numpy()
+            assert np.allclose(a, b, rtol=tol, atol=tol * max(1.0, np.abs(b).max())), (prec, k)
+        f = pdd.mc_interface(P, nodes, paths, dt, seed, precision=prec, schedule="persistent")
+        # FP64: same values to rounding; FP32: the forward and adjoint kernels
+        # are compiled separately, so per-path values agree to FP32 rounding
+        mtol = 1e-12 if prec == "fp64" else 2e-6
+        assert np.allclose(r["mean"].cpu().numpy(), f["mean"].cpu().numpy(), rtol=mtol, atol=mtol)
+        steps_r, steps_f = r["steps"].cpu().numpy(), f["steps"].cpu().numpy()
+        if prec == "fp64":
+            assert np.all(steps_r == steps_f)
+        else:
+            assert np.all(np.abs(steps_r - steps_f) <= 0.01 * steps_f)
+    r = pdd.mc_value_jacobian(P, nodes, paths, dt, seed, precision="fp64", schedule="graph")
+    for i in (0, 3):
+        e = np.zeros(5)
+        e[i] = 1.0
+        o = orc.walk_adjoint(P, nodes, paths, dt, seed, e)
+        row = pdd.jacobian_blocks(P, r["jac"][i])
+        for k in ("g_poly", "f_poly", "c_poly", "c_coef"):
+            want = o[k]
+            assert np.allclose(row[k].cpu().numpy(), want, rtol=1e-10, atol=1e-12 * max(1.0, np.abs(want).max())), k
+
+
+def test_autograd_jacobian_mode_matches_recompute(pdd):
+    P, nodes = _c5_small(5, 4, deg_terms=False)
+    paths = np.full(4, 500, np.int64)
+    sel = torch.tensor(CF.c5_fc_selection(), device="cuda")
+    tc = torch.tensor(np.random.default_rng(2).standard_normal(16) * 0.1, device="cuda", requires_grad=True)
+    grads = []
+    for mode in ("recompute", "jacobian"):
+        tc.grad = None
+        opts = dict(precision="fp32", schedule="persistent", gradient=mode)
+        u = pdd.PDDInterface.apply(P, nodes, paths, 2e-3, 0, opts, None, None, None, None, None, sel @ tc)
+        # linear loss: identical weights in both modes (u itself comes from
+        # differently compiled FP32 kernels in the two modes)
+        (u * torch.tensor([1.0, -2.0, 0.5, 3.0], device="cuda", dtype=u.dtype)).sum().backward()
+        grads.append(tc.grad.clone())
+    assert torch.allclose(grads[0], grads[1], rtol=1e-9, atol=1e-12)
