@@ -591,7 +591,13 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   o_doff = A.add(sizeof(int64_t) * ((size_t)a.n_nodes + 1));
   // adjoint buffers
   const int NM = dfc >= 0 ? n_mono(dim, dfc) : 0;
-  const int nt = (P.c.n_terms > 0 || P.f.n_terms > 0 || P.g.n_terms > 0) ? kAdjTerms : 0;
+  // generic terms anywhere in b, c, f select the term-capable kernels; for the
+  // adjoint (terms in b, c, f or g) the rows then carry kAdjTerms term
+  // columns per function
+  bool bcf_terms = P.c.n_terms > 0 || P.f.n_terms > 0;
+  for (int k = 0; k < dim; ++k) bcf_terms = bcf_terms || P.b[k].n_terms > 0;
+  const bool terms = a.adjoint ? (bcf_terms || P.g.n_terms > 0) : bcf_terms;
+  const int nt = (a.adjoint && terms) ? kAdjTerms : 0;
   const int NP = nt + NM;
   const int ngm = lp.g.poly_deg >= 0 ? lp.g.n_mono : 0;
   size_t o_igrad = 0, o_slot = 0, o_invn = 0, o_col = 0, o_gmap = 0;
@@ -713,7 +719,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     WalkLaunch& L = pl.wl;
     L.P = &pl.lp;
     L.dfc = dfc;
-    L.nt = nt;
+    L.terms = terms;
     L.fp32 = fp32;
     L.adjoint = a.adjoint;
     const int max_blocks = tune.blocks_per_cu * device_cus();

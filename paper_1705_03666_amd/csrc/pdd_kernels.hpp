@@ -16,7 +16,8 @@ struct pdd_node_stat_dev {
 struct WalkLaunch {
   const LinearParams* P;
   int dfc;                   // -1: no polynomial part in b, c, f; else 3
-  int nt;                    // adjoint: generic-term tangent slots (0 or kAdjTerms)
+  bool terms;                // b, c, f (adjoint: or g) have generic terms; adjoint rows then carry
+                             // kAdjTerms term columns per function
   bool fp32;
   bool adjoint;
   int grid;

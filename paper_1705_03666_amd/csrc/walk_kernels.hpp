@@ -1,15 +1,16 @@
 // Feynman-Kac walk kernels (Sec. 2.2, eqs. 2.7-2.9 in the elliptic
 // pure-Dirichlet limit; Euler-Maruyama plus boundary test, Sec. 2.1).
 //
-//  k_walk<R, DIM, DFC, LAYOUT, NT, ADJ>  persistent batched kernel: every
+//  k_walk<R, DIM, DFC, LAYOUT, TERMS, ADJ>  persistent batched kernel: every
 //      wavefront pops work items (node, path range) from a device queue and
 //      runs one path per lane; a lane whose path has exited takes the next
 //      path index of the item ("refill"), so lanes stay busy while exit times
 //      vary tenfold.  R = float: FP32 stepping / transforms; R = double: FP64.
-//      With ADJ the same paths are re-simulated with pathwise tangents and the
-//      derivative of each path value with respect to the coefficients of g, f
-//      and c is accumulated per item (the exact derivative of the discrete
-//      estimator).
+//      DFC = 3: b, c, f carry a dense cubic part; TERMS: they (or g, for the
+//      adjoint) carry generic terms.  With ADJ the same paths are simulated
+//      with pathwise tangents and the derivative of each path value with
+//      respect to the coefficients of g, f and c is accumulated per item (the
+//      exact derivative of the discrete estimator).
 //  k_walk_plain<DIM, DFC, LAYOUT>  the FP64 baseline: one node per launch,
 //      one path per thread until it exits, block-level partial statistics.
 //
@@ -88,16 +89,73 @@ __device__ __forceinline__ float sdt_of<float>(const LinearParams& P) { return P
 template <>
 __device__ __forceinline__ double sdt_of<double>(const LinearParams& P) { return P.sdt; }
 
-// Per-lane tangent state of the adjoint (unused when ADJ is false).
-template <typename R, int NT, int NM>
-struct Tangents {
-  static constexpr int NP = NT + NM;
-  R F[NP > 0 ? NP : 1];   // d Z / d coef_f
-  R S[NP > 0 ? NP : 1];   // sum of c-basis * dt
-  R A[NP > 0 ? NP : 1];   // sum of f Y dt S (before the S update)
-};
+// Coefficient tables read through the constant address space compile to
+// scalar loads (the tables are not written while a walk kernel runs).  The
+// empty asm statement hides the table address from the optimiser at every
+// use, so the loads are issued next to the arithmetic that consumes them
+// rather than hoisted out of the stepping loop into scalar registers, which
+// would then spill into vector-register lanes.
+#define PDD_CONST_AS __attribute__((address_space(4)))
 
-template <typename R, int DIM, int DFC, int LAYOUT, int NT, bool ADJ>
+template <typename R>
+__device__ __forceinline__ const R PDD_CONST_AS* coef_table(const LinearParams& P);
+template <>
+__device__ __forceinline__ const float PDD_CONST_AS* coef_table<float>(const LinearParams& P) {
+  uint64_t a = (uint64_t)(uintptr_t)P.cf;
+  asm volatile("" : "+s"(a));
+  return (const float PDD_CONST_AS*)a;
+}
+template <>
+__device__ __forceinline__ const double PDD_CONST_AS* coef_table<double>(const LinearParams& P) {
+  uint64_t a = (uint64_t)(uintptr_t)P.cd;
+  asm volatile("" : "+s"(a));
+  return (const double PDD_CONST_AS*)a;
+}
+
+// Dense graded-lex polynomial: c[0] + sum_m c[m] mono[m] (mono[0] = 1).
+template <typename R, int NM>
+__device__ __forceinline__ R poly_dot(const R PDD_CONST_AS* c, const R* mono) {
+  R s = c[0];
+#pragma unroll
+  for (int m = 1; m < NM; ++m) s += c[m] * mono[m];
+  return s;
+}
+
+// b_k, c or f at X: generic terms (only when TERMS) plus the dense polynomial.
+template <typename R, int DIM, int DFC, bool TERMS>
+__device__ __forceinline__ R bcf_value(const LinearParams& P, const DevFun& F, const R* X, const R* mono) {
+  R v = (R)0;
+  if constexpr (TERMS) {
+    if (F.n_terms > 0) v = terms_sum<R, DIM>(P.fac, P.cd, P.cf, F, X);
+  }
+  if constexpr (DFC >= 0) {
+    if (F.poly_deg >= 0) v += poly_dot<R, GradedLex<DIM, DFC>::N>(coef_table<R>(P) + F.poly_off, mono);
+  }
+  return v;
+}
+
+// Persistent batched walk.  Every wavefront pops work items (node, path range)
+// from a device queue and runs one path per lane; a lane whose path has ended
+// takes the next path index of the item, so lanes stay busy while exit times
+// vary tenfold.  Ended paths are parked in LDS as exit records (X, Y, Z and,
+// for the adjoint, the tangent S) and processed 64 at a time, one record per
+// lane: projection onto the boundary, g, the path value phi = g Y + Z, the
+// FP64 Welford update and the g-part of the derivative.
+//
+// Adjoint (ADJ).  With Z_{n+1} = Z_n + f(X_n) Y_n dt, Y_{n+1} = Y_n
+// exp(-c(X_n) dt) and phi = g(X_N) Y_N + Z_N, the exact derivatives of the
+// discrete path value with respect to a coefficient theta_j of f (basis
+// function m_j) and of c are
+//   d phi / d f_j = F_j = sum_n m_j(X_n) Y_n dt,
+//   d phi / d c_j = -phi S_j + B_j,  S_j = sum_n m_j(X_n) dt,
+//                                    B_j = sum_n m_j(X_n) dt Z_{n+1},
+// (summation by parts of -g Y_N S_j(N) - sum_n f_n Y_n dt S_j(n)).  F and B
+// need no per-path reset, so each lane keeps them as running sums over all
+// the paths it runs; only S is per path and travels with the exit record.
+// At every record flush the running sums are reduced across the wavefront
+// into FP64 per-item accumulators (column ic lives in lane ic % 64, slot
+// ic / 64), so no FP32 sum spans more than about one path per lane.
+template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ>
 __global__ void __launch_bounds__(kBlock)
 k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, uint32_t* __restrict__ qhead,
        ItemStat* __restrict__ istat, double* __restrict__ igrad, int grad_stride,
@@ -106,26 +164,27 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   using NZr = Normals<R, LAYOUT>;
   using GS = GroupShape<DIM, NZr::kPerBlock>;
   constexpr int NM = GradedLex<DIM, DFC>::N;
-  constexpr int NP = NT + NM;
-  constexpr int kGAcc = (GradedLex<3, kMaxPolyG>::N + kWave - 1) / kWave;
+  constexpr int NT = (ADJ && TERMS) ? kAdjTerms : 0;
+  constexpr int NP = ADJ ? NT + NM : 0;
+  constexpr int kRecW = DIM + 2 + NP;
+  constexpr int kWaves = kBlock / kWave;
+  constexpr int kCols = ADJ ? 2 * NP + NT + GradedLex<DIM, kMaxPolyG>::N : 0;
+  constexpr int kSlots = kCols > 0 ? (kCols + kWave - 1) / kWave : 1;
 
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const int wid = (int)(threadIdx.x / kWave);
-  __shared__ R rec_x[ADJ ? kBlock / kWave : 1][ADJ ? kWave : 1][3];
-  __shared__ R rec_y[ADJ ? kBlock / kWave : 1][ADJ ? kWave : 1];
-  // Per-item sums of the path derivatives, one private column per lane
-  // (rows: f parameters, c parameters, generic g terms).  Keeping them in LDS
-  // rather than registers leaves room for the per-path tangents.
-  constexpr int kAccRows = ADJ ? 2 * NP + NT : 1;
-  __shared__ R acc[ADJ ? kBlock / kWave : 1][kAccRows > 0 ? kAccRows : 1][ADJ ? kWave : 1];
-  // Forward: exit records (x_tau[3], Y, Z) and (path, steps | censored << 31).
-  __shared__ R frec[ADJ ? 1 : kBlock / kWave][ADJ ? 1 : kWave][5];
-  __shared__ uint32_t frec_i[ADJ ? 1 : kBlock / kWave][ADJ ? 1 : kWave][2];
+  // exit records, one column per record (conflict-free lane-per-record reads)
+  __shared__ R rec[kWaves][kRecW][kWave];
+  __shared__ uint32_t rec_i[kWaves][2][kWave];   // path, steps | censored << 31
+  // FP64 per-item derivative accumulators, column ic at [ic / 64][ic % 64]
+  __shared__ double acc[ADJ ? kWaves : 1][kSlots][kWave];
 
   const Dom<R> D = make_dom<R>(P);
   const R dt = dt_of<R>(P);
   const R sdt = sdt_of<R>(P);
+  const uint32_t max_steps = (uint32_t)P.max_steps;
   const uint32_t k0 = P.key0, k1 = P.key1;
+  const int ngm = (ADJ && P.g.poly_deg >= 0) ? P.g.n_mono : 0;
 
   for (;;) {
     const uint32_t it_idx = pop_item(qhead);
@@ -139,7 +198,6 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
     for (int k = 0; k < DIM; ++k) x0[k] = to_r<R>(P.nodes[(size_t)node * DIM + k]);
     const bool node_in = inside<R, DIM>(D, x0);
 
-    // lane state
     uint32_t path = it.p0 + (uint32_t)lane;
     bool alive = (path < pend) && node_in;
     bool fin = (path < pend) && !node_in;
@@ -153,28 +211,44 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
 
     double wn = 0.0, wmean = 0.0, wm2 = 0.0;
     int64_t lsteps = 0, lcens = 0;
-
-    Tangents<R, NT, NM> T;
-    double gacc[ADJ ? kGAcc : 1];
     int nrec = 0;
-    int nfrec = 0;
 
-    // Forward exit batch: lane l takes record l, evaluates g there, and folds
-    // phi = g Y + Z into its own Welford triple (every path of the item
-    // belongs to the same node, so any lane may take any path).
-    auto flush_exits = [&]() {
-      if constexpr (!ADJ) {
-        if (nfrec == 0) return;
-        // records written by other lanes are read here and the slots are
+    R S[NP > 0 ? NP : 1], Fr[NP > 0 ? NP : 1], Br[NP > 0 ? NP : 1], Gr[NT > 0 ? NT : 1];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) S[j] = Fr[j] = Br[j] = (R)0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) Gr[t] = (R)0;
+    if constexpr (ADJ) {
+#pragma unroll
+      for (int r = 0; r < kSlots; ++r) acc[wid][r][lane] = 0.0;
+    }
+
+    // adds a wavefront total to accumulator column ic
+    auto add_col = [&](int ic, double s) {
+      if (lane == (ic & (kWave - 1))) acc[wid][ic >> 6][lane] += s;
+    };
+    auto fold = [&](R& v, int ic) {
+      add_col(ic, wave_sum((double)v));
+      v = (R)0;
+    };
+
+    auto flush = [&]() {
+      if (nrec > 0) {
+        // records written by other lanes are read here and their slots are
         // reused right after: keep these LDS accesses in program order
         __builtin_amdgcn_wave_barrier();
-        if (lane < nfrec) {
-          R xp[3] = {(R)0, (R)0, (R)0};
+        R xr[3] = {(R)0, (R)0, (R)0};
+        R yr = (R)0;
+        if (lane < nrec) {
+          R xe[DIM];
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) xp[k] = frec[wid][lane][k];
-          const R yr = frec[wid][lane][3], zr = frec[wid][lane][4];
-          const uint32_t pr = frec_i[wid][lane][0], nr = frec_i[wid][lane][1];
-          const double ph = (double)(g_value<R, DIM>(P, xp) * yr + zr);
+          for (int k = 0; k < DIM; ++k) xe[k] = rec[wid][k][lane];
+          const R y = rec[wid][DIM][lane], z = rec[wid][DIM + 1][lane];
+          const uint32_t pr = rec_i[wid][0][lane], nr = rec_i[wid][1][lane];
+          project<R, DIM>(D, xe, xr);
+          const R gv = g_value<R, DIM>(P, xr);
+          const R phi = gv * y + z;
+          const double ph = (double)phi;
           wn += 1.0;
           const double d1 = ph - wmean;
           wmean += d1 / wn;
@@ -186,57 +260,57 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
             dump_phi[o] = ph;
             if (dump_steps != nullptr) dump_steps[o] = (int64_t)(nr & 0x7FFFFFFFu);
           }
-        }
-        __builtin_amdgcn_wave_barrier();
-        nfrec = 0;
-      }
-    };
-    if constexpr (ADJ) {
+          if constexpr (ADJ) {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) T.F[j] = T.S[j] = T.A[j] = (R)0;
-      for (int j = 0; j < kAccRows; ++j) acc[wid][j][lane] = (R)0;
+            for (int j = 0; j < NP; ++j) Br[j] -= phi * rec[wid][DIM + 2 + j][lane];
 #pragma unroll
-      for (int r = 0; r < kGAcc; ++r) gacc[r] = 0.0;
-    }
-
-    // g-polynomial gradient: the sum over exited paths of Y * monomial(X_tau),
-    // batched through LDS records (one record per lane), reduced monomial by
-    // monomial; lane (j % 64) keeps nested-order monomial j.
-    auto flush_records = [&]() {
-      if constexpr (ADJ) {
-        if (nrec == 0 || P.g.poly_deg < 0) { nrec = 0; return; }
-        __builtin_amdgcn_wave_barrier();
-        const bool have = lane < nrec;
-        R xr[3] = {(R)0, (R)0, (R)0};
-        R yr = (R)0;
-        if (have) {
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) xr[k] = rec_x[wid][lane][k];
-          yr = rec_y[wid][lane];
-        }
-        const int deg = P.g.poly_deg;
-        int idx = 0;
-        R xa = yr;
-        for (int a = 0; a <= deg; ++a) {
-          R xb = xa;
-          for (int b = 0; b <= (DIM >= 2 ? deg - a : 0); ++b) {
-            R xc = xb;
-            for (int c = 0; c <= (DIM >= 3 ? deg - a - b : 0); ++c) {
-              const double s = wave_sum((double)xc);
-              const int slot = idx / kWave;
-              if (lane == (idx & (kWave - 1))) {
-#pragma unroll
-                for (int r = 0; r < kGAcc; ++r) if (r == slot) gacc[r] += s;
-              }
-              ++idx;
-              if (DIM >= 3) xc *= xr[2];
-            }
-            if (DIM >= 2) xb *= xr[1];
+            for (int t = 0; t < NT; ++t)
+              if (t < P.g.n_terms) Gr[t] += y * term_value<R, DIM>(P.fac, P.g, t, xr);
+            yr = y;
           }
-          xa *= xr[0];
+        }
+        if constexpr (ADJ) {
+          // g polynomial: sum over the records of Y monomial(X_tau), nested
+          // order, one wavefront sum per monomial
+          if (P.g.poly_deg >= 0) {
+            const int deg = P.g.poly_deg;
+            int ic = 2 * NP + NT;
+            R xa = yr;
+            for (int a = 0; a <= deg; ++a) {
+              R xb = xa;
+              for (int b = 0; b <= (DIM >= 2 ? deg - a : 0); ++b) {
+                R xc = xb;
+                for (int c = 0; c <= (DIM >= 3 ? deg - a - b : 0); ++c) {
+                  add_col(ic, wave_sum((double)xc));
+                  ++ic;
+                  if (DIM >= 3) xc *= xr[2];
+                }
+                if (DIM >= 2) xb *= xr[1];
+              }
+              xa *= xr[0];
+            }
+          }
         }
         __builtin_amdgcn_wave_barrier();
         nrec = 0;
+      }
+      if constexpr (ADJ) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if (t < P.f.n_terms) fold(Fr[t], t);
+          if (t < P.c.n_terms) fold(Br[t], NP + t);
+          if (t < P.g.n_terms) fold(Gr[t], 2 * NP + t);
+        }
+        if constexpr (NM > 0) {
+          if (P.f.poly_deg >= 0) {
+#pragma unroll
+            for (int m = 0; m < NM; ++m) fold(Fr[NT + m], NT + m);
+          }
+          if (P.c.poly_deg >= 0) {
+#pragma unroll
+            for (int m = 0; m < NM; ++m) fold(Br[NT + m], NP + NT + m);
+          }
+        }
       }
     };
 
@@ -250,132 +324,93 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
 #pragma unroll
           for (int b = 0; b < GS::NB; ++b) {
             const uint64_t blk = blk0 + (uint64_t)b;
-            NZr::gen((uint32_t)blk, (uint32_t)((blk >> 32) & 0xFFFFFFu), path, (uint32_t)node, k0, k1,
+            // opaque copies of the key: the round keys are rebuilt with
+            // scalar adds at each use instead of living in registers
+            uint32_t ka = k0, kb = k1;
+            asm volatile("" : "+s"(ka), "+s"(kb));
+            NZr::gen((uint32_t)blk, (uint32_t)((blk >> 32) & 0xFFFFFFu), path, (uint32_t)node, ka, kb,
                      &z[b * NZr::kPerBlock]);
           }
         }
 #pragma unroll
         for (int s = 0; s < GS::G; ++s) {
-          if (alive) {
-            if ((int64_t)n >= P.max_steps) {
+          if (alive && n < max_steps) {
+            R mono[NM > 0 ? NM : 1];
+            if constexpr (DFC >= 0) monomials<R, DIM, DFC>(X, mono);
+            const R fv = bcf_value<R, DIM, DFC, TERMS>(P, P.f, X, mono);
+            const R cv = bcf_value<R, DIM, DFC, TERMS>(P, P.c, X, mono);
+            if constexpr (ADJ) {
+              const R Ydt = Y * dt;
+#pragma unroll
+              for (int t = 0; t < NT; ++t)
+                if (t < P.f.n_terms) Fr[t] += term_value<R, DIM>(P.fac, P.f, t, X) * Ydt;
+              if constexpr (NM > 0) {
+                if (P.f.poly_deg >= 0) {
+#pragma unroll
+                  for (int m = 0; m < NM; ++m) Fr[NT + m] += mono[m] * Ydt;
+                }
+              }
+            }
+            Z = Z + fv * Y * dt;
+            if constexpr (ADJ) {
+              const R Zdt = Z * dt;
+#pragma unroll
+              for (int t = 0; t < NT; ++t) {
+                if (t < P.c.n_terms) {
+                  const R e = term_value<R, DIM>(P.fac, P.c, t, X) * dt;
+                  S[t] += e;
+                  Br[t] += e * Z;
+                }
+              }
+              if constexpr (NM > 0) {
+                if (P.c.poly_deg >= 0) {
+#pragma unroll
+                  for (int m = 0; m < NM; ++m) {
+                    S[NT + m] += mono[m] * dt;
+                    Br[NT + m] += mono[m] * Zdt;
+                  }
+                }
+              }
+            }
+            Y = Y * fexp(-cv * dt);
+            R bv[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) bv[k] = bcf_value<R, DIM, DFC, TERMS>(P, P.b[k], X, mono);
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) X[k] = X[k] + bv[k] * dt + sdt * z[s * DIM + k];
+            ++n;
+            if (!inside<R, DIM>(D, X)) {
               alive = false;
               fin = true;
-              cens = true;
-            } else {
-              BCF<R, DIM, DFC> e;
-              if constexpr (DFC >= 0) monomials<R, DIM, DFC>(X, e.mono);
-              const R fv = fun_value<R, DIM, DFC>(P, P.f, X, e.mono);
-              const R cv = fun_value<R, DIM, DFC>(P, P.c, X, e.mono);
-              if constexpr (ADJ) {
-                const R fYdt = fv * Y * dt;
-                const R Ydt = Y * dt;
-                // generic terms of c and f, then their polynomial parts
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                  if (t < P.c.n_terms) {
-                    T.A[t] += fYdt * T.S[t];
-                    T.S[t] += term_value<R, DIM>(P.fac, P.c, t, X) * dt;
-                  }
-                  if (t < P.f.n_terms) T.F[t] += term_value<R, DIM>(P.fac, P.f, t, X) * Ydt;
-                }
-                if constexpr (DFC >= 0) {
-                  if (P.c.poly_deg >= 0) {
-#pragma unroll
-                    for (int m = 0; m < NM; ++m) {
-                      T.A[NT + m] += fYdt * T.S[NT + m];
-                      T.S[NT + m] += e.mono[m] * dt;
-                    }
-                  }
-                  if (P.f.poly_deg >= 0) {
-#pragma unroll
-                    for (int m = 0; m < NM; ++m) T.F[NT + m] += e.mono[m] * Ydt;
-                  }
-                }
-              }
-              Z = Z + fv * Y * dt;
-              Y = Y * fexp(-cv * dt);
-              R bv[DIM];
-#pragma unroll
-              for (int k = 0; k < DIM; ++k) bv[k] = fun_value<R, DIM, DFC>(P, P.b[k], X, e.mono);
-#pragma unroll
-              for (int k = 0; k < DIM; ++k) X[k] = X[k] + bv[k] * dt + sdt * z[s * DIM + k];
-              ++n;
-              if (!inside<R, DIM>(D, X)) {
-                alive = false;
-                fin = true;
-              }
             }
           }
         }
       }
+      if (alive && n >= max_steps) {
+        alive = false;
+        fin = true;
+        cens = true;
+      }
 
+      // ---- park ended paths in LDS, refill their lanes with the item's next paths
       const uint64_t fmask = ballot(fin);
-      if (fmask == 0) {
-        if (!__any(alive)) break;
-        continue;
-      }
-
-      // ---- exits.  Forward: park (exit point, Y, Z, path, steps) in LDS and
-      // evaluate g for 64 of them at a time, one per lane.  Adjoint: the
-      // tangents need g at once, so the exiting lanes evaluate it here.
-      if constexpr (!ADJ) {
+      if (fmask != 0) {
         const int nf = __popcll(fmask);
-        if (nfrec + nf > kWave) flush_exits();
+        if (nrec + nf > kWave) flush();
         if (fin) {
-          R xp[3];
-          project<R, DIM>(D, X, xp);
-          const int slot = nfrec + lane_rank(fmask);
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) frec[wid][slot][k] = xp[k];
-          frec[wid][slot][3] = Y;
-          frec[wid][slot][4] = Z;
-          frec_i[wid][slot][0] = path;
-          frec_i[wid][slot][1] = n | (cens ? 0x80000000u : 0u);
-        }
-        nfrec += nf;
-      }
-      if constexpr (ADJ) {
-        const int nf = __popcll(fmask);
-        if (nrec + nf > kWave) flush_records();
-      }
-      if (ADJ && fin) {
-        R xp[3];
-        project<R, DIM>(D, X, xp);
-        const R gv = g_value<R, DIM>(P, xp);
-        const R phi = gv * Y + Z;
-        const double ph = (double)phi;
-        wn += 1.0;
-        const double d1 = ph - wmean;
-        wmean += d1 / wn;
-        wm2 += d1 * (ph - wmean);
-        lsteps += (int64_t)n;
-        lcens += cens ? 1 : 0;
-        if (dump_phi != nullptr) {
-          const int64_t o = dump_off[node] + (int64_t)path;
-          dump_phi[o] = ph;
-          if (dump_steps != nullptr) dump_steps[o] = (int64_t)n;
-        }
-        if constexpr (ADJ) {
-#pragma unroll
-          for (int j = 0; j < NP; ++j) {
-            acc[wid][j][lane] += T.F[j];
-            acc[wid][NP + j][lane] += -gv * Y * T.S[j] - T.A[j];
-          }
-#pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (t < P.g.n_terms) acc[wid][2 * NP + t][lane] += Y * term_value<R, DIM>(P.fac, P.g, t, xp);
           const int slot = nrec + lane_rank(fmask);
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) rec_x[wid][slot][k] = xp[k];
-          rec_y[wid][slot] = Y;
+          for (int k = 0; k < DIM; ++k) rec[wid][k][slot] = X[k];
+          rec[wid][DIM][slot] = Y;
+          rec[wid][DIM + 1][slot] = Z;
+#pragma unroll
+          for (int j = 0; j < NP; ++j) rec[wid][DIM + 2 + j][slot] = S[j];
+          rec_i[wid][0][slot] = path;
+          rec_i[wid][1][slot] = n | (cens ? 0x80000000u : 0u);
         }
-      }
-      if constexpr (ADJ) nrec += __popcll(fmask);
-
-      // ---- refill finished lanes with the next paths of the item
-      {
+        nrec += nf;
         const uint32_t np = cursor + (uint32_t)lane_rank(fmask);
-        cursor += (uint32_t)__popcll(fmask);
+        cursor += (uint32_t)nf;
         if (fin) {
           fin = false;
           cens = false;
@@ -388,10 +423,8 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
             n = 0;
             alive = node_in;
             fin = !node_in;
-            if constexpr (ADJ) {
 #pragma unroll
-              for (int j = 0; j < NP; ++j) T.F[j] = T.S[j] = T.A[j] = (R)0;
-            }
+            for (int j = 0; j < NP; ++j) S[j] = (R)0;
           } else {
             path = pend;
           }
@@ -401,8 +434,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
     }
 
     // ---- item results
-    if constexpr (ADJ) flush_records();
-    if constexpr (!ADJ) flush_exits();
+    flush();
     wave_welford(wn, wmean, wm2);
     lsteps = wave_sum(lsteps);
     lcens = wave_sum(lcens);
@@ -417,32 +449,14 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
       istat[it.slot] = st;
     }
     if constexpr (ADJ) {
+      // row layout: [g terms NT | g poly nested ngm | f NP | c NP];
+      // accumulator column ic: [f NP | c NP | g terms NT | g poly ngm]
       double* row = igrad + (size_t)it.slot * (size_t)grad_stride;
-      // row layout: [g terms NT | g poly nested (grad_stride budget) | f NP | c NP]
-      int col = 0;
+      const int ncols = 2 * NP + NT + ngm;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const double v = wave_sum((double)acc[wid][2 * NP + t][lane]);
-        if (lane == 0) row[col + t] = v;
-      }
-      col += NT;
-      const int ngm = P.g.poly_deg >= 0 ? P.g.n_mono : 0;
-#pragma unroll
-      for (int r = 0; r < kGAcc; ++r) {
-        const int j = r * kWave + lane;
-        if (j < ngm) row[col + j] = gacc[r];
-      }
-      col += ngm;
-#pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        const double v = wave_sum((double)acc[wid][j][lane]);
-        if (lane == 0) row[col + j] = v;
-      }
-      col += NP;
-#pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        const double v = wave_sum((double)acc[wid][NP + j][lane]);
-        if (lane == 0) row[col + j] = v;
+      for (int r = 0; r < kSlots; ++r) {
+        const int ic = r * kWave + lane;
+        if (ic < ncols) row[ic < 2 * NP ? NT + ngm + ic : ic - 2 * NP] = acc[wid][r][lane];
       }
     }
   }
@@ -537,6 +551,35 @@ k_walk_plain(const LinearParams P, int node, uint32_t n_paths, ItemStat* __restr
     r.mean = m; r.m2 = q; r.n = (int64_t)n; r.steps = st; r.censored = ce; r.redrawn = 0;
     bstat[blockIdx.x] = r;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Launch of one k_walk instantiation, dispatched on dimension and on whether
+// b, c, f have a polynomial part.
+template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ>
+static hipError_t launch_walk_t(const WalkLaunch& L, hipStream_t st) {
+  hipLaunchKernelGGL((k_walk<R, DIM, DFC, LAYOUT, TERMS, ADJ>), dim3(L.grid), dim3(kBlock), 0, st, *L.P, L.items,
+                     L.n_items, L.qhead, L.istat, L.igrad, L.grad_stride, L.dump_phi, L.dump_steps, L.dump_off,
+                     L.refill_groups);
+  return hipGetLastError();
+}
+
+template <typename R, int LAYOUT, bool TERMS, bool ADJ>
+static hipError_t launch_walk_dim(const WalkLaunch& L, hipStream_t st) {
+  const bool poly = L.dfc >= 0;
+  switch (L.P->dim) {
+    case 1:
+      return poly ? launch_walk_t<R, 1, 3, LAYOUT, TERMS, ADJ>(L, st) : launch_walk_t<R, 1, -1, LAYOUT, TERMS, ADJ>(L, st);
+    case 2:
+      return poly ? launch_walk_t<R, 2, 3, LAYOUT, TERMS, ADJ>(L, st) : launch_walk_t<R, 2, -1, LAYOUT, TERMS, ADJ>(L, st);
+    default:
+      return poly ? launch_walk_t<R, 3, 3, LAYOUT, TERMS, ADJ>(L, st) : launch_walk_t<R, 3, -1, LAYOUT, TERMS, ADJ>(L, st);
+  }
+}
+
+template <typename R, int LAYOUT, bool ADJ>
+static hipError_t launch_walk_terms(const WalkLaunch& L, hipStream_t st) {
+  return L.terms ? launch_walk_dim<R, LAYOUT, true, ADJ>(L, st) : launch_walk_dim<R, LAYOUT, false, ADJ>(L, st);
 }
 
 }  // namespace pdd
