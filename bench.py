@@ -32,26 +32,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 compute units, 64 lanes each issue one VALU op per clock at 2.4 GHz
-PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# MI355X published FP32 vector peak 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes x
+# 2.4 GHz x 2 flops per FMA; one VALU lane operation (FMA, multiply, add,
+# integer op, conversion, transcendental) is counted as one op.
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# Algorithmic VALU lane-ops per path-step of the C5 walk (see the design notes
-# for the count): Philox4x32-10 = 10 rounds x (2 x 32x32->64 products at
-# quarter rate (8 slots) + 2 three-input xors) = 100 slots per block of 4
-# uniforms; QUAD24 + Box-Muller per pair = 2 conversions + log2, sqrt, sin,
-# cos at quarter rate (16) + 4 multiplies = 22.  A 3-D step uses 3/4 block and
-# 1.5 pairs: 75 + 33 = 108.  Then 20 cubic monomials (16 multiplies), f and c
-# (40 FMA), killing factor exp (1 multiply + exp2 at 4 = 5), Z/Y update (3),
-# X update (3 FMA), ball exit test (3 sub + 3 FMA + compare = 7): 74.
-# Forward: 182 per path-step.  Adjoint adds 3 x 20 tangent FMAs (F, S, A)
-# and two products (Y dt, f Y dt): 62, so 244 per path-step.
-OPS_PER_PS_FWD = 182.0
-OPS_PER_PS_ADJ = 244.0
+# Algorithmic VALU lane-ops per path-step of the C5 walk (3-D ball, b = 0,
+# cubic c and f, QUAD24 Gaussians); each op is one VALU lane operation:
+#   Philox4x32-10 block: 10 rounds x (2 32x32->64 products + 4 xors) + 2
+#     counter ops = 62, x 3/4 block per step                          46.5
+#   QUAD24 uniforms: 4 words x (shift, convert, fma) = 12, x 3/4         9
+#   Box-Muller pair: log2, mul, sqrt, sin, cos, 2 mul = 7, x 1.5        10.5
+#   cubic monomials of X                                                16
+#   f and c: 2 x 19 FMA                                                 38
+#   Z += f Y dt (2), Y *= exp2(-c dt log2 e) (4)                          6
+#   X += sigma sqrt(dt) z                                                3
+#   ball exit test: 3 sub, mul, 2 fma, compare                           7
+#   step count and cap                                                   2
+# forward: 138.  The adjoint adds Y dt, Z dt and 3 x 20 tangent FMAs
+# (F += m Y dt, S += m dt, B += m Z dt): 200.
+OPS_PER_PS_FWD = 138.0
+OPS_PER_PS_ADJ = 200.0
 
 
 def run(args):
@@ -96,10 +102,16 @@ def run(args):
     stats = {}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
+    ev_vj = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
     def step():
         # forward + adjoint in one pass: values and per-node Jacobian, then
-        # the loss gradient J^T w with w = dL/du = 2 (u - d)
+        # the loss gradient J^T w with w = dL/du = 2 (u - d).  The library
+        # launches on torch's current stream, so these events bracket the
+        # value+Jacobian graph (walk kernel + its small reductions).
+        ev_vj[0].record()
         r = pdd.mc_value_jacobian(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_a)
+        ev_vj[1].record()
         grad = (2.0 * (r["mean"] - d)) @ r["jac"]
         return r, grad
 
@@ -115,7 +127,7 @@ def run(args):
         torch.cuda.synchronize()
         log(f"bench: warmup {i + 1}/{args.warmup} done")
 
-    step_ms = []
+    step_ms, vj_ms = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -124,6 +136,7 @@ def run(args):
         ev[2].record()
         torch.cuda.synchronize()
         step_ms.append(ev[0].elapsed_time(ev[2]))
+        vj_ms.append(ev_vj[0].elapsed_time(ev_vj[1]))
         stats["fwd"] = r
         log(f"bench: step {i + 1}/{args.steps}: value+jacobian+gradient {step_ms[-1]:.1f} ms")
     torch.cuda.synchronize()
@@ -147,7 +160,6 @@ def run(args):
     mean_steps = r["steps"].double() / r["n"].double()
     var = r["var"]
     fwd_s, adj_s = np.median(fwd_ms) / 1e3, np.median(adj_ms) / 1e3
-    vj_s = np.median(step_ms) / 1e3
     value = ps / (ms_step / 1e3)
 
     # interface nodes per second at SE = 1e-3: budget N_i = s_i^2 / 1e-6 paths
@@ -175,7 +187,7 @@ def run(args):
     # call (the call's other kernels take microseconds), algorithmic ops
     dominant = "adjoint"
     ops = ps * OPS_PER_PS_ADJ
-    dur = vj_s
+    dur = np.median(vj_ms) / 1e3
     achieved = ops / dur / 1e12
     peak = PEAK_LANE_OPS / 1e12
 
@@ -205,7 +217,7 @@ def run(args):
         "speedup_batched_fwd_vs_plain_fp64_fwd": fwd_ps_s / plain_ps_s,
         "mean_steps_per_path": float(mean_steps.mean().item()),
         "roofline": {"bound": "alu", "kernel": f"k_walk ({dominant}, FP32, DIM 3)", "achieved": achieved,
-                     "peak": peak, "unit": "Tlane-op/s", "frac": achieved / peak, "traffic": None,
+                     "peak": peak, "unit": "Top/s", "frac": achieved / peak, "traffic": None,
                      "ops_per_path_step": OPS_PER_PS_ADJ if dominant == "adjoint" else OPS_PER_PS_FWD,
                      "launch_ms": dur * 1e3},
     }

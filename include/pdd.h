@@ -153,7 +153,9 @@ typedef struct {
   double* dump_phi;       /* device, optional [sum(paths)]: per-path value, node-major */
   int64_t* dump_steps;    /* device, optional [sum(paths)]: per-path step (segment) count */
   int32_t schedule;       /* pdd_schedule */
-  int32_t chunk_paths;    /* paths per work item; 0 = autotuned/default */
+  int32_t chunk_paths;    /* paths per large work item (about the last eighth of each node's paths
+                             goes into items of chunk_paths/8, at least 256, queued last);
+                             0 = autotuned/default */
   int32_t blocks_per_cu;  /* persistent grid size per compute unit; 0 = autotuned/default */
   int32_t refill_groups;  /* step groups between lane refills; 0 = autotuned/default (1) */
 } pdd_options;

@@ -349,30 +349,48 @@ struct Items {
   std::vector<int32_t> slot_node; // per slot: node
 };
 
+// Work items, guided sizes.  A node's paths are cut into items of `chunk`
+// paths, except about its last eighth, which is cut into items of chunk / 8
+// (at least 256) queued after every large item.  While an item's last paths
+// finish, the lanes that ran its earlier paths idle; large items make that
+// rare, and the small items at the end of the queue even out the finishing
+// times of the wavefronts.  Slots stay node-major (a node's items are
+// consecutive), so per-node reductions run in a fixed order.  Within each
+// size class the queue is ordered longest first by `cost` when given.
 Items make_items(int64_t n_nodes, const int64_t* counts, int64_t count_all, int chunk, const std::vector<double>& cost) {
   Items r;
   r.first.resize((size_t)n_nodes + 1);
+  const int64_t big = std::max(1, chunk);
+  const int64_t small = std::max<int64_t>(std::min<int64_t>(256, big), big / 8);
   std::vector<WorkItem> slots;
+  std::vector<char> is_small;
   for (int64_t i = 0; i < n_nodes; ++i) {
     r.first[(size_t)i] = (int64_t)slots.size();
     const int64_t N = counts ? counts[i] : count_all;
-    for (int64_t p0 = 0; p0 < N; p0 += chunk) {
+    const int64_t n_big = N > big ? (N - N / 8) / big : 0;
+    int64_t p0 = 0;
+    auto push = [&](int64_t cnt, bool sm) {
       WorkItem w;
       w.node = (int32_t)i;
       w.p0 = (uint32_t)p0;
-      w.count = (uint32_t)std::min<int64_t>(chunk, N - p0);
+      w.count = (uint32_t)cnt;
       w.slot = (int32_t)slots.size();
       slots.push_back(w);
+      is_small.push_back(sm ? 1 : 0);
       r.slot_node.push_back((int32_t)i);
-    }
+      p0 += cnt;
+    };
+    for (int64_t b = 0; b < n_big; ++b) push(big, false);
+    while (p0 < N) push(std::min<int64_t>(small, N - p0), true);
   }
   r.first[(size_t)n_nodes] = (int64_t)slots.size();
   r.q = slots;
-  if (!cost.empty()) {
-    std::stable_sort(r.q.begin(), r.q.end(), [&](const WorkItem& a, const WorkItem& b) {
-      return cost[(size_t)a.node] * a.count > cost[(size_t)b.node] * b.count;
-    });
-  }
+  std::stable_sort(r.q.begin(), r.q.end(), [&](const WorkItem& a, const WorkItem& b) {
+    const char sa = is_small[(size_t)a.slot], sb = is_small[(size_t)b.slot];
+    if (sa != sb) return sa < sb;
+    if (cost.empty()) return false;
+    return cost[(size_t)a.node] * a.count > cost[(size_t)b.node] * b.count;
+  });
   return r;
 }
 

@@ -155,8 +155,14 @@ __device__ __forceinline__ R bcf_value(const LinearParams& P, const DevFun& F, c
 // At every record flush the running sums are reduced across the wavefront
 // into FP64 per-item accumulators (column ic lives in lane ic % 64, slot
 // ic / 64), so no FP32 sum spans more than about one path per lane.
+// Occupancy request: the FP32 kernels without generic terms fit in 128 VGPRs
+// (four waves per SIMD), those with terms in 256; the FP64 kernels (parity
+// and baseline use) are left unconstrained.
+template <typename R, bool TERMS>
+constexpr int walk_min_waves() { return sizeof(R) == 4 ? (TERMS ? 2 : 4) : 1; }
+
 template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, (walk_min_waves<R, TERMS>()))
 k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, uint32_t* __restrict__ qhead,
        ItemStat* __restrict__ istat, double* __restrict__ igrad, int grad_stride,
        double* __restrict__ dump_phi, int64_t* __restrict__ dump_steps, const int64_t* __restrict__ dump_off,
