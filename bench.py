@@ -162,24 +162,42 @@ def run(args):
     fwd_s, adj_s = np.median(fwd_ms) / 1e3, np.median(adj_ms) / 1e3
     value = ps / (ms_step / 1e3)
 
-    # interface nodes per second at SE = 1e-3: budget N_i = s_i^2 / 1e-6 paths
-    # at the measured mean steps per path, run at the measured fwd+adj rate
-    need_ps = float((var / 1e-6 * mean_steps).sum().item())
-    nodes_per_s = n / (need_ps / value)
+    # ---- interface nodes per second at a standard error of 1e-3 (SE-target
+    # mode): a pilot of 1e3 paths per node estimates s_i, then each node runs
+    # N_i = clamp(ceil(s_i^2 / 1e-6), 1e3, 1e7) paths (paths 0..N_i-1, so the
+    # pilot's paths are part of the final estimate) through the value+Jacobian
+    # pass.  Batched FP32 on `se_nodes` nodes; the plain FP64 one-node-per-
+    # launch forward+adjoint on an evenly spaced subset of them.
+    def se_target(idx, precision, extra):
+        sub = nodes[torch.as_tensor(idx, device=dev)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pilot = pdd.mc_interface(P, sub, np.full(len(idx), 1000, np.int64), w.dt, w.seed, precision=precision,
+                                 coefs=coefs, **extra)
+        s2 = (pilot["var"]).cpu().numpy()
+        budget = np.clip(np.ceil(s2 / 1e-6), 1e3, 1e7).astype(np.int64)
+        res = pdd.mc_value_jacobian(P, sub, budget, w.dt, w.seed, precision=precision, coefs=coefs, **extra)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        se = torch.sqrt(res["var"] / res["n"].double())
+        return el, budget, res, float(se.max().item())
 
-    # plain FP64 one-node-per-launch forward on a node sample (same paths)
-    k = min(args.plain_nodes, n)
-    idx = np.linspace(0, n - 1, k).round().astype(int)
-    sub_nodes = nodes[torch.tensor(idx, device=dev)]
-    sub_coefs = coefs
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    rp = pdd.mc_interface(P, sub_nodes, paths[idx], w.dt, w.seed, precision="fp64_plain", coefs=sub_coefs)
-    e1.record()
-    torch.cuda.synchronize()
-    plain_ps_s = float(rp["steps"].sum().item()) / (e0.elapsed_time(e1) / 1e3)
-    log(f"bench: plain FP64 forward on {k} nodes: {plain_ps_s:.3e} path-steps/s")
+    k_se = min(args.se_nodes, n)
+    idx_se = np.linspace(0, n - 1, k_se).round().astype(int)
+    se_target(idx_se[:8], "fp32", dict(schedule="persistent", **sched_a))        # warm-up
+    el_b, budget_b, res_b, se_max_b = se_target(idx_se, "fp32", dict(schedule="persistent", **sched_a))
+    nodes_per_s = k_se / el_b
+    ps_se = float(res_b["steps"].sum().item())
+    log(f"bench: SE-target batched FP32 fwd+adj: {k_se} nodes, {budget_b.sum():.3e} paths, {el_b:.2f} s "
+        f"-> {nodes_per_s:.1f} nodes/s (max SE {se_max_b:.2e})")
+    k_pl = min(args.plain_nodes, k_se)
+    idx_pl = idx_se[np.linspace(0, k_se - 1, k_pl).round().astype(int)]
+    el_p, budget_p, res_p, se_max_p = se_target(idx_pl, "fp64_plain", {})
+    plain_nodes_per_s = k_pl / el_p
+    plain_ps_s = float(res_p["steps"].sum().item()) / el_p
+    log(f"bench: SE-target plain FP64 fwd+adj: {k_pl} nodes, {budget_p.sum():.3e} paths, {el_p:.2f} s "
+        f"-> {plain_nodes_per_s:.2f} nodes/s (max SE {se_max_p:.2e})")
+
     fwd_ps_s = ps / fwd_s
     adj_ps_s = ps / adj_s
 
@@ -213,8 +231,12 @@ def run(args):
         "adjoint_path_steps_per_s": adj_ps_s,
         "forward_plus_recomputing_adjoint_path_steps_per_s": ps / (fwd_s + adj_s),
         "interface_nodes_per_s_at_se_1e-3": nodes_per_s,
-        "plain_fp64_forward_path_steps_per_s": plain_ps_s,
-        "speedup_batched_fwd_vs_plain_fp64_fwd": fwd_ps_s / plain_ps_s,
+        "se_target": {"nodes": k_se, "paths": int(budget_b.sum()), "path_steps": ps_se, "seconds": el_b,
+                      "max_se": se_max_b, "budget_rule": "pilot 1e3 paths; N_i = clamp(ceil(s_i^2/1e-6), 1e3, 1e7)"},
+        "plain_fp64_fwd_adj_nodes_per_s_at_se_1e-3": plain_nodes_per_s,
+        "plain_fp64_fwd_adj_path_steps_per_s": plain_ps_s,
+        "plain_sample_nodes": k_pl,
+        "speedup_vs_plain_fp64_at_se_1e-3": nodes_per_s / plain_nodes_per_s,
         "mean_steps_per_path": float(mean_steps.mean().item()),
         "roofline": {"bound": "alu", "kernel": f"k_walk ({dominant}, FP32, DIM 3)", "achieved": achieved,
                      "peak": peak, "unit": "Top/s", "frac": achieved / peak, "traffic": None,
@@ -222,15 +244,17 @@ def run(args):
                      "launch_ms": dur * 1e3},
     }
     if args.cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"], out["fp32_vs_fp64_oracle"] = cpu_baseline(w, args.cpu_seconds, pdd, coefs, dev)
     return out
 
 
-def cpu_baseline(w, seconds):
+def cpu_baseline(w, seconds, pdd, coefs, dev):
     """The FP64 oracle (forward + adjoint) on a bounded sample of the same
-    workload, timed on the host's cores."""
+    workload, timed on the host's cores; the GPU FP32 path is then run on the
+    same sample (same nodes, paths and seed) and its node values and gradient
+    are compared with the oracle's."""
+    import torch
     import oracle
-    from workloads import configs as CF
     threads = oracle.default_threads()
     P = w.problem_template
     # calibrate on a tiny sample, then size the sample for ~`seconds`
@@ -251,9 +275,26 @@ def cpu_baseline(w, seconds):
                             n_threads=threads)
     el = time.perf_counter() - t
     ps = float(r["stats"]["steps"].sum())
-    return {"value": ps / el, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+    base = {"value": ps / el, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"C5 forward+adjoint, {nn} nodes x {per_node} paths ({ps:.3e} path-steps, {el:.1f} s), FP64",
             "cpu": platform.processor() or platform.machine()}
+    # error of the FP32-stepping GPU path against the FP64 oracle on this sample
+    sub = torch.tensor(w.nodes[idx], device=dev)
+    g = pdd.mc_adjoint(P, sub, pa, w.dt, w.seed, torch.ones(nn, dtype=torch.float64, device=dev), precision="fp32",
+                       coefs=coefs, with_stats=True)
+    mean_g = g["stats"]["mean"].cpu().numpy()
+    om = r["stats"]["mean"]
+    se = np.sqrt(r["stats"]["m2"] / (r["stats"]["n"] - 1) / r["stats"]["n"])
+    z = np.abs(mean_g - om) / se
+    grad_err = {}
+    for k in ("g_poly", "f_poly", "c_poly"):
+        a, b = g[k].cpu().numpy(), np.asarray(r[k])
+        grad_err[k] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    err = {"nodes": nn, "paths_per_node": per_node, "mean_err_max_se": float(z.max()),
+           "mean_err_rms_se": float(np.sqrt(np.mean(z ** 2))), "gradient_rel_l2_err": grad_err}
+    log(f"bench: FP32 GPU vs FP64 oracle: node values max {z.max():.3f} SE, rms {np.sqrt(np.mean(z ** 2)):.3f} SE; "
+        f"gradient rel err {grad_err}")
+    return base, err
 
 
 def main():
@@ -263,7 +304,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=float, default=1.0, help="path budget scale (1 = 1e5 paths/node)")
     ap.add_argument("--nodes", type=int, default=4096)
-    ap.add_argument("--plain-nodes", type=int, default=16)
+    ap.add_argument("--plain-nodes", type=int, default=8, help="plain FP64 nodes in the SE-target comparison")
+    ap.add_argument("--se-nodes", type=int, default=1024, help="nodes in the SE-target run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="use the default schedule")

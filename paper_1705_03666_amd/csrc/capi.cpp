@@ -259,14 +259,15 @@ struct Plan {
     if ((e = launch_stage(d_jobs, n_jobs, d_perm, d_cd, d_cf, st)) != hipSuccess) return e;
     if (plain) {
       for (const auto& L : pl)
-        if ((e = launch_plain(L, st)) != hipSuccess) return e;
-      return launch_finalize_nodes(d_istat, d_first, n_nodes, out, ctr, st);
-    }
-    if ((e = launch_fill_u32(d_qhead, 1, 0u, st)) != hipSuccess) return e;
-    if (branch) {
-      if ((e = launch_branch(bl, st)) != hipSuccess) return e;
+        if ((e = (L.adjoint ? launch_plain_adj(L, st) : launch_plain(L, st))) != hipSuccess) return e;
+      if (!adjoint) return launch_finalize_nodes(d_istat, d_first, n_nodes, out, ctr, st);
     } else {
-      if ((e = launch_walk(wl, st)) != hipSuccess) return e;
+      if ((e = launch_fill_u32(d_qhead, 1, 0u, st)) != hipSuccess) return e;
+      if (branch) {
+        if ((e = launch_branch(bl, st)) != hipSuccess) return e;
+      } else {
+        if ((e = launch_walk(wl, st)) != hipSuccess) return e;
+      }
     }
     if (out != nullptr)
       if ((e = launch_finalize_nodes(d_istat, d_first, n_nodes, out, ctr, st)) != hipSuccess) return e;
@@ -469,7 +470,6 @@ pdd_status validate_linear(const LinearPlanArgs& a) {
   if (o.dump_steps && !o.dump_phi) return fail(PDD_ERR_INVALID_ARG, "dump_steps needs dump_phi");
   if (a.adjoint) {
     if (a.grads == nullptr && a.jac == nullptr) return fail(PDD_ERR_INVALID_ARG, "grads_host is NULL");
-    if (o.precision == PDD_FP64_PLAIN) return fail(PDD_ERR_UNSUPPORTED, "the adjoint has no plain FP64 variant; use PDD_FP64");
   }
   return PDD_OK;
 }
@@ -575,7 +575,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   if (!plain) {
     items = make_items(a.n_nodes, a.paths, 0, tune.chunk_paths, cost);
   }
-  const int n_items = (int)items.q.size();
+  int n_items = (int)items.q.size();
   pl.n_items = n_items;
   pl.n_nodes = a.n_nodes;
 
@@ -592,14 +592,23 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   for (int64_t i = 0; i < a.n_nodes; ++i) doff[(size_t)i + 1] = doff[(size_t)i] + a.paths[i];
   int64_t n_stat = 0;
   if (plain) {
+    // forward: at most 4096 grid-striding blocks per node; adjoint: one path
+    // per thread, one derivative row per block
     plain_first.resize((size_t)a.n_nodes + 1);
     for (int64_t i = 0; i < a.n_nodes; ++i) {
       plain_first[(size_t)i] = n_stat;
       const int64_t N = a.paths[i];
-      const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((N + kBlock - 1) / kBlock, 4096));
+      const int64_t nb = std::max<int64_t>(1, a.adjoint ? (N + kBlock - 1) / kBlock
+                                                        : std::min<int64_t>((N + kBlock - 1) / kBlock, 4096));
       n_stat += nb;
+      if (a.adjoint) items.slot_node.insert(items.slot_node.end(), (size_t)nb, (int32_t)i);
     }
     plain_first[(size_t)a.n_nodes] = n_stat;
+    if (a.adjoint) {
+      items.first = plain_first;
+      n_items = (int)n_stat;
+      pl.n_items = n_items;
+    }
   } else {
     n_stat = n_items;
     o_items = A.add(sizeof(WorkItem) * std::max(1, n_items));
@@ -731,6 +740,10 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
       L.dump_phi = o.dump_phi;
       L.dump_steps = o.dump_steps;
       L.dump_base = doff[(size_t)i];
+      L.adjoint = a.adjoint;
+      L.nt = nt;
+      L.brow = a.adjoint ? pl.d_igrad + (size_t)plain_first[(size_t)i] * (size_t)pl.grad_stride : nullptr;
+      L.grad_stride = pl.grad_stride;
       pl.pl.push_back(L);
     }
   } else {

@@ -43,6 +43,11 @@ struct PlainLaunch {
   double* dump_phi;
   int64_t* dump_steps;
   int64_t dump_base;
+  // adjoint: one derivative row per block
+  bool adjoint;
+  int nt;                    // generic-term tangent slots (0 or kAdjTerms)
+  double* brow;
+  int grad_stride;
 };
 
 struct BranchLaunch {
@@ -63,6 +68,7 @@ struct BranchLaunch {
 
 hipError_t launch_walk(const WalkLaunch& L, hipStream_t st);
 hipError_t launch_plain(const PlainLaunch& L, hipStream_t st);
+hipError_t launch_plain_adj(const PlainLaunch& L, hipStream_t st);
 hipError_t launch_branch(const BranchLaunch& L, hipStream_t st);
 size_t branch_stack_entry_bytes(bool fp32);
 int branch_lds_depth(bool fp32);

@@ -560,6 +560,162 @@ k_walk_plain(const LinearParams P, int node, uint32_t n_paths, ItemStat* __restr
 }
 
 // ---------------------------------------------------------------------------
+// FP64 plain adjoint: one node per launch, one path per thread (grid covers
+// the node's paths), the straightforward per-path tangents
+//   F_j += m_j Y dt,  A_j += f Y dt S_j (before S moves),  S_j += m_j dt,
+// and at the exit d phi/d f_j = F_j, d phi/d c_j = -g Y S_j - A_j,
+// d phi/d g_k = Y G_k(X_tau).  Each block reduces its paths' derivatives
+// into one row (layout as k_walk: [g terms NT | g poly nested | f NP | c NP])
+// and its statistics into one ItemStat.
+template <int DIM, int DFC, int LAYOUT, int NT>
+__global__ void __launch_bounds__(kBlock)
+k_walk_plain_adj(const LinearParams P, int node, uint32_t n_paths, ItemStat* __restrict__ bstat,
+                 double* __restrict__ brow, int grad_stride) {
+  using NZr = Normals<double, LAYOUT>;
+  constexpr int PB = NZr::kPerBlock;
+  constexpr int NM = GradedLex<DIM, DFC>::N;
+  constexpr int NP = NT + NM;
+  const Dom<double> D = make_dom<double>(P);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  double x0[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) x0[k] = P.nodes[(size_t)node * DIM + k];
+  const bool node_in = inside<double, DIM>(D, x0);
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool have = p < n_paths;
+
+  double X[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) X[k] = x0[k];
+  double Y = 1.0, Z = 0.0;
+  uint32_t n = 0;
+  bool cens = false;
+  double F[NP > 0 ? NP : 1], S[NP > 0 ? NP : 1], A[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) F[j] = S[j] = A[j] = 0.0;
+  if (have && node_in) {
+    uint64_t cur = ~0ull;
+    double zc[PB];
+    for (;;) {
+      if ((int64_t)n >= P.max_steps) { cens = true; break; }
+      BCF<double, DIM, DFC> e;
+      if constexpr (DFC >= 0) monomials<double, DIM, DFC>(X, e.mono);
+      const double fv = fun_value<double, DIM, DFC>(P, P.f, X, e.mono);
+      const double cv = fun_value<double, DIM, DFC>(P, P.c, X, e.mono);
+      const double fYdt = fv * Y * P.dt;
+      const double Ydt = Y * P.dt;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t < P.c.n_terms) {
+          A[t] += fYdt * S[t];
+          S[t] += term_value<double, DIM>(P.fac, P.c, t, X) * P.dt;
+        }
+        if (t < P.f.n_terms) F[t] += term_value<double, DIM>(P.fac, P.f, t, X) * Ydt;
+      }
+      if constexpr (DFC >= 0) {
+        if (P.c.poly_deg >= 0) {
+#pragma unroll
+          for (int m = 0; m < NM; ++m) {
+            A[NT + m] += fYdt * S[NT + m];
+            S[NT + m] += e.mono[m] * P.dt;
+          }
+        }
+        if (P.f.poly_deg >= 0) {
+#pragma unroll
+          for (int m = 0; m < NM; ++m) F[NT + m] += e.mono[m] * Ydt;
+        }
+      }
+      double bv[DIM];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) bv[k] = fun_value<double, DIM, DFC>(P, P.b[k], X, e.mono);
+      Z = Z + fv * Y * P.dt;
+      Y = Y * exp(-cv * P.dt);
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const uint64_t j = (uint64_t)n * DIM + k;
+        const uint64_t blk = j / PB;
+        if (blk != cur) {
+          NZr::gen((uint32_t)blk, (uint32_t)((blk >> 32) & 0xFFFFFFu), p, (uint32_t)node, P.key0, P.key1, zc);
+          cur = blk;
+        }
+        double zk = zc[0];
+#pragma unroll
+        for (int q = 1; q < PB; ++q) if ((int)(j % PB) == q) zk = zc[q];
+        X[k] = X[k] + bv[k] * P.dt + P.sdt * zk;
+      }
+      ++n;
+      if (!inside<double, DIM>(D, X)) break;
+    }
+  }
+  double xp[3];
+  project<double, DIM>(D, X, xp);
+  const double gv = g_value<double, DIM>(P, xp);
+  const double phi = gv * Y + Z;
+
+  // block statistics: one sample per thread that has a path
+  __shared__ double sn[kBlock / kWave], sm[kBlock / kWave], sq[kBlock / kWave], red[kBlock / kWave];
+  __shared__ int64_t ss[kBlock / kWave], sc[kBlock / kWave];
+  double wn = have ? 1.0 : 0.0, wmean = have ? phi : 0.0, wm2 = 0.0;
+  int64_t lsteps = have ? (int64_t)n : 0, lcens = (have && cens) ? 1 : 0;
+  wave_welford(wn, wmean, wm2);
+  lsteps = wave_sum(lsteps);
+  lcens = wave_sum(lcens);
+  if (lane == 0) { sn[wid] = wn; sm[wid] = wmean; sq[wid] = wm2; ss[wid] = lsteps; sc[wid] = lcens; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bn = 0.0, bm = 0.0, bq = 0.0;
+    int64_t st = 0, ce = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+      chan_merge(bn, bm, bq, sn[w], sm[w], sq[w]);
+      st += ss[w];
+      ce += sc[w];
+    }
+    ItemStat r;
+    r.mean = bm; r.m2 = bq; r.n = (int64_t)bn; r.steps = st; r.censored = ce; r.redrawn = 0;
+    bstat[blockIdx.x] = r;
+  }
+
+  // derivative columns, one block sum each (waves in order)
+  double* row = brow + (size_t)blockIdx.x * (size_t)grad_stride;
+  auto put = [&](int col, double v) {
+    const double s = wave_sum(have ? v : 0.0);
+    __syncthreads();
+    if (lane == 0) red[wid] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[w];
+      row[col] = t;
+    }
+  };
+  int col = 0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) put(col + t, t < P.g.n_terms ? Y * term_value<double, DIM>(P.fac, P.g, t, xp) : 0.0);
+  col += NT;
+  if (P.g.poly_deg >= 0) {
+    const int deg = P.g.poly_deg;
+    double xa = Y;
+    for (int a = 0; a <= deg; ++a) {
+      double xb = xa;
+      for (int b = 0; b <= (DIM >= 2 ? deg - a : 0); ++b) {
+        double xc = xb;
+        for (int c = 0; c <= (DIM >= 3 ? deg - a - b : 0); ++c) {
+          put(col++, xc);
+          if (DIM >= 3) xc *= xp[2];
+        }
+        if (DIM >= 2) xb *= xp[1];
+      }
+      xa *= xp[0];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NP; ++j) put(col + j, F[j]);
+  col += NP;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) put(col + j, -gv * Y * S[j] - A[j]);
+}
+
+// ---------------------------------------------------------------------------
 // Launch of one k_walk instantiation, dispatched on dimension and on whether
 // b, c, f have a polynomial part.
 template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ>

@@ -278,6 +278,35 @@ def test_adjoint_fp64_matches_oracle(pdd, orc):
         stats_close(g["stats"], o["stats"])
 
 
+def test_plain_fp64_adjoint_matches_oracle(pdd, orc):
+    """The single-node-per-launch FP64 adjoint (one path per thread, textbook
+    tangents) against the oracle; terms and polynomials in g, f, c."""
+    P, nodes = _c5_small(1, 4)
+    paths = np.array([150, 64, 301, 90], np.int64)
+    dt = 1e-2
+    w = np.array([0.5, -1.0, 2.0, 0.25])
+    o = orc.walk_adjoint(P, nodes, paths, dt, 21, w)
+    g = pdd.mc_adjoint(P, nodes, paths, dt, 21, w, precision="fp64_plain", layout="pair52", with_stats=True)
+    torch.cuda.synchronize()
+    for k in ("g_coef", "g_poly", "f_coef", "f_poly", "c_coef", "c_poly"):
+        got, want = g[k].cpu().numpy(), o[k]
+        assert got.shape == want.shape, k
+        assert np.allclose(got, want, rtol=1e-10, atol=1e-12 * max(1.0, np.abs(want).max())), k
+    stats_close(g["stats"], o["stats"])
+
+
+def test_plain_value_jacobian_matches_batched(pdd):
+    P, nodes = _c5_small(6, 3, deg_terms=False)
+    paths = np.array([700, 257, 1024], np.int64)
+    a = pdd.mc_value_jacobian(P, nodes, paths, 2e-3, 9, precision="fp64_plain")
+    b = pdd.mc_value_jacobian(P, nodes, paths, 2e-3, 9, precision="fp64", schedule="persistent")
+    torch.cuda.synchronize()
+    assert torch.allclose(a["mean"], b["mean"], rtol=1e-12, atol=1e-14)
+    assert torch.equal(a["steps"], b["steps"])
+    ja, jb = a["jac"].cpu().numpy(), b["jac"].cpu().numpy()
+    assert np.allclose(ja, jb, rtol=1e-10, atol=1e-12 * max(1.0, np.abs(jb).max()))
+
+
 def test_adjoint_fp32_matches_crn_finite_differences(pdd):
     P, nodes = _c5_small(2, 6, deg_terms=False)
     paths = np.full(6, 2000, np.int64)
