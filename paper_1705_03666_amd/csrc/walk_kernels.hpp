@@ -174,16 +174,32 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   constexpr int NP = ADJ ? NT + NM : 0;
   constexpr int kRecW = DIM + 2 + NP;
   constexpr int kWaves = kBlock / kWave;
-  constexpr int kCols = ADJ ? 2 * NP + NT + GradedLex<DIM, kMaxPolyG>::N : 0;
+  constexpr int kGMono = GradedLex<DIM, kMaxPolyG>::N;      // g-polynomial monomials, at most
+  constexpr int kCols = ADJ ? 2 * NP + NT + kGMono : 0;
   constexpr int kSlots = kCols > 0 ? (kCols + kWave - 1) / kWave : 1;
+  constexpr int kGSlots = (kGMono + kWave - 1) / kWave;
+  // power table of the g-gradient pass, one row of odd stride per record:
+  // Y x0^a (a = 0..deg), x1^b, x2^c (b, c = 1..deg), and a constant 1
+  constexpr int kPwStride = (DIM * kMaxPolyG + 2) | 1;
+  constexpr int kFoldMax = NP > NT ? NP : (NT > 0 ? NT : 1);
+  constexpr int kArea0 = kRecW * kWave;
+  constexpr int kArea1 = ADJ ? kWave * kPwStride : 0;
+  constexpr int kArea2 = ADJ ? kWave * (kFoldMax | 1) : 0;
+  constexpr int kArea = kArea0 > kArea1 ? (kArea0 > kArea2 ? kArea0 : kArea2) : (kArea1 > kArea2 ? kArea1 : kArea2);
 
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const int wid = (int)(threadIdx.x / kWave);
-  // exit records, one column per record (conflict-free lane-per-record reads)
-  __shared__ R rec[kWaves][kRecW][kWave];
+  // Per-wave scratch, used in turn as (1) the exit records, field-major with
+  // one column per record (conflict-free lane-per-record reads), (2) the
+  // power table of the g-gradient pass and (3) the transpose of the
+  // running derivative sums.
+  __shared__ R area[kWaves][kArea];
   __shared__ uint32_t rec_i[kWaves][2][kWave];   // path, steps | censored << 31
   // FP64 per-item derivative accumulators, column ic at [ic / 64][ic % 64]
   __shared__ double acc[ADJ ? kWaves : 1][kSlots][kWave];
+  // g-polynomial monomial k (nested order): its three power-table rows
+  __shared__ uint32_t gmono[ADJ ? kGMono : 1];
+  R* const rec = &area[wid][0];
 
   const Dom<R> D = make_dom<R>(P);
   const R dt = dt_of<R>(P);
@@ -191,6 +207,20 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   const uint32_t max_steps = (uint32_t)P.max_steps;
   const uint32_t k0 = P.key0, k1 = P.key1;
   const int ngm = (ADJ && P.g.poly_deg >= 0) ? P.g.n_mono : 0;
+  if constexpr (ADJ) {
+    if (P.g.poly_deg >= 0 && threadIdx.x == 0) {
+      const int deg = P.g.poly_deg, one = DIM * deg + 1;
+      int k = 0;
+      for (int ea = 0; ea <= deg; ++ea)
+        for (int eb = 0; eb <= (DIM >= 2 ? deg - ea : 0); ++eb)
+          for (int ec = 0; ec <= (DIM >= 3 ? deg - ea - eb : 0); ++ec) {
+            const uint32_t rb = eb > 0 ? (uint32_t)(deg + eb) : (uint32_t)one;
+            const uint32_t rc = ec > 0 ? (uint32_t)(2 * deg + ec) : (uint32_t)one;
+            gmono[k++] = (uint32_t)ea | (rb << 8) | (rc << 16);
+          }
+    }
+    __syncthreads();
+  }
 
   for (;;) {
     const uint32_t it_idx = pop_item(qhead);
@@ -229,18 +259,31 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
       for (int r = 0; r < kSlots; ++r) acc[wid][r][lane] = 0.0;
     }
 
-    // adds a wavefront total to accumulator column ic
-    auto add_col = [&](int ic, double s) {
-      if (lane == (ic & (kWave - 1))) acc[wid][ic >> 6][lane] += s;
-    };
-    auto fold = [&](R& v, int ic) {
-      add_col(ic, wave_sum((double)v));
-      v = (R)0;
+    // Folds CNT running sums v[] of every lane into accumulator columns
+    // ic0.. through an LDS transpose: lane j then adds up column j in FP64.
+    auto fold = [&](R* v, const int cnt, const int ic0) {
+      constexpr int kS = kFoldMax | 1;
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int j = 0; j < kFoldMax; ++j)
+        if (j < cnt) rec[lane * kS + j] = v[j];
+      __builtin_amdgcn_wave_barrier();
+      if (lane < cnt) {
+        double s = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < kWave; ++i) s += (double)rec[i * kS + lane];
+        const int ic = ic0 + lane;
+        acc[wid][ic >> 6][ic & (kWave - 1)] += s;
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int j = 0; j < kFoldMax; ++j)
+        if (j < cnt) v[j] = (R)0;
     };
 
     auto flush = [&]() {
       if (nrec > 0) {
-        // records written by other lanes are read here and their slots are
+        // records written by other lanes are read here and the area is
         // reused right after: keep these LDS accesses in program order
         __builtin_amdgcn_wave_barrier();
         R xr[3] = {(R)0, (R)0, (R)0};
@@ -248,8 +291,8 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
         if (lane < nrec) {
           R xe[DIM];
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) xe[k] = rec[wid][k][lane];
-          const R y = rec[wid][DIM][lane], z = rec[wid][DIM + 1][lane];
+          for (int k = 0; k < DIM; ++k) xe[k] = rec[k * kWave + lane];
+          const R y = rec[DIM * kWave + lane], z = rec[(DIM + 1) * kWave + lane];
           const uint32_t pr = rec_i[wid][0][lane], nr = rec_i[wid][1][lane];
           project<R, DIM>(D, xe, xr);
           const R gv = g_value<R, DIM>(P, xr);
@@ -268,7 +311,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           }
           if constexpr (ADJ) {
 #pragma unroll
-            for (int j = 0; j < NP; ++j) Br[j] -= phi * rec[wid][DIM + 2 + j][lane];
+            for (int j = 0; j < NP; ++j) Br[j] -= phi * rec[(DIM + 2 + j) * kWave + lane];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
               if (t < P.g.n_terms) Gr[t] += y * term_value<R, DIM>(P.fac, P.g, t, xr);
@@ -276,24 +319,50 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           }
         }
         if constexpr (ADJ) {
-          // g polynomial: sum over the records of Y monomial(X_tau), nested
-          // order, one wavefront sum per monomial
+          // g polynomial: column k gets the sum over the records of
+          // Y monomial_k(X_tau).  Record lanes write their power rows, then
+          // lane k % 64 sums monomial k over the records in FP64.
           if (P.g.poly_deg >= 0) {
             const int deg = P.g.poly_deg;
-            int ic = 2 * NP + NT;
-            R xa = yr;
-            for (int a = 0; a <= deg; ++a) {
-              R xb = xa;
-              for (int b = 0; b <= (DIM >= 2 ? deg - a : 0); ++b) {
-                R xc = xb;
-                for (int c = 0; c <= (DIM >= 3 ? deg - a - b : 0); ++c) {
-                  add_col(ic, wave_sum((double)xc));
-                  ++ic;
-                  if (DIM >= 3) xc *= xr[2];
-                }
-                if (DIM >= 2) xb *= xr[1];
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nrec) {
+              R* row = rec + lane * kPwStride;
+              R pa = yr;
+              for (int e = 0; e <= deg; ++e) {
+                row[e] = pa;
+                pa *= xr[0];
               }
-              xa *= xr[0];
+              if constexpr (DIM >= 2) {
+                R pb = xr[1];
+                for (int e = 1; e <= deg; ++e) {
+                  row[deg + e] = pb;
+                  pb *= xr[1];
+                }
+              }
+              if constexpr (DIM >= 3) {
+                R pc = xr[2];
+                for (int e = 1; e <= deg; ++e) {
+                  row[2 * deg + e] = pc;
+                  pc *= xr[2];
+                }
+              }
+              row[DIM * deg + 1] = (R)1;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int r = 0; r < kGSlots; ++r) {
+              const int k = r * kWave + lane;
+              if (k < ngm) {
+                const uint32_t m = gmono[k];
+                const int ra = (int)(m & 0xFFu), rb = (int)((m >> 8) & 0xFFu), rc = (int)(m >> 16);
+                double sum = 0.0;
+                for (int i = 0; i < nrec; ++i) {
+                  const R* row = rec + i * kPwStride;
+                  sum += (double)(row[ra] * row[rb] * row[rc]);
+                }
+                const int ic = 2 * NP + NT + k;
+                acc[wid][ic >> 6][ic & (kWave - 1)] += sum;
+              }
             }
           }
         }
@@ -301,22 +370,11 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
         nrec = 0;
       }
       if constexpr (ADJ) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          if (t < P.f.n_terms) fold(Fr[t], t);
-          if (t < P.c.n_terms) fold(Br[t], NP + t);
-          if (t < P.g.n_terms) fold(Gr[t], 2 * NP + t);
+        if constexpr (NP > 0) {
+          fold(Fr, NP, 0);
+          fold(Br, NP, NP);
         }
-        if constexpr (NM > 0) {
-          if (P.f.poly_deg >= 0) {
-#pragma unroll
-            for (int m = 0; m < NM; ++m) fold(Fr[NT + m], NT + m);
-          }
-          if (P.c.poly_deg >= 0) {
-#pragma unroll
-            for (int m = 0; m < NM; ++m) fold(Br[NT + m], NP + NT + m);
-          }
-        }
+        if constexpr (NT > 0) fold(Gr, NT, 2 * NP);
       }
     };
 
@@ -406,11 +464,11 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
         if (fin) {
           const int slot = nrec + lane_rank(fmask);
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) rec[wid][k][slot] = X[k];
-          rec[wid][DIM][slot] = Y;
-          rec[wid][DIM + 1][slot] = Z;
+          for (int k = 0; k < DIM; ++k) rec[k * kWave + slot] = X[k];
+          rec[DIM * kWave + slot] = Y;
+          rec[(DIM + 1) * kWave + slot] = Z;
 #pragma unroll
-          for (int j = 0; j < NP; ++j) rec[wid][DIM + 2 + j][slot] = S[j];
+          for (int j = 0; j < NP; ++j) rec[(DIM + 2 + j) * kWave + slot] = S[j];
           rec_i[wid][0][slot] = path;
           rec_i[wid][1][slot] = n | (cens ? 0x80000000u : 0u);
         }
