@@ -44,9 +44,9 @@ def log(msg):
 
 # Algorithmic VALU lane-ops per path-step of the C5 walk (3-D ball, b = 0,
 # cubic c and f, QUAD24 Gaussians); each op is one VALU lane operation:
-#   Philox4x32-10 block: 10 rounds x (2 32x32->64 products + 4 xors) + 2
-#     counter ops = 62, x 3/4 block per step                          46.5
-#   QUAD24 uniforms: 4 words x (shift, convert, fma) = 12, x 3/4         9
+#   Philox4x32-10 block: 10 rounds x (2 32x32->64 products + 2 three-input
+#     xors) + 2 counter ops = 42, x 3/4 block per step                  31.5
+#   QUAD24 uniforms: 4 words x (funnel shift, add) = 8, x 3/4            6
 #   Box-Muller pair: log2, mul, sqrt, sin, cos, 2 mul = 7, x 1.5        10.5
 #   cubic monomials of X                                                16
 #   f and c: 2 x 19 FMA                                                 38
@@ -54,10 +54,10 @@ def log(msg):
 #   X += sigma sqrt(dt) z                                                3
 #   ball exit test: 3 sub, mul, 2 fma, compare                           7
 #   step count and cap                                                   2
-# forward: 138.  The adjoint adds Y dt, Z dt and 3 x 20 tangent FMAs
-# (F += m Y dt, S += m dt, B += m Z dt): 200.
-OPS_PER_PS_FWD = 138.0
-OPS_PER_PS_ADJ = 200.0
+# forward: 120.  The adjoint adds Y dt, Z dt and 3 x 20 tangent FMAs
+# (F += m Y dt, S += m dt, B += m Z dt): 182.
+OPS_PER_PS_FWD = 120.0
+OPS_PER_PS_ADJ = 182.0
 
 
 def run(args):

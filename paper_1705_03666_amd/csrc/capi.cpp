@@ -558,6 +558,10 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   lp.f = T.add(P.f, dim, dfc, false);
   lp.g = T.add(P.g, dim, 0, true);
   lp.n_fac = (int)T.fac.size();
+  auto nonzero = [](const DevFun& F) { return F.n_terms > 0 || F.poly_deg >= 0; };
+  lp.has_b = nonzero(lp.b[0]) || nonzero(lp.b[1]) || nonzero(lp.b[2]);
+  lp.has_c = nonzero(lp.c);
+  lp.has_f = nonzero(lp.f);
 
   // ---- work items
   const Tuning tune = choose_tuning(dim, fp32, a.adjoint, o, device_cus());

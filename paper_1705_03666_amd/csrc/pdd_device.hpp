@@ -13,15 +13,20 @@ namespace pdd {
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
 // and xors.  The key (the seed) is uniform across a wavefront, so the key
-// schedule stays in scalar registers.
+// schedule stays in scalar registers.  The three-way xors are single
+// three-input bitwise operations (truth table 0x96 = a ^ b ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
                                               uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -37,7 +42,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 //   PAIR52: u = (2 k + 1) 2^-53, k = (w_hi << 20) | (w_lo >> 12) (exact in FP64)
 // Box-Muller: z0 = r cos(2 pi u_b), z1 = r sin(2 pi u_b), r = sqrt(-2 ln u_a).
 __device__ __forceinline__ float u24f(uint32_t w) {
-  return __builtin_fmaf((float)(w >> 9), 0x1p-23f, 0x1p-24f);
+  // 0x3F800000 | (w >> 9) is the float 1 + (w >> 9) 2^-23 in [1, 2) (one
+  // funnel shift of 0x7F:w); subtracting 1 - 2^-24 is exact and leaves
+  // (2 (w >> 9) + 1) 2^-24.
+  const uint32_t bits = __builtin_amdgcn_alignbit(0x7Fu, w, 9);
+  return __builtin_bit_cast(float, bits) - 0x1.fffffep-1f;
 }
 __device__ __forceinline__ double u24d(uint32_t w) {
   return (double)(w >> 9) * 0x1p-23 + 0x1p-24;

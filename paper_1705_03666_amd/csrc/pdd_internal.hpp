@@ -41,6 +41,7 @@ struct LinearParams {
   float dtf, sdtf;
   int64_t max_steps;
   uint32_t key0, key1;
+  int32_t has_b, has_c, has_f, pad_flags;   // b, c, f not identically zero
   DevFun b[3], c, f, g;
   const DevFactor* fac;
   const double* cd;

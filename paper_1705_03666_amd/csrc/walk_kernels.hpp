@@ -415,7 +415,9 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
                 }
               }
             }
-            Z = Z + fv * Y * dt;
+            // terms known to vanish are skipped: X + 0 dt, Z + 0 and
+            // Y exp(0) leave the same bits as evaluating them
+            if (P.has_f) Z = Z + fv * Y * dt;
             if constexpr (ADJ) {
               const R Zdt = Z * dt;
 #pragma unroll
@@ -436,12 +438,17 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
                 }
               }
             }
-            Y = Y * fexp(-cv * dt);
-            R bv[DIM];
+            if (P.has_c) Y = Y * fexp(-cv * dt);
+            if (P.has_b) {
+              R bv[DIM];
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) bv[k] = bcf_value<R, DIM, DFC, TERMS>(P, P.b[k], X, mono);
+              for (int k = 0; k < DIM; ++k) bv[k] = bcf_value<R, DIM, DFC, TERMS>(P, P.b[k], X, mono);
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) X[k] = X[k] + bv[k] * dt + sdt * z[s * DIM + k];
+              for (int k = 0; k < DIM; ++k) X[k] = X[k] + bv[k] * dt + sdt * z[s * DIM + k];
+            } else {
+#pragma unroll
+              for (int k = 0; k < DIM; ++k) X[k] = X[k] + sdt * z[s * DIM + k];
+            }
             ++n;
             if (!inside<R, DIM>(D, X)) {
               alive = false;
