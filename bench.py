@@ -59,6 +59,23 @@ def log(msg):
 OPS_PER_PS_FWD = 120.0
 OPS_PER_PS_ADJ = 182.0
 
+# HBM bytes per launch of the dominant kernel (C5 value+Jacobian walk),
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the 256 MiB copy
+# calibration (x 2.000 / x 1.000).  Valid only for the kernel sources they
+# were counted on: any change to them makes the bench report null.
+TRAFFIC_SOURCES = ['paper_1705_03666_amd/csrc/walk_kernels.hpp', 'paper_1705_03666_amd/csrc/pdd_device.hpp', 'paper_1705_03666_amd/csrc/pdd_internal.hpp', 'paper_1705_03666_amd/csrc/walk_adj_f32.hip']
+TRAFFIC_SHA256 = "b8cb9e23f96fe42deecd1c689b5988effa3c45e290d3359182427a0758461794"
+TRAFFIC_BYTES = 36.90e6 + 95.37e6
+
+
+def traffic_bytes():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES if h.hexdigest() == TRAFFIC_SHA256 else None
+
 
 def run(args):
     import torch
@@ -91,7 +108,16 @@ def run(args):
     log(f"bench: data ready ({time.time() - t0:.1f} s)")
 
     from paper_1705_03666_amd import autotune
-    if args.tune:
+
+    def parse_sched(text):
+        b, r, c = (int(v) for v in text.split(","))
+        return {"blocks_per_cu": b, "refill_groups": r, "chunk_paths": c}
+
+    if args.schedule_adj:
+        sched_a = parse_sched(args.schedule_adj)
+        sched_f = parse_sched(args.schedule_fwd) if args.schedule_fwd else dict(sched_a)
+        log(f"bench: given schedules: forward {sched_f}, adjoint {sched_a}")
+    elif args.tune:
         t0 = time.time()
         sched_f = autotune.tune(P, nodes, paths, w.dt, w.seed, "fp32", False, coefs, log=log)
         sched_a = autotune.tune(P, nodes, paths, w.dt, w.seed, "fp32", True, coefs, log=log)
@@ -123,7 +149,8 @@ def run(args):
 
     for i in range(args.warmup):
         step()
-        step_recompute()
+        if not args.steps_only:
+            step_recompute()
         torch.cuda.synchronize()
         log(f"bench: warmup {i + 1}/{args.warmup} done")
 
@@ -142,6 +169,17 @@ def run(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms_step = wall * 1e3 / args.steps
+
+    if args.steps_only:
+        # profiling mode: only the timed value+Jacobian steps above
+        r = stats["fwd"]
+        ps = float(r["steps"].sum().item())
+        dur = np.median(vj_ms) / 1e3
+        return {"metric": "path-steps/s (batched FP32 forward+adjoint, C5)", "value": ps / (ms_step / 1e3),
+                "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "ms_per_step": ms_step, "mode": "steps-only", "tuned_adjoint": sched_a,
+                "roofline": {"bound": "alu", "achieved": ps * OPS_PER_PS_ADJ / dur / 1e12,
+                             "peak": PEAK_LANE_OPS / 1e12, "unit": "Top/s", "launch_ms": dur * 1e3}}
 
     # the path-recomputing route (forward kernel, then adjoint kernel), timed
     # separately with the same schedule
@@ -239,7 +277,7 @@ def run(args):
         "speedup_vs_plain_fp64_at_se_1e-3": nodes_per_s / plain_nodes_per_s,
         "mean_steps_per_path": float(mean_steps.mean().item()),
         "roofline": {"bound": "alu", "kernel": f"k_walk ({dominant}, FP32, DIM 3)", "achieved": achieved,
-                     "peak": peak, "unit": "Top/s", "frac": achieved / peak, "traffic": None,
+                     "peak": peak, "unit": "Top/s", "frac": achieved / peak, "traffic": traffic_bytes(),
                      "ops_per_path_step": OPS_PER_PS_ADJ if dominant == "adjoint" else OPS_PER_PS_FWD,
                      "launch_ms": dur * 1e3},
     }
@@ -309,6 +347,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="use the default schedule")
+    ap.add_argument("--schedule-adj", default="", help="blocks_per_cu,refill_groups,chunk_paths (skips tuning)")
+    ap.add_argument("--schedule-fwd", default="", help="as --schedule-adj, for the forward kernel")
+    ap.add_argument("--steps-only", action="store_true",
+                    help="run only the timed value+Jacobian steps (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 256 MiB (reference for the FETCH/WRITE counters)")
     args = ap.parse_args()
