@@ -157,7 +157,7 @@ typedef struct {
                              goes into items of chunk_paths/8, at least 256, queued last);
                              0 = autotuned/default */
   int32_t blocks_per_cu;  /* persistent grid size per compute unit; 0 = autotuned/default */
-  int32_t refill_groups;  /* step groups between lane refills; 0 = autotuned/default (1) */
+  int32_t refill_groups;  /* step groups between lane refills; 0 = autotuned/default (3) */
 } pdd_options;
 
 /* Per-node result: mean and sum of squared deviations (variance = m2/(n-1),

@@ -27,7 +27,7 @@ SPACE = {
     "refill_groups": [1, 2, 3, 4, 6, 8],
     "chunk_paths": [2048, 4096, 8192, 16384, 32768],
 }
-DEFAULT = {"blocks_per_cu": 4, "refill_groups": 2, "chunk_paths": 8192}
+DEFAULT = {"blocks_per_cu": 8, "refill_groups": 3, "chunk_paths": 16384}
 VERSION = 2
 
 

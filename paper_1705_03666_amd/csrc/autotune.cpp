@@ -11,10 +11,12 @@ namespace pdd {
 Tuning choose_tuning(int dim, bool fp32, bool adjoint, const pdd_options& o, int n_cus) {
   (void)dim;
   (void)n_cus;
+  (void)adjoint;
   Tuning t;
-  t.chunk_paths = adjoint ? 4096 : 4096;
-  t.blocks_per_cu = fp32 ? 2 : 2;
-  t.refill_groups = 1;
+  // measured on MI355X for the 3-D C5 walk (forward and adjoint alike)
+  t.chunk_paths = 16384;
+  t.blocks_per_cu = fp32 ? 8 : 4;
+  t.refill_groups = 3;
   if (o.chunk_paths > 0) t.chunk_paths = o.chunk_paths;
   if (o.blocks_per_cu > 0) t.blocks_per_cu = o.blocks_per_cu;
   if (o.refill_groups > 0) t.refill_groups = o.refill_groups;
