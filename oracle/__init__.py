@@ -8,6 +8,7 @@ of plain input data.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from typing import Optional
@@ -50,7 +51,13 @@ class ODomain(C.Structure):
 
 class OLinear(C.Structure):
     _fields_ = [("dom", ODomain), ("sigma", C.c_double), ("b", OFun * 3), ("c", OFun), ("f", OFun),
-                ("g", OFun)]
+                ("g", OFun), ("boundary_shift", C.c_double)]
+
+
+# Gobet-Menozzi boundary-shift constant c0 = -zeta(1/2) / sqrt(2 pi) (the
+# mean overshoot of a Gaussian random walk over a level, in units of its
+# step standard deviation); zeta(1/2) = -1.4603545088095868...
+GOBET_MENOZZI_C0 = 1.4603545088095868 / math.sqrt(2.0 * math.pi)
 
 
 class OBranching(C.Structure):
@@ -165,10 +172,11 @@ def _odomain(D) -> ODomain:
     return o
 
 
-def _olinear(P: LinearProblem, keep: _Keep) -> OLinear:
+def _olinear(P: LinearProblem, keep: _Keep, boundary_shift: float = 0.0) -> OLinear:
     o = OLinear()
     o.dom = _odomain(P.domain)
     o.sigma = float(P.sigma)
+    o.boundary_shift = float(boundary_shift)
     from workloads.problem import zero_fun
     for k in range(3):
         o.b[k] = _ofun(P.b[k] if k < len(P.b) else zero_fun(), P.ndim, keep)
@@ -218,13 +226,14 @@ def fun_eval(F: Fun, ndim: int, x) -> float:
 
 def walk(P: LinearProblem, nodes, paths, dt: float, seed: int, layout: int = PAIR52,
          max_steps: Optional[int] = None, n_threads: Optional[int] = None, dump: bool = False,
-         node_ids=None) -> dict:
+         node_ids=None, boundary_shift: float = 0.0) -> dict:
     """Per-node sample mean / variance of the Feynman-Kac walk (optionally the
     per-path values and step counts, concatenated node after node).  node_ids
     gives the node index used in the random-number counters (default: the
-    node's position), so a sample of a larger node set reproduces its paths."""
+    node's position), so a sample of a larger node set reproduces its paths.
+    boundary_shift = GOBET_MENOZZI_C0 selects the boundary-corrected exit test."""
     keep = _Keep()
-    o = _olinear(P, keep)
+    o = _olinear(P, keep, boundary_shift)
     nodes = keep.arr(nodes, np.float64)
     paths = keep.arr(paths, np.int64)
     n = len(paths)
@@ -246,10 +255,11 @@ def walk(P: LinearProblem, nodes, paths, dt: float, seed: int, layout: int = PAI
 
 
 def walk_adjoint(P: LinearProblem, nodes, paths, dt: float, seed: int, w, layout: int = PAIR52,
-                 max_steps: Optional[int] = None, n_threads: Optional[int] = None) -> dict:
+                 max_steps: Optional[int] = None, n_threads: Optional[int] = None,
+                 boundary_shift: float = 0.0) -> dict:
     """Gradient of sum_i w_i * mean_i with respect to the coefficients of g, f, c."""
     keep = _Keep()
-    o = _olinear(P, keep)
+    o = _olinear(P, keep, boundary_shift)
     nodes = keep.arr(nodes, np.float64)
     paths = keep.arr(paths, np.int64)
     w = keep.arr(w, np.float64)

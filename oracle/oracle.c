@@ -224,14 +224,38 @@ typedef struct {
  * pure-Dirichlet limit, with c read as a killing rate: dY = -c Y dt):
  *   X_0 = node, Y_0 = 1, Z_0 = 0; for n = 0, 1, ...
  *     Z += f(X) Y dt;  Y *= exp(-c(X) dt);  X += b(X) dt + sigma sqrt(dt) zeta_n
- *   stopping at the first n with X outside D; then phi = g(P(X)) Y + Z with P
- *   the nearest-boundary projection.  A node outside D gives phi = g(P(node)).
+ *   stopping at the first n with X outside D (or outside the shrunk test
+ *   domain of the corrected scheme); then phi = g(P(X)) Y + Z with P the
+ *   nearest-boundary projection onto dD.  A node outside D gives phi = g(P(node)).
  *   A path reaching max_steps is censored: phi = g(P(X)) Y + Z. */
+/* The domain of the exit test: D itself, or D shrunk by c0 sigma sqrt(dt)
+ * for the boundary-corrected scheme (Sec. 2.1 points to Gobet and Menozzi's
+ * corrected Euler schemes for stopped diffusions; their correction moves the
+ * boundary inward by c0 |sigma n| sqrt(dt), c0 = -zeta(1/2)/sqrt(2 pi), and
+ * |sigma n| = sigma here since the diffusion matrix is sigma I). */
+static orc_domain test_domain(const orc_linear* P, double dt) {
+  orc_domain T = P->dom;
+  if (P->boundary_shift > 0.0) {
+    const double delta = P->boundary_shift * P->sigma * sqrt(dt);
+    if (T.kind == ORC_BOX) {
+      for (int k = 0; k < T.dim; ++k) {
+        T.lo[k] = T.lo[k] + delta;
+        T.hi[k] = T.hi[k] - delta;
+      }
+    } else if (T.kind == ORC_BALL) {
+      T.radius = T.radius - delta;
+      if (T.radius < 0.0) T.radius = 0.0;
+    }
+  }
+  return T;
+}
+
 static path_result walk_path(const orc_linear* P, const double* node, const uint32_t key[2], int layout,
                              uint32_t node_idx, uint32_t path_idx, double dt, int64_t max_steps,
                              tangents* tg) {
   path_result R;
   const orc_domain* D = &P->dom;
+  const orc_domain DT = test_domain(P, dt);
   int d = D->dim;
   double X[3] = {0.0, 0.0, 0.0}, Xp[3];
   for (int k = 0; k < d; ++k) X[k] = node[k];
@@ -243,7 +267,7 @@ static path_result walk_path(const orc_linear* P, const double* node, const uint
     for (int j = 0; j < tg->nf; ++j) tg->F[j] = 0.0;
     for (int j = 0; j < tg->nc; ++j) { tg->S[j] = 0.0; tg->A[j] = 0.0; }
   }
-  if (!orc_inside(D, X)) {
+  if (!orc_inside(&DT, X)) {
     orc_project(D, X, Xp);
     R.phi = orc_fun_eval(&P->g, Xp);
     R.steps = 0;
@@ -268,7 +292,7 @@ static path_result walk_path(const orc_linear* P, const double* node, const uint
     for (int k = 0; k < d; ++k) bx[k] = orc_fun_eval(&P->b[k], X);
     for (int k = 0; k < d; ++k) X[k] = X[k] + bx[k] * dt + P->sigma * sdt * zeta[k];
     n += 1;
-    if (!orc_inside(D, X)) break;
+    if (!orc_inside(&DT, X)) break;
   }
   orc_project(D, X, Xp);
   R.phi = orc_fun_eval(&P->g, Xp) * Y + Z;

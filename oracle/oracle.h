@@ -58,11 +58,17 @@ typedef struct {
   double lo[3], hi[3], center[3], radius;
 } orc_domain;
 
-/* 0.5 sigma^2 Lap u + b.grad u - c u = -f in D, u = g on dD */
+/* 0.5 sigma^2 Lap u + b.grad u - c u = -f in D, u = g on dD.
+ * boundary_shift = 0: the plain exit test (X outside D after a step).
+ * boundary_shift = c0 > 0: the exit test of Gobet and Menozzi's boundary
+ * correction for stopped Euler schemes: the path stops once X leaves D shrunk
+ * by c0 sigma sqrt(dt) (ball: radius R - c0 sigma sqrt(dt); box: every face
+ * moved inward by it); the exit value still uses the projection onto dD. */
 typedef struct {
   orc_domain dom;
   double sigma;
   orc_fun b[3], c, f, g;
+  double boundary_shift;
 } orc_linear;
 
 /* u_t = 0.5 sigma^2 Lap u + beta (sum_i alpha_i u^i - u), u(.,0) = psi, at time T */

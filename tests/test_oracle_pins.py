@@ -190,6 +190,44 @@ def test_walk_exit_time_bias_is_order_sqrt_dt(orc):
         assert abs(b / math.sqrt(dt) - 0.5826 * 2.0 / d) < 0.15 + 4 * se / math.sqrt(dt), bias
 
 
+def test_boundary_corrected_walk_removes_the_sqrt_dt_bias(orc):
+    """Gobet-Menozzi boundary shift (the corrected stopped-Euler schemes that
+    Sec. 2.1 points to): stopping once X leaves D shrunk by c0 sigma sqrt(dt),
+    c0 = -zeta(1/2)/sqrt(2 pi), cancels the first-order overshoot term.  Exit
+    time from the 3-D unit ball, u = (1 - |x|^2)/3, dt = 4e-3, where the plain
+    test is biased by about 0.5826 sqrt(dt) 2/3 = 0.025: the corrected
+    estimate must sit within 4 SE plus an O(dt) allowance of the closed form
+    and remove most of the plain bias (an outward shift or a wrong constant
+    fails both)."""
+    assert orc.GOBET_MENOZZI_C0 == pytest.approx(-special.zeta(0.5) / math.sqrt(2 * math.pi), rel=1e-15)
+    prob = LinearProblem(ball(3), 1.0, [zero_fun()] * 3, zero_fun(), const_fun(1.0), zero_fun())
+    x = np.array([[0.3, 0.0, 0.0], [0.0, 0.6, 0.0]])
+    exact = (1.0 - (x ** 2).sum(axis=1)) / 3.0
+    dt = 4e-3
+    n = np.array([200000, 200000])
+    plain = orc.walk(prob, x, n, dt, 11)
+    corr = orc.walk(prob, x, n, dt, 11, boundary_shift=orc.GOBET_MENOZZI_C0)
+    b_plain = plain["mean"] - exact
+    b_corr = corr["mean"] - exact
+    assert np.all(b_plain > 10 * plain["se"]), b_plain
+    assert np.all(np.abs(b_corr) < 4 * corr["se"] + 0.5 * dt), (b_corr, corr["se"])
+    assert np.all(np.abs(b_corr) < 0.25 * b_plain), (b_corr, b_plain)
+
+
+def test_boundary_corrected_walk_harmonic_data_in_the_square(orc):
+    """The same correction in a box (every face moved inward): harmonic data
+    g = e^x sin y on [0,1]^2 (u = g) at dt = 1e-2, where the plain test is off
+    by tens of SE near the face y = 1."""
+    w = CF.c1()
+    nd = w.nodes[[2, 13]]
+    exact = CF.c1_exact(nd)
+    n = np.array([100000, 100000])
+    plain = orc.walk(w.problem, nd, n, 1e-2, 3)
+    corr = orc.walk(w.problem, nd, n, 1e-2, 3, boundary_shift=orc.GOBET_MENOZZI_C0)
+    assert np.max(np.abs(plain["mean"] - exact) / plain["se"]) > 10
+    assert np.all(np.abs(corr["mean"] - exact) < 4 * corr["se"] + 1e-2 * 0.5)
+
+
 def test_walk_exit_time_ball(orc):
     """f = 1, g = 0, c = 0: the estimator is E[n dt] -> (1 - |x|^2)/d."""
     for d, x0 in ((2, [0.0, 0.0]), (3, [0.3, 0.0, 0.0])):
