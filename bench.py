@@ -281,9 +281,59 @@ def run(args):
                      "ops_per_path_step": OPS_PER_PS_ADJ if dominant == "adjoint" else OPS_PER_PS_FWD,
                      "launch_ms": dur * 1e3},
     }
+    if args.extras:
+        out["other_workloads"] = other_workloads(pdd, dev)
     if args.cpu_baseline:
         out["cpu_baseline"], out["fp32_vs_fp64_oracle"] = cpu_baseline(w, args.cpu_seconds, pdd, coefs, dev)
     return out
+
+
+def other_workloads(pdd, dev):
+    """Throughput of the other synthetic workloads (FP32 stepping, default
+    schedule, cached graphs; one warm-up call each): C3's 4096-node batch
+    over 8 layouts with variance-targeted budgets, C2's drift/killing/source
+    problem on the disk (5e4 of its 1e6 paths per node), C4's KPP branching
+    estimator (1e4 of its 1e5 trees per point)."""
+    import torch
+    from workloads import configs as CF
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    res = {}
+    parts = CF.c3()
+    subs = [(p.problem, torch.tensor(p.nodes, device=dev), p.paths, p.dt, p.seed) for p in parts]
+
+    def run_c3():
+        return [pdd.mc_interface(P, nd, pa, dt, sd, precision="fp32") for P, nd, pa, dt, sd in subs]
+
+    rs, el = timed(run_c3)
+    ps = sum(float(r["steps"].sum().item()) for r in rs)
+    nn = sum(len(p.paths) for p in parts)
+    res["c3_batch"] = {"nodes": nn, "paths": int(sum(int(p.paths.sum()) for p in parts)), "path_steps": ps,
+                       "seconds": el, "path_steps_per_s": ps / el, "nodes_per_s": nn / el}
+    log(f"bench: C3 batch: {nn} nodes in {el * 1e3:.1f} ms, {ps / el:.3e} path-steps/s")
+    c2 = CF.c2(scale=0.05)
+    n2 = torch.tensor(c2.nodes, device=dev)
+    r2, el2 = timed(lambda: pdd.mc_interface(c2.problem, n2, c2.paths, c2.dt, c2.seed, precision="fp32"))
+    ps2 = float(r2["steps"].sum().item())
+    res["c2"] = {"nodes": len(c2.paths), "paths_per_node": int(c2.paths[0]), "path_steps": ps2, "seconds": el2,
+                 "path_steps_per_s": ps2 / el2}
+    log(f"bench: C2: {ps2:.3e} path-steps in {el2 * 1e3:.1f} ms, {ps2 / el2:.3e} path-steps/s")
+    c4 = CF.c4(scale=0.1)
+    p4 = torch.tensor(c4.points, device=dev)
+    r4, el4 = timed(lambda: pdd.branching_eval(c4.problem, p4, c4.trees, c4.seed, precision="fp32"))
+    segs = float(r4["steps"].sum().item())
+    trees = float(len(c4.points) * c4.trees)
+    res["c4"] = {"points": len(c4.points), "trees_per_point": c4.trees, "segments": segs, "seconds": el4,
+                 "trees_per_s": trees / el4, "segments_per_s": segs / el4}
+    log(f"bench: C4: {trees:.3e} trees, {segs:.3e} segments in {el4 * 1e3:.1f} ms")
+    return res
 
 
 def cpu_baseline(w, seconds, pdd, coefs, dev):
@@ -346,6 +396,7 @@ def main():
     ap.add_argument("--se-nodes", type=int, default=1024, help="nodes in the SE-target run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--no-extras", dest="extras", action="store_false", help="skip the C2/C3/C4 throughput lines")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="use the default schedule")
     ap.add_argument("--schedule-adj", default="", help="blocks_per_cu,refill_groups,chunk_paths (skips tuning)")
     ap.add_argument("--schedule-fwd", default="", help="as --schedule-adj, for the forward kernel")

@@ -158,6 +158,13 @@ typedef struct {
                              0 = autotuned/default */
   int32_t blocks_per_cu;  /* persistent grid size per compute unit; 0 = autotuned/default */
   int32_t refill_groups;  /* step groups between lane refills; 0 = autotuned/default (3) */
+  int32_t boundary_correction; /* linear walks: 0 = plain exit test (X outside D after a step);
+                                  1 = boundary-corrected test of Gobet and Menozzi (Sec. 2.1 points to
+                                  their schemes): the path stops once X leaves D shrunk by
+                                  c0 sigma sqrt(dt), c0 = -zeta(1/2)/sqrt(2 pi) ~ 0.5826, which removes
+                                  the O(sqrt dt) overshoot bias; g is still taken at the projection of
+                                  X onto the boundary of D.  Ignored by pdd_branching_eval. */
+  int32_t reserved;       /* must be 0 */
 } pdd_options;
 
 /* Per-node result: mean and sum of squared deviations (variance = m2/(n-1),

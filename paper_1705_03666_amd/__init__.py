@@ -75,7 +75,8 @@ _SCHED = {"auto": A.PDD_SCHED_AUTO, "persistent": A.PDD_SCHED_PERSISTENT, "graph
 
 
 def _options(precision: str, layout: Optional[str], max_steps: int, schedule: str, chunk_paths: int,
-             blocks_per_cu: int, refill_groups: int, dump_phi=None, dump_steps=None) -> A.pdd_options:
+             blocks_per_cu: int, refill_groups: int, dump_phi=None, dump_steps=None,
+             boundary_correction: bool = False) -> A.pdd_options:
     if precision not in _PREC:
         raise ValueError(f"precision must be one of {list(_PREC)}")
     if layout is None:
@@ -90,6 +91,8 @@ def _options(precision: str, layout: Optional[str], max_steps: int, schedule: st
     o.chunk_paths = int(chunk_paths)
     o.blocks_per_cu = int(blocks_per_cu)
     o.refill_groups = int(refill_groups)
+    o.boundary_correction = 1 if boundary_correction else 0
+    o.reserved = 0
     return o
 
 
@@ -178,7 +181,8 @@ def _nodes_tensor(nodes, ndim: int) -> torch.Tensor:
 def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str = "fp32",
                  layout: Optional[str] = None, max_steps: int = 0, dump: bool = False, schedule: str = "auto",
                  chunk_paths: int = 0, blocks_per_cu: int = 0, refill_groups: int = 0,
-                 coefs: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+                 coefs: Optional[Dict[str, torch.Tensor]] = None,
+                 boundary_correction: bool = False) -> Dict[str, torch.Tensor]:
     """Monte Carlo value of the linear problem at every node (pdd_mc_interface).
     Returns device tensors mean, m2, n, steps, censored, var, se (and, with
     dump=True, the per-path values `phi` and step counts `path_steps`,
@@ -197,7 +201,8 @@ def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str
         total = int(ph.sum())
         dphi = torch.empty(max(total, 1), dtype=torch.float64, device="cuda")
         dst = torch.empty(max(total, 1), dtype=torch.int64, device="cuda")
-    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups, dphi, dst)
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups, dphi, dst,
+                 boundary_correction)
     st = library().pdd_mc_interface(C.byref(p), nt.data_ptr() if n else None, n,
                                     ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt), int(seed) & (2 ** 64 - 1),
                                     C.byref(o), raw.data_ptr(), _stream_handle())
@@ -213,7 +218,7 @@ def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str
 def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = "fp32",
                layout: Optional[str] = None, max_steps: int = 0, schedule: str = "auto", chunk_paths: int = 0,
                blocks_per_cu: int = 0, refill_groups: int = 0, coefs: Optional[Dict[str, torch.Tensor]] = None,
-               with_stats: bool = False) -> Dict[str, torch.Tensor]:
+               with_stats: bool = False, boundary_correction: bool = False) -> Dict[str, torch.Tensor]:
     """Gradient of sum_i w_i u_i with respect to the coefficient arrays of g, f
     and c (pdd_mc_adjoint).  Returns device tensors g_coef, g_poly, f_coef,
     f_poly, c_coef, c_poly (and the per-node statistics with with_stats)."""
@@ -243,7 +248,8 @@ def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = 
         grads[name + "_coef"] = grads[name + "_coef"][:T]
         grads[name + "_poly"] = grads[name + "_poly"][:M]
     raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda") if with_stats else None
-    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups)
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups,
+                 boundary_correction=boundary_correction)
     st = library().pdd_mc_adjoint(C.byref(p), nt.data_ptr() if n else None, n,
                                   ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt), int(seed) & (2 ** 64 - 1),
                                   C.byref(o), wt.data_ptr() if n else None, gstruct,
@@ -270,7 +276,8 @@ def param_layout(problem):
 def mc_value_jacobian(problem, nodes, paths, dt: float, seed: int = 0, precision: str = "fp32",
                       layout: Optional[str] = None, max_steps: int = 0, schedule: str = "auto", chunk_paths: int = 0,
                       blocks_per_cu: int = 0, refill_groups: int = 0,
-                      coefs: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+                      coefs: Optional[Dict[str, torch.Tensor]] = None,
+                      boundary_correction: bool = False) -> Dict[str, torch.Tensor]:
     """Per-node statistics and the Jacobian d mean_i / d coefficients in one
     pass (pdd_mc_value_jacobian).  Returns the statistics of mc_interface plus
     `jac` [n, n_params] (column blocks in `param_layout(problem)` order)."""
@@ -287,7 +294,8 @@ def mc_value_jacobian(problem, nodes, paths, dt: float, seed: int = 0, precision
         raise PddError("pdd_param_count rejected the problem")
     raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
     jac = torch.zeros((max(n, 1), max(npar, 1)), dtype=torch.float64, device="cuda")
-    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups)
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups,
+                 boundary_correction=boundary_correction)
     st = library().pdd_mc_value_jacobian(C.byref(p), nt.data_ptr() if n else None, n,
                                          ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt),
                                          int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(), jac.data_ptr(),

@@ -458,6 +458,8 @@ pdd_status validate_linear(const LinearPlanArgs& a) {
   if (o.chunk_paths < 0 || o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.refill_groups < 0 || o.refill_groups > 64)
     return fail(PDD_ERR_INVALID_ARG, "schedule override out of range");
   if (o.schedule < PDD_SCHED_AUTO || o.schedule > PDD_SCHED_PERSISTENT_GRAPH) return fail(PDD_ERR_INVALID_ARG, "unknown schedule");
+  if (o.boundary_correction < 0 || o.boundary_correction > 1 || o.reserved != 0)
+    return fail(PDD_ERR_INVALID_ARG, "boundary_correction must be 0 or 1 and reserved 0");
   if (a.n_nodes > 0) {
     if ((s = check_device_ptr(a.nodes, "nodes_dev")) != PDD_OK) return s;
     if (!a.adjoint || a.out || a.jac) if ((s = check_device_ptr(a.out, "out_dev")) != PDD_OK) return s;
@@ -543,6 +545,22 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   lp.rad2 = P.domain.radius * P.domain.radius;
   lp.radf = (float)lp.rad;
   lp.rad2f = (float)lp.rad2;
+  // exit-test domain: D, or D shrunk by c0 sigma sqrt(dt) (Gobet-Menozzi shift;
+  // c0 = -zeta(1/2)/sqrt(2 pi), zeta(1/2) = -1.4603545088095868...)
+  {
+    const double delta = o.boundary_correction ? (1.4603545088095868 / std::sqrt(2.0 * M_PI)) * P.sigma * std::sqrt(a.dt)
+                                               : 0.0;
+    double trad = P.domain.radius - delta;
+    if (trad < 0.0) trad = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      lp.tlo[k] = P.domain.lo[k] + delta;
+      lp.thi[k] = P.domain.hi[k] - delta;
+      lp.tlof[k] = (float)lp.tlo[k];
+      lp.thif[k] = (float)lp.thi[k];
+    }
+    lp.trad2 = trad * trad;
+    lp.trad2f = (float)lp.trad2;
+  }
   lp.dt = a.dt;
   lp.sdt = P.sigma * std::sqrt(a.dt);
   lp.dtf = (float)lp.dt;

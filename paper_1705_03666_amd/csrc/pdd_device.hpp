@@ -290,6 +290,29 @@ __device__ __forceinline__ Dom<double> make_dom<double>(const LinearParams& P) {
   return D;
 }
 
+// Domain of the exit test: D, or D shrunk for the boundary-corrected scheme
+// (only the fields the test reads: kind, lo, hi, ctr, rad2).
+template <typename R>
+__device__ __forceinline__ Dom<R> make_test_dom(const LinearParams& P);
+template <>
+__device__ __forceinline__ Dom<float> make_test_dom<float>(const LinearParams& P) {
+  Dom<float> D;
+  D.kind = P.dom_kind;
+  for (int k = 0; k < 3; ++k) { D.lo[k] = P.tlof[k]; D.hi[k] = P.thif[k]; D.ctr[k] = P.ctrf[k]; }
+  D.rad = P.radf;
+  D.rad2 = P.trad2f;
+  return D;
+}
+template <>
+__device__ __forceinline__ Dom<double> make_test_dom<double>(const LinearParams& P) {
+  Dom<double> D;
+  D.kind = P.dom_kind;
+  for (int k = 0; k < 3; ++k) { D.lo[k] = P.tlo[k]; D.hi[k] = P.thi[k]; D.ctr[k] = P.ctr[k]; }
+  D.rad = P.rad;
+  D.rad2 = P.trad2;
+  return D;
+}
+
 template <typename R, int DIM>
 __device__ __forceinline__ bool inside(const Dom<R>& D, const R* x) {
   if (D.kind == DOM_BOX) {

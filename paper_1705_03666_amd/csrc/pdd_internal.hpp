@@ -42,6 +42,9 @@ struct LinearParams {
   int64_t max_steps;
   uint32_t key0, key1;
   int32_t has_b, has_c, has_f, pad_flags;   // b, c, f not identically zero
+  // domain of the exit test (D itself, or D shrunk for the boundary-corrected scheme)
+  double tlo[3], thi[3], trad2;
+  float tlof[3], thif[3], trad2f;
   DevFun b[3], c, f, g;
   const DevFactor* fac;
   const double* cd;

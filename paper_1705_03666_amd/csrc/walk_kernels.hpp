@@ -201,7 +201,8 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   __shared__ uint32_t gmono[ADJ ? kGMono : 1];
   R* const rec = &area[wid][0];
 
-  const Dom<R> D = make_dom<R>(P);
+  const Dom<R> D = make_dom<R>(P);          // projection of exit points
+  const Dom<R> Dt = make_test_dom<R>(P);    // exit test
   const R dt = dt_of<R>(P);
   const R sdt = sdt_of<R>(P);
   const uint32_t max_steps = (uint32_t)P.max_steps;
@@ -232,7 +233,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
     R x0[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) x0[k] = to_r<R>(P.nodes[(size_t)node * DIM + k]);
-    const bool node_in = inside<R, DIM>(D, x0);
+    const bool node_in = inside<R, DIM>(Dt, x0);
 
     uint32_t path = it.p0 + (uint32_t)lane;
     bool alive = (path < pend) && node_in;
@@ -450,7 +451,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
               for (int k = 0; k < DIM; ++k) X[k] = X[k] + sdt * z[s * DIM + k];
             }
             ++n;
-            if (!inside<R, DIM>(D, X)) {
+            if (!inside<R, DIM>(Dt, X)) {
               alive = false;
               fin = true;
             }
@@ -543,10 +544,11 @@ k_walk_plain(const LinearParams P, int node, uint32_t n_paths, ItemStat* __restr
   using NZr = Normals<double, LAYOUT>;
   constexpr int PB = NZr::kPerBlock;
   const Dom<double> D = make_dom<double>(P);
+  const Dom<double> Dt = make_test_dom<double>(P);
   double x0[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) x0[k] = P.nodes[(size_t)node * DIM + k];
-  const bool node_in = inside<double, DIM>(D, x0);
+  const bool node_in = inside<double, DIM>(Dt, x0);
   double wn = 0.0, wmean = 0.0, wm2 = 0.0;
   int64_t lsteps = 0, lcens = 0;
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n_paths; p += gridDim.x * blockDim.x) {
@@ -584,7 +586,7 @@ k_walk_plain(const LinearParams P, int node, uint32_t n_paths, ItemStat* __restr
           X[k] = X[k] + bv[k] * P.dt + P.sdt * zk;
         }
         ++n;
-        if (!inside<double, DIM>(D, X)) break;
+        if (!inside<double, DIM>(Dt, X)) break;
       }
     }
     double xp[3];
@@ -641,11 +643,12 @@ k_walk_plain_adj(const LinearParams P, int node, uint32_t n_paths, ItemStat* __r
   constexpr int NM = GradedLex<DIM, DFC>::N;
   constexpr int NP = NT + NM;
   const Dom<double> D = make_dom<double>(P);
+  const Dom<double> Dt = make_test_dom<double>(P);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   double x0[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) x0[k] = P.nodes[(size_t)node * DIM + k];
-  const bool node_in = inside<double, DIM>(D, x0);
+  const bool node_in = inside<double, DIM>(Dt, x0);
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool have = p < n_paths;
 
@@ -709,7 +712,7 @@ k_walk_plain_adj(const LinearParams P, int node, uint32_t n_paths, ItemStat* __r
         X[k] = X[k] + bv[k] * P.dt + P.sdt * zk;
       }
       ++n;
-      if (!inside<double, DIM>(D, X)) break;
+      if (!inside<double, DIM>(Dt, X)) break;
     }
   }
   double xp[3];

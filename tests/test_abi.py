@@ -42,7 +42,7 @@ def test_struct_sizes_match_header_layout(abi):
     assert C.sizeof(abi.pdd_factor) == 32
     assert C.sizeof(abi.pdd_fun) == 40
     assert C.sizeof(abi.pdd_domain) == 8 + 10 * 8
-    assert C.sizeof(abi.pdd_options) == 48
+    assert C.sizeof(abi.pdd_options) == 56
 
 
 def _problem(abi, **kw):

@@ -100,6 +100,52 @@ def test_fp64_matches_oracle_per_path(pdd, orc, case, layout):
     stats_close(g, o)
 
 
+@pytest.mark.parametrize("case", ["c1", "c5", "ball3_c3"])
+def test_boundary_corrected_fp64_matches_oracle_per_path(pdd, orc, case):
+    """Gobet-Menozzi shifted exit test: per-path values and exit steps equal the
+    oracle's on the same streams (batched and plain kernels), and the shift is
+    in effect (the plain test exits later)."""
+    P, nodes, dt = CASES[case]()
+    paths = np.array([(53 + 37 * i) % 300 + 100 for i in range(len(nodes))], np.int64)
+    log(f"boundary-corrected per-path: case={case} nodes={len(nodes)} paths={paths.sum()}")
+    o = orc.walk(P, nodes, paths, dt, 7, layout=orc.PAIR52, dump=True, boundary_shift=orc.GOBET_MENOZZI_C0)
+    for prec, kw in (("fp64", dict(schedule="persistent", chunk_paths=100)), ("fp64", dict(schedule="graph")),
+                     ("fp64_plain", {})):
+        g = pdd.mc_interface(P, nodes, paths, dt, 7, precision=prec, layout="pair52", dump=True,
+                             boundary_correction=True, **kw)
+        torch.cuda.synchronize()
+        assert np.all(g["path_steps"].cpu().numpy() == o["path_steps"]), (prec, kw)
+        nbad, worst = per_path_close(g["phi"].cpu().numpy(), o["phi"])
+        assert nbad == 0, (prec, kw, nbad, worst)
+        stats_close(g, o)
+    plain = orc.walk(P, nodes, paths, dt, 7, layout=orc.PAIR52)
+    assert plain["steps"].sum() > o["steps"].sum()
+
+
+def test_boundary_corrected_adjoint_and_fp32(pdd, orc):
+    """The corrected test in the adjoint (batched and plain FP64 against the
+    oracle) and in FP32 stepping (within 4 SE of the FP64 oracle)."""
+    P, nodes = _c5_small(2, 4)
+    paths = np.array([150, 64, 201, 90], np.int64)
+    dt = 1e-2
+    w = np.array([0.5, -1.0, 2.0, 0.25])
+    o = orc.walk_adjoint(P, nodes, paths, dt, 21, w, boundary_shift=orc.GOBET_MENOZZI_C0)
+    for prec in ("fp64", "fp64_plain"):
+        g = pdd.mc_adjoint(P, nodes, paths, dt, 21, w, precision=prec, layout="pair52", schedule="persistent",
+                           chunk_paths=50, with_stats=True, boundary_correction=True)
+        torch.cuda.synchronize()
+        for k in ("g_coef", "g_poly", "f_coef", "f_poly", "c_coef", "c_poly"):
+            got, want = g[k].cpu().numpy(), o[k]
+            assert np.allclose(got, want, rtol=1e-10, atol=1e-12 * max(1.0, np.abs(want).max())), (prec, k)
+        stats_close(g["stats"], o["stats"])
+    paths = np.full(4, 20000, np.int64)
+    of = orc.walk(P, nodes, paths, 2e-3, 5, layout=orc.QUAD24, boundary_shift=orc.GOBET_MENOZZI_C0)
+    gf = pdd.mc_interface(P, nodes, paths, 2e-3, 5, precision="fp32", boundary_correction=True)
+    torch.cuda.synchronize()
+    gm, gs = gf["mean"].cpu().numpy(), gf["se"].cpu().numpy()
+    assert np.all(np.abs(gm - of["mean"]) <= 4.0 * np.sqrt(gs ** 2 + of["se"] ** 2) + 1e-5)
+
+
 def test_degenerate_nodes_and_budgets(pdd, orc):
     w = CF.c1()
     nodes = np.array([[1.2, 0.3], [0.0, 0.5], [0.5, 0.5], [0.3, 0.3], [0.5, 1e-9]])
