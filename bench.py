@@ -325,6 +325,21 @@ def other_workloads(pdd, dev):
     res["c2"] = {"nodes": len(c2.paths), "paths_per_node": int(c2.paths[0]), "path_steps": ps2, "seconds": el2,
                  "path_steps_per_s": ps2 / el2}
     log(f"bench: C2: {ps2:.3e} path-steps in {el2 * 1e3:.1f} ms, {ps2 / el2:.3e} path-steps/s")
+    # boundary-corrected exit test vs the plain one: C1 (harmonic data, exact
+    # u = g) at dt = 4e-3 with 1e6 FP32 paths per node; error in SE units
+    c1 = CF.c1(scale=100.0, dt=4e-3)
+    n1 = torch.tensor(c1.nodes, device=dev)
+    exact = CF.c1_exact(c1.nodes)
+    acc = {}
+    for name, corr in (("plain", False), ("corrected", True)):
+        r1, el1 = timed(lambda: pdd.mc_interface(c1.problem, n1, c1.paths, c1.dt, c1.seed, precision="fp32",
+                                                 boundary_correction=corr))
+        err = np.abs(r1["mean"].cpu().numpy() - exact) / r1["se"].cpu().numpy()
+        acc[name] = {"max_err_se": float(err.max()), "mean_err_se": float(err.mean()),
+                     "path_steps_per_s": float(r1["steps"].sum().item()) / el1}
+    res["c1_boundary_correction_dt_4e-3"] = acc
+    log(f"bench: C1 dt=4e-3 error vs exact (SE units): plain max {acc['plain']['max_err_se']:.1f}, "
+        f"corrected max {acc['corrected']['max_err_se']:.1f}")
     c4 = CF.c4(scale=0.1)
     p4 = torch.tensor(c4.points, device=dev)
     r4, el4 = timed(lambda: pdd.branching_eval(c4.problem, p4, c4.trees, c4.seed, precision="fp32"))

@@ -421,6 +421,88 @@ int orc_walk(const orc_linear* P, const double* nodes, int64_t n_nodes, const in
 }
 
 /* ------------------------------------------------------------------------ */
+/* Walk on Spheres.  Distance to the boundary of the open set D: ball
+ * R - |x - c|, box min_k min(x_k - lo_k, hi_k - x_k) (negative outside). */
+static double boundary_distance(const orc_domain* D, const double* x) {
+  if (D->kind == ORC_BALL) {
+    double r2 = 0.0;
+    for (int k = 0; k < D->dim; ++k) {
+      double v = x[k] - D->center[k];
+      r2 += v * v;
+    }
+    return D->radius - sqrt(r2);
+  }
+  double m = INFINITY;
+  for (int k = 0; k < D->dim; ++k) {
+    double lo = x[k] - D->lo[k], hi = D->hi[k] - x[k];
+    if (lo < m) m = lo;
+    if (hi < m) m = hi;
+  }
+  return m;
+}
+
+static int fun_is_zero(const orc_fun* F) { return F->n_terms == 0 && F->n_mono == 0; }
+
+static void wos_node(void* vctx, int64_t i, int worker) {
+  (void)worker;
+  walk_ctx* C = (walk_ctx*)vctx;
+  const orc_linear* P = C->P;
+  const orc_domain* D = &P->dom;
+  int d = D->dim;
+  double eps = C->dt;
+  orc_stat s = {0.0, 0.0, 0, 0, 0};
+  for (int64_t p = 0; p < C->paths[i]; ++p) {
+    double X[3] = {0.0, 0.0, 0.0}, Xp[3];
+    for (int k = 0; k < d; ++k) X[k] = C->nodes[i * d + k];
+    int64_t n = 0;
+    int censored = 0;
+    if (orc_inside(D, X)) {
+      for (;;) {
+        double r = boundary_distance(D, X);
+        if (r < eps) break;
+        if (n == C->max_steps) { censored = 1; break; }
+        double zeta[3], z2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+          zeta[k] = walk_normal(C->key, C->layout, node_id(C, i), (uint32_t)p, (uint64_t)n * d + k);
+          z2 += zeta[k] * zeta[k];
+        }
+        double zn = sqrt(z2);
+        for (int k = 0; k < d; ++k) X[k] = X[k] + r * (zeta[k] / zn);
+        n += 1;
+      }
+    }
+    orc_project(D, X, Xp);
+    double phi = orc_fun_eval(&P->g, Xp);
+    welford_push(&s, phi);
+    s.steps += n;
+    s.censored += censored;
+    if (C->dump_phi) C->dump_phi[C->offsets[i] + p] = phi;
+    if (C->dump_steps) C->dump_steps[C->offsets[i] + p] = n;
+  }
+  C->out[i] = s;
+}
+
+int orc_wos(const orc_linear* P, const double* nodes, int64_t n_nodes, const int64_t* paths,
+            double eps, uint64_t seed, int layout, int64_t max_steps, int n_threads,
+            orc_stat* out, double* dump_phi, int64_t* dump_steps) {
+  if ((P->dom.kind != ORC_BOX && P->dom.kind != ORC_BALL) || P->dom.dim < 1 || P->dom.dim > 3 || !(eps > 0.0))
+    return -1;
+  for (int k = 0; k < P->dom.dim; ++k)
+    if (!fun_is_zero(&P->b[k])) return -1;
+  if (!fun_is_zero(&P->c) || !fun_is_zero(&P->f)) return -1;
+  walk_ctx C;
+  memset(&C, 0, sizeof(C));
+  C.P = P; C.nodes = nodes; C.paths = paths; C.dt = eps; C.layout = layout;
+  C.max_steps = max_steps; C.out = out; C.dump_phi = dump_phi; C.dump_steps = dump_steps;
+  make_key(seed, C.key);
+  int64_t* off = prefix_offsets(paths, n_nodes);
+  C.offsets = off;
+  run_pool(n_threads, n_nodes, wos_node, &C);
+  free(off);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 static int fun_params(const orc_fun* F) { return F->n_terms + F->n_mono; }
 
 static void adjoint_node(void* vctx, int64_t i, int worker) {

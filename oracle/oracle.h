@@ -100,6 +100,18 @@ int orc_walk(const orc_linear* P, const double* nodes, int64_t n_nodes, const in
              double dt, uint64_t seed, int layout, int64_t max_steps, int n_threads,
              orc_stat* out, double* dump_phi, int64_t* dump_steps, const int64_t* node_ids);
 
+/* ---- Walk on Spheres (the method the paper recommends for Laplace's
+   equation with Dirichlet data, Sec. 2.1): b = c = f = 0, any sigma.
+   Jump n of path p moves X by r_n theta_n, r_n = dist(X, boundary of D),
+   theta_n = zeta / |zeta| with zeta the walk Gaussians nd .. nd+d-1 of the
+   path (same counters as orc_walk); it stops at the first r < eps (before
+   jumping) with phi = g(P(X)); steps = number of jumps.  A path reaching
+   max_steps jumps is censored with phi = g(P(X)).  A node outside D gives
+   phi = g(P(node)), 0 jumps.  Returns -1 if b, c or f is not zero. */
+int orc_wos(const orc_linear* P, const double* nodes, int64_t n_nodes, const int64_t* paths,
+            double eps, uint64_t seed, int layout, int64_t max_steps, int n_threads,
+            orc_stat* out, double* dump_phi, int64_t* dump_steps);
+
 /* gradient of sum_i w_i * mean_i with respect to the coefficient arrays
    (accumulated into caller-zeroed arrays; NULL pointers are skipped) */
 int orc_walk_adjoint(const orc_linear* P, const double* nodes, int64_t n_nodes, const int64_t* paths,

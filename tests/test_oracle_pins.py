@@ -228,6 +228,51 @@ def test_boundary_corrected_walk_harmonic_data_in_the_square(orc):
     assert np.all(np.abs(corr["mean"] - exact) < 4 * corr["se"] + 1e-2 * 0.5)
 
 
+def test_walk_on_spheres_reproduces_harmonic_data_in_the_square(orc):
+    """Walk on Spheres (recommended in Sec. 2.1 for Laplace with Dirichlet
+    data): u = g = e^x sin y on [0,1]^2 within 4 SE plus the eps-shell bias
+    (at most eps |grad g|); the jump count grows like log(1/eps)."""
+    w = CF.c1()
+    nd = w.nodes[[1, 7, 14]]
+    exact = CF.c1_exact(nd)
+    eps = 1e-4
+    r = orc.wos(w.problem, nd, np.full(3, 100000), eps, 5)
+    assert np.all(np.abs(r["mean"] - exact) < 4 * r["se"] + eps * math.e * math.sqrt(2.0))
+    jumps = r["steps"] / r["n"]
+    r2 = orc.wos(w.problem, nd, np.full(3, 20000), 1e-2, 5)
+    more = jumps - r2["steps"] / r2["n"]
+    # log(1e-2 / 1e-4) = 4.6: the extra jumps per path are of that order
+    assert np.all((more > 2.0) & (more < 12.0)), (jumps, more)
+
+
+def test_walk_on_spheres_exit_law_from_the_centre_is_uniform(orc):
+    """From the centre of the unit ball the first jump lands on the sphere,
+    uniformly: E[x^4] = 1/5 and E[x^2 y^2] = 1/15 on S^2 (moments of the
+    uniform law), with exactly one jump per path."""
+    prob = LinearProblem(ball(3), 1.0, [zero_fun()] * 3, zero_fun(), zero_fun(),
+                         make_fun([(1.0, [factor("pow", 0, power=4)])]))
+    r = orc.wos(prob, np.zeros((1, 3)), np.array([200000]), 1e-6, 9)
+    assert r["steps"][0] == r["n"][0]
+    assert abs(r["mean"][0] - 0.2) < 4 * r["se"][0]
+    prob.g = make_fun([(1.0, [factor("pow", 0, power=2), factor("pow", 1, power=2)])])
+    r = orc.wos(prob, np.zeros((1, 3)), np.array([200000]), 1e-6, 10)
+    assert abs(r["mean"][0] - 1.0 / 15.0) < 4 * r["se"][0]
+
+
+def test_walk_on_spheres_matches_the_poisson_kernel(orc):
+    """Off-centre start in the unit ball: the exit law is the harmonic
+    measure, so E[g(X_tau)] is the Poisson integral of g, here for the
+    non-harmonic g = x^4 at x0 = (0.5, 0, 0), by 1-D quadrature."""
+    a = 0.5
+    kern = lambda t: (1 - a * a) / (4 * math.pi * (1 + a * a - 2 * a * math.cos(t)) ** 1.5)
+    want = 2 * math.pi * integrate.quad(lambda t: kern(t) * math.cos(t) ** 4 * math.sin(t), 0, math.pi,
+                                        epsabs=1e-13)[0]
+    prob = LinearProblem(ball(3), 1.0, [zero_fun()] * 3, zero_fun(), zero_fun(),
+                         make_fun([(1.0, [factor("pow", 0, power=4)])]))
+    r = orc.wos(prob, np.array([[a, 0.0, 0.0]]), np.array([300000]), 1e-5, 13)
+    assert abs(r["mean"][0] - want) < 4 * r["se"][0] + 4e-5, (r["mean"][0], want, r["se"][0])
+
+
 def test_walk_exit_time_ball(orc):
     """f = 1, g = 0, c = 0: the estimator is E[n dt] -> (1 - |x|^2)/d."""
     for d, x0 in ((2, [0.0, 0.0]), (3, [0.3, 0.0, 0.0])):
