@@ -312,12 +312,38 @@ def other_workloads(pdd, dev):
     def run_c3():
         return [pdd.mc_interface(P, nd, pa, dt, sd, precision="fp32") for P, nd, pa, dt, sd in subs]
 
+    from oracle import fun_eval  # exact u = g for the harmonic data of C3 (reference values only)
+
+    def err_se(rs_):
+        z = []
+        for p, r in zip(parts, rs_):
+            exact = np.array([fun_eval(p.problem.g, p.problem.ndim, x) for x in p.nodes])
+            z.append(np.abs(r["mean"].cpu().numpy() - exact) / r["se"].cpu().numpy())
+        z = np.concatenate(z)
+        return float(z.max()), float(np.sqrt(np.mean(z ** 2)))
+
     rs, el = timed(run_c3)
     ps = sum(float(r["steps"].sum().item()) for r in rs)
     nn = sum(len(p.paths) for p in parts)
+    zmax, zrms = err_se(rs)
     res["c3_batch"] = {"nodes": nn, "paths": int(sum(int(p.paths.sum()) for p in parts)), "path_steps": ps,
-                       "seconds": el, "path_steps_per_s": ps / el, "nodes_per_s": nn / el}
-    log(f"bench: C3 batch: {nn} nodes in {el * 1e3:.1f} ms, {ps / el:.3e} path-steps/s")
+                       "seconds": el, "path_steps_per_s": ps / el, "nodes_per_s": nn / el,
+                       "err_vs_exact_max_se": zmax, "err_vs_exact_rms_se": zrms}
+    log(f"bench: C3 batch (Euler): {nn} nodes in {el * 1e3:.1f} ms, {ps / el:.3e} path-steps/s, "
+        f"error vs exact max {zmax:.1f} SE, rms {zrms:.1f} SE")
+
+    # the same batch by walk on spheres (b = c = f = 0), eps = 1e-4
+    def run_c3_wos():
+        return [pdd.wos_interface(P, nd, pa, 1e-4, sd, precision="fp32") for P, nd, pa, dt, sd in subs]
+
+    rw, elw = timed(run_c3_wos)
+    jumps = sum(float(r["steps"].sum().item()) for r in rw)
+    zmax, zrms = err_se(rw)
+    res["c3_batch_walk_on_spheres"] = {"eps": 1e-4, "jumps": jumps, "seconds": elw, "jumps_per_s": jumps / elw,
+                                       "nodes_per_s": nn / elw, "err_vs_exact_max_se": zmax,
+                                       "err_vs_exact_rms_se": zrms}
+    log(f"bench: C3 batch (walk on spheres): {elw * 1e3:.1f} ms, {jumps / elw:.3e} jumps/s, "
+        f"error vs exact max {zmax:.1f} SE, rms {zrms:.1f} SE")
     c2 = CF.c2(scale=0.05)
     n2 = torch.tensor(c2.nodes, device=dev)
     r2, el2 = timed(lambda: pdd.mc_interface(c2.problem, n2, c2.paths, c2.dt, c2.seed, precision="fp32"))

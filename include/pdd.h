@@ -197,6 +197,21 @@ pdd_status pdd_mc_interface(const pdd_linear_problem* problem, const double* nod
                             const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
                             pdd_node_stat* out_dev, void* hip_stream);
 
+/* Walk on Spheres for Laplace's equation with Dirichlet data, the method
+ * Sec. 2.1 recommends for that case: b, c and f must be identically zero
+ * (no terms, no polynomial; else PDD_ERR_UNSUPPORTED); sigma does not
+ * matter.  Each path jumps from X to X + r theta, r = distance from X to the
+ * boundary of D, theta uniform on the unit sphere (the path's Gaussians of
+ * jump n, nd .. nd+d-1, normalised: same counters as pdd_mc_interface), and
+ * stops once r < eps, with phi = g(projection of X onto the boundary).
+ * steps in out_dev counts jumps; a path reaching options->max_steps jumps
+ * (0: 100000) is censored.  Arguments as pdd_mc_interface with eps > 0 in
+ * place of dt; precision FP32_STEP or FP64 (no plain variant), no boundary
+ * correction, no dumps of more than phi and steps. */
+pdd_status pdd_wos_interface(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                             const int64_t* paths_host, double eps, uint64_t seed, const pdd_options* options,
+                             pdd_node_stat* out_dev, void* hip_stream);
+
 /* Branching estimator (Sec. 3.1-3.2) at points_dev [n_points][dim] (device,
  * FP64), trees_per_point trees each (< 2^32).  out_dev: device [n_points];
  * steps = segments simulated, censored = trees that failed 16 draws (value 0).

@@ -215,6 +215,40 @@ def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str
     return res
 
 
+def wos_interface(problem, nodes, paths, eps: float, seed: int = 0, precision: str = "fp32",
+                 layout: Optional[str] = None, max_steps: int = 0, dump: bool = False, schedule: str = "auto",
+                 chunk_paths: int = 0, blocks_per_cu: int = 0, refill_groups: int = 0,
+                 coefs: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+    """Walk on Spheres for Laplace's equation (pdd_wos_interface): b, c, f
+    must be zero; eps is the width of the stopping shell.  Same outputs as
+    mc_interface, with steps counting jumps."""
+    _need_gpu()
+    keep = _Keep()
+    p = _linear(problem, keep, coefs)
+    nt = _nodes_tensor(nodes, problem.domain.ndim)
+    n = nt.shape[0]
+    ph = np.ascontiguousarray(np.asarray(paths, dtype=np.int64).reshape(-1))
+    if ph.shape[0] != n:
+        raise ValueError("paths must have one entry per node")
+    raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
+    dphi = dst = None
+    if dump:
+        total = int(ph.sum())
+        dphi = torch.empty(max(total, 1), dtype=torch.float64, device="cuda")
+        dst = torch.empty(max(total, 1), dtype=torch.int64, device="cuda")
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups, dphi, dst)
+    st = library().pdd_wos_interface(C.byref(p), nt.data_ptr() if n else None, n,
+                                     ph.ctypes.data_as(C.POINTER(C.c_int64)), float(eps), int(seed) & (2 ** 64 - 1),
+                                     C.byref(o), raw.data_ptr(), _stream_handle())
+    _check(st, "pdd_wos_interface")
+    res = _stats(raw[:n])
+    if dump:
+        total = int(ph.sum())
+        res["phi"], res["path_steps"] = dphi[:total], dst[:total]
+    res["_keep"] = keep
+    return res
+
+
 def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = "fp32",
                layout: Optional[str] = None, max_steps: int = 0, schedule: str = "auto", chunk_paths: int = 0,
                blocks_per_cu: int = 0, refill_groups: int = 0, coefs: Optional[Dict[str, torch.Tensor]] = None,

@@ -414,6 +414,7 @@ struct LinearPlanArgs {
   const pdd_fun_grad* grads;
   double* jac;          // value+Jacobian mode: [n_nodes][jac_ld]
   int64_t jac_ld;
+  bool wos = false;     // walk on spheres; dt holds eps
 };
 
 int64_t param_count(const pdd_linear_problem& P) {
@@ -460,6 +461,14 @@ pdd_status validate_linear(const LinearPlanArgs& a) {
   if (o.schedule < PDD_SCHED_AUTO || o.schedule > PDD_SCHED_PERSISTENT_GRAPH) return fail(PDD_ERR_INVALID_ARG, "unknown schedule");
   if (o.boundary_correction < 0 || o.boundary_correction > 1 || o.reserved != 0)
     return fail(PDD_ERR_INVALID_ARG, "boundary_correction must be 0 or 1 and reserved 0");
+  if (a.wos) {
+    auto zero = [](const pdd_fun& F) { return F.n_terms == 0 && F.poly_degree < 0; };
+    bool ok = zero(P.c) && zero(P.f);
+    for (int k = 0; k < D.dim; ++k) ok = ok && zero(P.b[k]);
+    if (!ok) return fail(PDD_ERR_UNSUPPORTED, "walk on spheres needs b = c = f = 0 (Laplace's equation)");
+    if (o.precision == PDD_FP64_PLAIN) return fail(PDD_ERR_UNSUPPORTED, "walk on spheres has no plain variant");
+    if (o.boundary_correction) return fail(PDD_ERR_INVALID_ARG, "boundary_correction does not apply to walk on spheres");
+  }
   if (a.n_nodes > 0) {
     if ((s = check_device_ptr(a.nodes, "nodes_dev")) != PDD_OK) return s;
     if (!a.adjoint || a.out || a.jac) if ((s = check_device_ptr(a.out, "out_dev")) != PDD_OK) return s;
@@ -491,7 +500,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   // ---- plan cache lookup
   std::string key;
   if (graph) {
-    key_add(key, a.adjoint ? 2 : 1);
+    key_add(key, a.adjoint ? 2 : (a.wos ? 3 : 1));
     int dev = 0;
     PDD_HIP(hipGetDevice(&dev));
     key_add(key, dev);
@@ -565,7 +574,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   lp.sdt = P.sigma * std::sqrt(a.dt);
   lp.dtf = (float)lp.dt;
   lp.sdtf = (float)lp.sdt;
-  lp.max_steps = o.max_steps > 0 ? o.max_steps : (int64_t)std::ceil(100.0 / a.dt);
+  lp.max_steps = o.max_steps > 0 ? o.max_steps : (a.wos ? (int64_t)100000 : (int64_t)std::ceil(100.0 / a.dt));
   if (lp.max_steps > 0x7FFFFFFF) lp.max_steps = 0x7FFFFFFF;
   lp.key0 = (uint32_t)a.seed;
   lp.key1 = (uint32_t)(a.seed >> 32);
@@ -775,6 +784,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     L.terms = terms;
     L.fp32 = fp32;
     L.adjoint = a.adjoint;
+    L.wos = a.wos;
     const int max_blocks = tune.blocks_per_cu * device_cus();
     const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
     L.grid = std::max(1, std::min(max_blocks, need));
@@ -1015,6 +1025,22 @@ pdd_status pdd_mc_interface(const pdd_linear_problem* problem, const double* nod
     if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
     LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, false, nullptr, nullptr,
                      nullptr, 0};
+    return run_linear(a, (hipStream_t)hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_wos_interface(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                             const int64_t* paths_host, double eps, uint64_t seed, const pdd_options* options,
+                             pdd_node_stat* out_dev, void* hip_stream) {
+  try {
+    if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
+    LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, eps, seed, *options, out_dev, false, nullptr, nullptr,
+                     nullptr, 0};
+    a.wos = true;
     return run_linear(a, (hipStream_t)hip_stream);
   } catch (const std::bad_alloc&) {
     return fail(PDD_ERR_NO_MEMORY, "host allocation failed");

@@ -330,6 +330,67 @@ __device__ __forceinline__ bool inside(const Dom<R>& D, const R* x) {
   return r2 < D.rad2;
 }
 
+// Distance from x to the boundary of D (negative outside): ball R - |x - c|,
+// box min_k min(x_k - lo_k, hi_k - x_k).
+template <typename R, int DIM>
+__device__ __forceinline__ R boundary_distance(const Dom<R>& D, const R* x) {
+  if (D.kind == DOM_BOX) {
+    R m = x[0] - D.lo[0];
+    m = fmin(m, D.hi[0] - x[0]);
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) {
+      m = fmin(m, x[k] - D.lo[k]);
+      m = fmin(m, D.hi[k] - x[k]);
+    }
+    return m;
+  }
+  R r2 = (R)0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const R d = x[k] - D.ctr[k];
+    r2 += d * d;
+  }
+  return D.rad - sqrt(r2);
+}
+
+// x += r z / |z| (z2 = |z|^2): FP64 in the order r (z_k / |z|); FP32 with the
+// hardware reciprocal square root.
+template <typename R, int DIM>
+__device__ __forceinline__ void jump_sphere(R* x, R r, R z2, const R* z);
+template <>
+__device__ __forceinline__ void jump_sphere<double, 1>(double* x, double r, double z2, const double* z) {
+  const double zn = sqrt(z2);
+  x[0] = x[0] + r * (z[0] / zn);
+}
+template <>
+__device__ __forceinline__ void jump_sphere<double, 2>(double* x, double r, double z2, const double* z) {
+  const double zn = sqrt(z2);
+  for (int k = 0; k < 2; ++k) x[k] = x[k] + r * (z[k] / zn);
+}
+template <>
+__device__ __forceinline__ void jump_sphere<double, 3>(double* x, double r, double z2, const double* z) {
+  const double zn = sqrt(z2);
+  for (int k = 0; k < 3; ++k) x[k] = x[k] + r * (z[k] / zn);
+}
+template <int DIM>
+__device__ __forceinline__ void jump_sphere_f(float* x, float r, float z2, const float* z) {
+  const float s = r * __builtin_amdgcn_rsqf(z2);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) x[k] = x[k] + s * z[k];
+}
+template <>
+__device__ __forceinline__ void jump_sphere<float, 1>(float* x, float r, float z2, const float* z) {
+  jump_sphere_f<1>(x, r, z2, z);
+}
+template <>
+__device__ __forceinline__ void jump_sphere<float, 2>(float* x, float r, float z2, const float* z) {
+  jump_sphere_f<2>(x, r, z2, z);
+}
+template <>
+__device__ __forceinline__ void jump_sphere<float, 3>(float* x, float r, float z2, const float* z) {
+  jump_sphere_f<3>(x, r, z2, z);
+}
+
 // Nearest boundary point.  Outside a box: clamp; inside a box (censored path):
 // the nearest face; ball: c + R (x - c)/|x - c| (c + R e_0 at the centre).
 template <typename R, int DIM>

@@ -20,6 +20,7 @@ struct WalkLaunch {
                              // kAdjTerms term columns per function
   bool fp32;
   bool adjoint;
+  bool wos;                  // walk on spheres (b = c = f = 0; P->dt holds eps)
   int grid;
   const WorkItem* items;
   int n_items;

@@ -102,7 +102,10 @@ hipError_t launch_walk_fwd(const WalkLaunch& L, hipStream_t st);
 hipError_t launch_walk_adj_f32(const WalkLaunch& L, hipStream_t st);
 hipError_t launch_walk_adj_f64(const WalkLaunch& L, hipStream_t st);
 
+hipError_t launch_walk_wos(const WalkLaunch& L, hipStream_t st);
+
 hipError_t launch_walk(const WalkLaunch& L, hipStream_t st) {
+  if (L.wos) return launch_walk_wos(L, st);
   if (!L.adjoint) return launch_walk_fwd(L, st);
   return L.fp32 ? launch_walk_adj_f32(L, st) : launch_walk_adj_f64(L, st);
 }

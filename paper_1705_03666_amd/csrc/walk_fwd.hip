@@ -5,6 +5,22 @@
 
 namespace pdd {
 
+template <typename R, int LAYOUT>
+static hipError_t launch_wos_dim(const WalkLaunch& L, hipStream_t st) {
+  switch (L.P->dim) {
+    case 1: return launch_walk_t<R, 1, -1, LAYOUT, false, false, true>(L, st);
+    case 2: return launch_walk_t<R, 2, -1, LAYOUT, false, false, true>(L, st);
+    default: return launch_walk_t<R, 3, -1, LAYOUT, false, false, true>(L, st);
+  }
+}
+
+// Walk on spheres (Laplace's equation; b = c = f = 0).
+hipError_t launch_walk_wos(const WalkLaunch& L, hipStream_t st) {
+  if (L.fp32) return launch_wos_dim<float, RNG_QUAD24>(L, st);
+  if (L.P->layout == RNG_QUAD24) return launch_wos_dim<double, RNG_QUAD24>(L, st);
+  return launch_wos_dim<double, RNG_PAIR52>(L, st);
+}
+
 hipError_t launch_walk_fwd(const WalkLaunch& L, hipStream_t st) {
   if (L.fp32) return launch_walk_terms<float, RNG_QUAD24, false>(L, st);
   if (L.P->layout == RNG_QUAD24) return launch_walk_terms<double, RNG_QUAD24, false>(L, st);

@@ -161,7 +161,7 @@ __device__ __forceinline__ R bcf_value(const LinearParams& P, const DevFun& F, c
 template <typename R, bool TERMS>
 constexpr int walk_min_waves() { return sizeof(R) == 4 ? (TERMS ? 2 : 4) : 1; }
 
-template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ>
+template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ, bool WOS = false>
 __global__ void __launch_bounds__(kBlock, (walk_min_waves<R, TERMS>()))
 k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, uint32_t* __restrict__ qhead,
        ItemStat* __restrict__ istat, double* __restrict__ igrad, int grad_stride,
@@ -399,6 +399,24 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
         }
 #pragma unroll
         for (int s = 0; s < GS::G; ++s) {
+          if constexpr (WOS) {
+            // walk on spheres: jump by the distance to the boundary in the
+            // direction of this jump's Gaussians, or stop inside the eps shell
+            if (alive && n < max_steps) {
+              const R r = boundary_distance<R, DIM>(D, X);
+              if (!(r >= dt)) {
+                alive = false;
+                fin = true;
+              } else {
+                R z2 = (R)0;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) z2 += z[s * DIM + k] * z[s * DIM + k];
+                jump_sphere<R, DIM>(X, r, z2, &z[s * DIM]);
+                ++n;
+              }
+            }
+            continue;
+          }
           if (alive && n < max_steps) {
             R mono[NM > 0 ? NM : 1];
             if constexpr (DFC >= 0) monomials<R, DIM, DFC>(X, mono);
@@ -461,7 +479,8 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
       if (alive && n >= max_steps) {
         alive = false;
         fin = true;
-        cens = true;
+        // walk on spheres: a path already inside the eps shell exits normally
+        cens = WOS ? (boundary_distance<R, DIM>(D, X) >= dt) : true;
       }
 
       // ---- park ended paths in LDS, refill their lanes with the item's next paths
@@ -786,9 +805,9 @@ k_walk_plain_adj(const LinearParams P, int node, uint32_t n_paths, ItemStat* __r
 // ---------------------------------------------------------------------------
 // Launch of one k_walk instantiation, dispatched on dimension and on whether
 // b, c, f have a polynomial part.
-template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ>
+template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ, bool WOS = false>
 static hipError_t launch_walk_t(const WalkLaunch& L, hipStream_t st) {
-  hipLaunchKernelGGL((k_walk<R, DIM, DFC, LAYOUT, TERMS, ADJ>), dim3(L.grid), dim3(kBlock), 0, st, *L.P, L.items,
+  hipLaunchKernelGGL((k_walk<R, DIM, DFC, LAYOUT, TERMS, ADJ, WOS>), dim3(L.grid), dim3(kBlock), 0, st, *L.P, L.items,
                      L.n_items, L.qhead, L.istat, L.igrad, L.grad_stride, L.dump_phi, L.dump_steps, L.dump_off,
                      L.refill_groups);
   return hipGetLastError();

@@ -108,6 +108,22 @@ def test_invalid_linear_arguments_are_rejected_on_the_host(abi, case):
     assert len(lib.pdd_last_error()) > 0
 
 
+def test_walk_on_spheres_rejects_non_laplace_problems(abi):
+    lib = abi.load()
+    p = _problem(abi)
+    o = _opts(abi)
+    paths = (C.c_int64 * 1)(10)
+    coef = (C.c_double * 1)(1.0)
+    p.c.poly_degree = 0
+    p.c.poly = C.cast(coef, C.c_void_p).value
+    st = lib.pdd_wos_interface(C.byref(p), None, 1, paths, 1e-3, 0, C.byref(o), None, None)
+    assert st == abi.PDD_ERR_UNSUPPORTED
+    p.c.poly_degree = -1
+    p.c.poly = None
+    st = lib.pdd_wos_interface(C.byref(p), None, 1, paths, -1.0, 0, C.byref(o), None, None)
+    assert st == abi.PDD_ERR_INVALID_ARG
+
+
 def test_branching_admissibility_is_checked_on_the_host(abi):
     """Assumption 3.2: binary branching with |psi| <= 2 blows up at
     T* = ln(psi/(psi-1))/beta = ln 2; T = 1 is rejected, T = 0.5 passes the check

@@ -146,6 +146,48 @@ def test_boundary_corrected_adjoint_and_fp32(pdd, orc):
     assert np.all(np.abs(gm - of["mean"]) <= 4.0 * np.sqrt(gs ** 2 + of["se"] ** 2) + 1e-5)
 
 
+WOS_CASES = {
+    "c1": lambda: (CF.c1().problem, CF.c1().nodes[::3]),
+    "disk_c3": lambda: (CF.c3(scale=0.01)[4].problem, CF.c3(scale=0.01)[4].nodes[:6]),
+    "ball3_c3": lambda: (CF.c3(scale=0.01)[7].problem, CF.c3(scale=0.01)[7].nodes[:6]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(WOS_CASES))
+@pytest.mark.parametrize("layout", ["pair52", "quad24"])
+def test_wos_fp64_matches_oracle_per_path(pdd, orc, case, layout):
+    """Walk on spheres: per-path values and jump counts equal the oracle's on
+    the same streams (persistent and graph schedules)."""
+    P, nodes = WOS_CASES[case]()
+    paths = np.array([(41 + 29 * i) % 300 + 90 for i in range(len(nodes))], np.int64)
+    eps = 1e-4
+    log(f"wos per-path: case={case} layout={layout} nodes={len(nodes)} paths={paths.sum()}")
+    o = orc.wos(P, nodes, paths, eps, 4, layout=orc.PAIR52 if layout == "pair52" else orc.QUAD24, dump=True)
+    for sched, chunk in (("persistent", 64), ("graph", 0)):
+        g = pdd.wos_interface(P, nodes, paths, eps, 4, precision="fp64", layout=layout, dump=True,
+                              schedule=sched, chunk_paths=chunk)
+        torch.cuda.synchronize()
+        assert np.all(g["path_steps"].cpu().numpy() == o["path_steps"]), sched
+        nbad, worst = per_path_close(g["phi"].cpu().numpy(), o["phi"])
+        assert nbad == 0, (sched, nbad, worst)
+        stats_close(g, o)
+
+
+def test_wos_fp32_matches_oracle_and_exact(pdd, orc):
+    """FP32 walk on spheres on the 3-D ball layout of the batched workload:
+    within 4 SE of the FP64 oracle and of the exact harmonic value g(x)."""
+    part = CF.c3(scale=0.01)[7]
+    P, nodes = part.problem, part.nodes[:16]
+    paths = np.full(len(nodes), 20000, np.int64)
+    o = orc.wos(P, nodes, paths, 1e-4, 6, layout=orc.QUAD24)
+    g = pdd.wos_interface(P, nodes, paths, 1e-4, 6, precision="fp32")
+    torch.cuda.synchronize()
+    gm, gs = g["mean"].cpu().numpy(), g["se"].cpu().numpy()
+    assert np.all(np.abs(gm - o["mean"]) <= 4.0 * np.sqrt(gs ** 2 + o["se"] ** 2) + 1e-5)
+    exact = np.array([orc.fun_eval(P.g, 3, x) for x in nodes])
+    assert np.all(np.abs(gm - exact) <= 4.0 * gs + 1e-3)
+
+
 def test_degenerate_nodes_and_budgets(pdd, orc):
     w = CF.c1()
     nodes = np.array([[1.2, 0.3], [0.0, 0.5], [0.5, 0.5], [0.3, 0.3], [0.5, 1e-9]])
