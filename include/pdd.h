@@ -164,7 +164,15 @@ typedef struct {
                                   c0 sigma sqrt(dt), c0 = -zeta(1/2)/sqrt(2 pi) ~ 0.5826, which removes
                                   the O(sqrt dt) overshoot bias; g is still taken at the projection of
                                   X onto the boundary of D.  Ignored by pdd_branching_eval. */
-  int32_t reserved;       /* must be 0 */
+  int32_t specialize;     /* batched linear walks (PDD_FP64, PDD_FP32_STEP) whose b, c or f have generic
+                             terms: 0 = auto: compile, at run time, a kernel with the problem's factor
+                             structure (functions, coordinates, scales, shifts, powers) written in as
+                             constants, and fall back to the table-driven kernel (with a note on
+                             stderr) if the runtime compiler is unavailable; 1 = required (a failed
+                             compilation returns PDD_ERR_HIP); -1 = never.  Both kernels evaluate the
+                             same operations in the same order.  Coefficients stay run-time data, so
+                             one compiled kernel (cached in memory and in $PDD_JIT_CACHE, default
+                             ~/.cache/pdd_jit) serves every coefficient value.  Ignored elsewhere. */
 } pdd_options;
 
 /* Per-node result: mean and sum of squared deviations (variance = m2/(n-1),

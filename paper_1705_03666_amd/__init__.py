@@ -72,13 +72,17 @@ def _stream_handle() -> int:
 _PREC = {"fp64_plain": A.PDD_FP64_PLAIN, "fp64": A.PDD_FP64, "fp32": A.PDD_FP32_STEP}
 _LAYOUT = {"pair52": A.PDD_RNG_PAIR52, "quad24": A.PDD_RNG_QUAD24}
 _SCHED = {"auto": A.PDD_SCHED_AUTO, "persistent": A.PDD_SCHED_PERSISTENT, "graph": A.PDD_SCHED_PERSISTENT_GRAPH}
+# problem-specialised kernels for generic terms in b, c, f (pdd_options.specialize)
+_SPEC = {"auto": 0, "on": 1, "off": -1}
 
 
 def _options(precision: str, layout: Optional[str], max_steps: int, schedule: str, chunk_paths: int,
              blocks_per_cu: int, refill_groups: int, dump_phi=None, dump_steps=None,
-             boundary_correction: bool = False) -> A.pdd_options:
+             boundary_correction: bool = False, specialize: str = "auto") -> A.pdd_options:
     if precision not in _PREC:
         raise ValueError(f"precision must be one of {list(_PREC)}")
+    if specialize not in _SPEC:
+        raise ValueError(f"specialize must be one of {list(_SPEC)}")
     if layout is None:
         layout = "quad24" if precision == "fp32" else "pair52"
     o = A.pdd_options()
@@ -92,7 +96,7 @@ def _options(precision: str, layout: Optional[str], max_steps: int, schedule: st
     o.blocks_per_cu = int(blocks_per_cu)
     o.refill_groups = int(refill_groups)
     o.boundary_correction = 1 if boundary_correction else 0
-    o.reserved = 0
+    o.specialize = _SPEC[specialize]
     return o
 
 
@@ -182,7 +186,7 @@ def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str
                  layout: Optional[str] = None, max_steps: int = 0, dump: bool = False, schedule: str = "auto",
                  chunk_paths: int = 0, blocks_per_cu: int = 0, refill_groups: int = 0,
                  coefs: Optional[Dict[str, torch.Tensor]] = None,
-                 boundary_correction: bool = False) -> Dict[str, torch.Tensor]:
+                 boundary_correction: bool = False, specialize: str = "auto") -> Dict[str, torch.Tensor]:
     """Monte Carlo value of the linear problem at every node (pdd_mc_interface).
     Returns device tensors mean, m2, n, steps, censored, var, se (and, with
     dump=True, the per-path values `phi` and step counts `path_steps`,
@@ -202,7 +206,7 @@ def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str
         dphi = torch.empty(max(total, 1), dtype=torch.float64, device="cuda")
         dst = torch.empty(max(total, 1), dtype=torch.int64, device="cuda")
     o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups, dphi, dst,
-                 boundary_correction)
+                 boundary_correction, specialize)
     st = library().pdd_mc_interface(C.byref(p), nt.data_ptr() if n else None, n,
                                     ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt), int(seed) & (2 ** 64 - 1),
                                     C.byref(o), raw.data_ptr(), _stream_handle())
@@ -252,7 +256,8 @@ def wos_interface(problem, nodes, paths, eps: float, seed: int = 0, precision: s
 def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = "fp32",
                layout: Optional[str] = None, max_steps: int = 0, schedule: str = "auto", chunk_paths: int = 0,
                blocks_per_cu: int = 0, refill_groups: int = 0, coefs: Optional[Dict[str, torch.Tensor]] = None,
-               with_stats: bool = False, boundary_correction: bool = False) -> Dict[str, torch.Tensor]:
+               with_stats: bool = False, boundary_correction: bool = False,
+               specialize: str = "auto") -> Dict[str, torch.Tensor]:
     """Gradient of sum_i w_i u_i with respect to the coefficient arrays of g, f
     and c (pdd_mc_adjoint).  Returns device tensors g_coef, g_poly, f_coef,
     f_poly, c_coef, c_poly (and the per-node statistics with with_stats)."""
@@ -283,7 +288,7 @@ def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = 
         grads[name + "_poly"] = grads[name + "_poly"][:M]
     raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda") if with_stats else None
     o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups,
-                 boundary_correction=boundary_correction)
+                 boundary_correction=boundary_correction, specialize=specialize)
     st = library().pdd_mc_adjoint(C.byref(p), nt.data_ptr() if n else None, n,
                                   ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt), int(seed) & (2 ** 64 - 1),
                                   C.byref(o), wt.data_ptr() if n else None, gstruct,
@@ -311,7 +316,7 @@ def mc_value_jacobian(problem, nodes, paths, dt: float, seed: int = 0, precision
                       layout: Optional[str] = None, max_steps: int = 0, schedule: str = "auto", chunk_paths: int = 0,
                       blocks_per_cu: int = 0, refill_groups: int = 0,
                       coefs: Optional[Dict[str, torch.Tensor]] = None,
-                      boundary_correction: bool = False) -> Dict[str, torch.Tensor]:
+                      boundary_correction: bool = False, specialize: str = "auto") -> Dict[str, torch.Tensor]:
     """Per-node statistics and the Jacobian d mean_i / d coefficients in one
     pass (pdd_mc_value_jacobian).  Returns the statistics of mc_interface plus
     `jac` [n, n_params] (column blocks in `param_layout(problem)` order)."""
@@ -329,7 +334,7 @@ def mc_value_jacobian(problem, nodes, paths, dt: float, seed: int = 0, precision
     raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
     jac = torch.zeros((max(n, 1), max(npar, 1)), dtype=torch.float64, device="cuda")
     o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups,
-                 boundary_correction=boundary_correction)
+                 boundary_correction=boundary_correction, specialize=specialize)
     st = library().pdd_mc_value_jacobian(C.byref(p), nt.data_ptr() if n else None, n,
                                          ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt),
                                          int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(), jac.data_ptr(),

@@ -50,7 +50,7 @@ class pdd_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("rng_layout", C.c_int32), ("max_steps", C.c_int64),
                 ("dump_phi", C.c_void_p), ("dump_steps", C.c_void_p), ("schedule", C.c_int32),
                 ("chunk_paths", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill_groups", C.c_int32),
-                ("boundary_correction", C.c_int32), ("reserved", C.c_int32)]
+                ("boundary_correction", C.c_int32), ("specialize", C.c_int32)]
 
 
 class pdd_node_stat(C.Structure):

@@ -8,18 +8,24 @@
 
 namespace pdd {
 
-Tuning choose_tuning(int dim, bool fp32, bool adjoint, const pdd_options& o, int n_cus) {
+Tuning choose_tuning(int dim, bool fp32, bool adjoint, const pdd_options& o, int n_cus, int64_t total_paths) {
   (void)dim;
-  (void)n_cus;
   (void)adjoint;
   Tuning t;
   // measured on MI355X for the 3-D C5 walk (forward and adjoint alike)
   t.chunk_paths = 16384;
   t.blocks_per_cu = fp32 ? 8 : 4;
   t.refill_groups = 3;
-  if (o.chunk_paths > 0) t.chunk_paths = o.chunk_paths;
   if (o.blocks_per_cu > 0) t.blocks_per_cu = o.blocks_per_cu;
   if (o.refill_groups > 0) t.refill_groups = o.refill_groups;
+  if (o.chunk_paths > 0) {
+    t.chunk_paths = o.chunk_paths;
+  } else {
+    // a call too small for the default items: halve the item size (down to
+    // 1024 paths) until every resident wavefront gets about four items
+    const int64_t waves = (int64_t)t.blocks_per_cu * std::max(1, n_cus) * 4;
+    while (t.chunk_paths > 1024 && total_paths / t.chunk_paths < 4 * waves) t.chunk_paths /= 2;
+  }
   t.chunk_paths = std::max(1, t.chunk_paths);
   return t;
 }

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -17,6 +18,7 @@
 #include "pdd.h"
 #include "pdd_internal.hpp"
 #include "pdd_kernels.hpp"
+#include "pdd_spec.hpp"
 #include "pdd_tuning.hpp"
 
 using namespace pdd;
@@ -459,8 +461,9 @@ pdd_status validate_linear(const LinearPlanArgs& a) {
   if (o.chunk_paths < 0 || o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.refill_groups < 0 || o.refill_groups > 64)
     return fail(PDD_ERR_INVALID_ARG, "schedule override out of range");
   if (o.schedule < PDD_SCHED_AUTO || o.schedule > PDD_SCHED_PERSISTENT_GRAPH) return fail(PDD_ERR_INVALID_ARG, "unknown schedule");
-  if (o.boundary_correction < 0 || o.boundary_correction > 1 || o.reserved != 0)
-    return fail(PDD_ERR_INVALID_ARG, "boundary_correction must be 0 or 1 and reserved 0");
+  if (o.boundary_correction < 0 || o.boundary_correction > 1)
+    return fail(PDD_ERR_INVALID_ARG, "boundary_correction must be 0 or 1");
+  if (o.specialize < -1 || o.specialize > 1) return fail(PDD_ERR_INVALID_ARG, "specialize must be -1, 0 or 1");
   if (a.wos) {
     auto zero = [](const pdd_fun& F) { return F.n_terms == 0 && F.poly_degree < 0; };
     bool ok = zero(P.c) && zero(P.f);
@@ -591,7 +594,9 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   lp.has_f = nonzero(lp.f);
 
   // ---- work items
-  const Tuning tune = choose_tuning(dim, fp32, a.adjoint, o, device_cus());
+  int64_t total_paths = 0;
+  for (int64_t i = 0; i < a.n_nodes; ++i) total_paths += a.paths[i];
+  const Tuning tune = choose_tuning(dim, fp32, a.adjoint, o, device_cus(), total_paths);
   std::vector<double> cost((size_t)a.n_nodes);
   for (int64_t i = 0; i < a.n_nodes; ++i) cost[(size_t)i] = 0.0;
   std::vector<double> hnodes((size_t)a.n_nodes * dim);
@@ -682,6 +687,23 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     for (int t = 0; t < P.c.n_terms; ++t) colmap.push_back(nt + ngm + NP + t);
     for (int m = 0; m < n_mono(dim, P.c.poly_degree); ++m) colmap.push_back(nt + ngm + NP + nt + m);
     o_colmap = A.add(sizeof(int32_t) * std::max<size_t>(1, colmap.size()));
+  }
+
+  // ---- problem-specialised kernel for per-step generic terms
+  hipFunction_t spec = nullptr;
+  if (!plain && bcf_terms && !a.wos && o.specialize >= 0) {
+    const std::string src = spec_terms_source(lp, T.fac);
+    std::string why = "a scale or shift is not finite";
+    if (src.empty() ||
+        !spec_walk_kernel(src, fp32, dim, dfc, fp32 ? (int)PDD_RNG_QUAD24 : o.rng_layout, a.adjoint, &spec, &why)) {
+      spec = nullptr;
+      if (o.specialize == 1) return fail(PDD_ERR_HIP, "problem-specialised kernel: " + why);
+      static std::once_flag once;
+      std::call_once(once, [&] {
+        std::fprintf(stderr, "pdd: problem-specialised kernel unavailable, using the table-driven kernel: %s\n",
+                     why.c_str());
+      });
+    }
   }
 
   // ---- allocate
@@ -785,6 +807,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     L.fp32 = fp32;
     L.adjoint = a.adjoint;
     L.wos = a.wos;
+    L.spec = spec;
     const int max_blocks = tune.blocks_per_cu * device_cus();
     const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
     L.grid = std::max(1, std::min(max_blocks, need));

@@ -3,8 +3,10 @@
 // wavefront reductions.  Everything is a header so the compiler can inline it
 // into each kernel instantiation.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 #include "pdd_internal.hpp"
 
@@ -122,6 +124,22 @@ __device__ __forceinline__ float ftanh(float x) {
 }
 __device__ __forceinline__ double ftanh(double x) { return tanh(x); }
 
+// Read-only tables (factor records, coefficients) are read through the
+// constant address space, which compiles to scalar loads: the records are
+// wave-uniform, so their fields land in scalar registers and the switch over
+// the factor's function becomes a uniform branch.  The empty asm statement
+// hides the table address from the optimiser, so the loads stay next to
+// their use instead of being hoisted out of the stepping loop into scalar
+// registers that would then spill.
+#define PDD_CONST_AS __attribute__((address_space(4)))
+
+template <typename T>
+__device__ __forceinline__ const T PDD_CONST_AS* const_table(const T* p) {
+  uint64_t a = reinterpret_cast<uint64_t>(p);
+  asm volatile("" : "+s"(a));
+  return (const T PDD_CONST_AS*)a;
+}
+
 template <typename R>
 __device__ __forceinline__ R fac_a(const DevFactor& f);
 template <>
@@ -171,20 +189,59 @@ __device__ __forceinline__ R factor_value(const DevFactor& fa, const R* x) {
   return r;
 }
 
+// factor_value with the function and the power fixed at compile time (the
+// form used by problem-specialised kernels): the same operations in the same
+// order, so it returns the same bits.
+template <typename R, int DIM, int FN, int POW>
+__device__ __forceinline__ R factor_fixed(const R* x, int d, R a, R b) {
+  const R s = a * pick<R, DIM>(x, d) + b;
+  R v;
+  if constexpr (FN == FN_EXP) v = fexp(s);
+  else if constexpr (FN == FN_SIN) v = fsin(s);
+  else if constexpr (FN == FN_COS) v = fcos(s);
+  else if constexpr (FN == FN_TANH) v = ftanh(s);
+  else v = s;
+  R r = (R)1;
+#pragma unroll
+  for (int k = 0; k < POW; ++k) r *= v;
+  return r;
+}
+
 // Product of the factors of term t (without its coefficient).
 template <typename R, int DIM>
 __device__ __forceinline__ R term_value(const DevFactor* __restrict__ fac, const DevFun& F, int t, const R* x) {
   R v = (R)1;
-  const DevFactor* tf = fac + F.fac_off + t * F.n_factors;
-  for (int j = 0; j < F.n_factors; ++j) v *= factor_value<R, DIM>(tf[j], x);
+  const DevFactor PDD_CONST_AS* tf = const_table(fac) + F.fac_off + t * F.n_factors;
+  for (int j = 0; j < F.n_factors; ++j) {
+    DevFactor fa;
+    fa.fn = tf[j].fn;
+    fa.dim = tf[j].dim;
+    fa.power = tf[j].power;
+    fa.af = tf[j].af;
+    fa.bf = tf[j].bf;
+    fa.ad = tf[j].ad;
+    fa.bd = tf[j].bd;
+    v *= factor_value<R, DIM>(fa, x);
+  }
   return v;
+}
+
+template <typename R>
+__device__ __forceinline__ R coef_const(const double* __restrict__ cd, const float* __restrict__ cf, int i);
+template <>
+__device__ __forceinline__ float coef_const<float>(const double* __restrict__, const float* __restrict__ cf, int i) {
+  return const_table(cf)[i];
+}
+template <>
+__device__ __forceinline__ double coef_const<double>(const double* __restrict__ cd, const float* __restrict__, int i) {
+  return const_table(cd)[i];
 }
 
 template <typename R, int DIM>
 __device__ __forceinline__ R terms_sum(const DevFactor* __restrict__ fac, const double* __restrict__ cd,
                                        const float* __restrict__ cf, const DevFun& F, const R* x) {
   R s = (R)0;
-  for (int t = 0; t < F.n_terms; ++t) s += coef_at<R>(cd, cf, F.coef_off + t) * term_value<R, DIM>(fac, F, t, x);
+  for (int t = 0; t < F.n_terms; ++t) s += coef_const<R>(cd, cf, F.coef_off + t) * term_value<R, DIM>(fac, F, t, x);
   return s;
 }
 

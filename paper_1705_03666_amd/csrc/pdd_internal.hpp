@@ -1,6 +1,14 @@
 // Structures shared by the host layer (capi.cpp) and the HIP kernels.
 #pragma once
+#ifdef __HIPCC_RTC__
+// runtime compilation: the fixed-width types come with the compiler's own headers
+typedef __hip_internal::int32_t int32_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::int64_t int64_t;
+typedef __hip_internal::uint64_t uint64_t;
+#else
 #include <stdint.h>
+#endif
 
 namespace pdd {
 

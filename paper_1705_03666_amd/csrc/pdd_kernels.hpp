@@ -21,6 +21,7 @@ struct WalkLaunch {
   bool fp32;
   bool adjoint;
   bool wos;                  // walk on spheres (b = c = f = 0; P->dt holds eps)
+  hipFunction_t spec;        // problem-specialised k_walk (runtime-compiled), or null
   int grid;
   const WorkItem* items;
   int n_items;

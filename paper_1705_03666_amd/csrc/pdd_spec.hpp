@@ -1,0 +1,36 @@
+// Problem-specialised walk kernels (host side).
+//
+// A problem whose b, c or f carry generic terms (products of exp, sin, cos,
+// tanh and powers of affine functions of one coordinate) pays, in the
+// precompiled kernels, for reading and dispatching on every factor record at
+// every step.  Instead the library writes the factor structure of that
+// problem (functions, coordinates, scales, shifts, powers) into C++ source as
+// constants, compiles k_walk with it at run time for the device in use, and
+// launches the result.  Coefficients stay in the staged table, so one compiled
+// kernel serves every coefficient value.  The specialised kernel evaluates the
+// same products in the same order as the table-driven one.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "pdd_internal.hpp"
+
+namespace pdd {
+
+// Source of the term policy (struct pdd_spec::SpecTerms) for the functions
+// described by P.b, P.c, P.f, P.g and the factor records `fac`; empty when a
+// value cannot be written as a literal (non-finite scale or shift).
+std::string spec_terms_source(const LinearParams& P, const std::vector<DevFactor>& fac);
+
+// Loads (compiling on first use, per device) the k_walk instantiation
+// <R, DIM, DFC, LAYOUT, TERMS = true, ADJ, WOS = false, SpecTerms>.  Returns
+// false with a message in *err when the runtime compiler or the module load
+// fails.  Compiled code objects are kept in memory for the life of the
+// process and, when the directory is writable, in $PDD_JIT_CACHE (default
+// ~/.cache/pdd_jit).
+bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc, int layout, bool adjoint,
+                      hipFunction_t* fn, std::string* err);
+
+}  // namespace pdd

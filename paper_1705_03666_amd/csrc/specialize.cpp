@@ -1,0 +1,250 @@
+// Problem-specialised walk kernels: source generation, runtime compilation
+// (hiprtc) and a two-level cache of the compiled code objects.
+#include "pdd_spec.hpp"
+
+#include <hip/hiprtc.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+
+namespace pdd {
+
+// Text of the device headers, embedded at build time (rtc_sources.cpp).
+extern const int kRtcHeaderCount;
+extern const char* const kRtcHeaderNames[];
+extern const char* const kRtcHeaderBodies[];
+
+namespace {
+
+bool literal(double v, std::string* out) {
+  if (!std::isfinite(v)) return false;
+  char b[64];
+  std::snprintf(b, sizeof b, "%a", v);
+  *out = std::string("(R)") + b;
+  return true;
+}
+
+const char* kFunNames[6] = {"b0", "b1", "b2", "c", "f", "g"};
+
+const DevFun& fun_at(const LinearParams& P, int w) {
+  if (w < 3) return P.b[w];
+  if (w == 3) return P.c;
+  if (w == 4) return P.f;
+  return P.g;
+}
+
+uint64_t fnv1a(const std::string& s) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char ch : s) {
+    h ^= ch;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string cache_dir() {
+  const char* e = std::getenv("PDD_JIT_CACHE");
+  if (e && *e) return e;
+  const char* home = std::getenv("HOME");
+  if (!home || !*home) return "";
+  return std::string(home) + "/.cache/pdd_jit";
+}
+
+bool read_file(const std::string& p, std::string* out) {
+  std::ifstream f(p, std::ios::binary);
+  if (!f) return false;
+  std::stringstream s;
+  s << f.rdbuf();
+  *out = s.str();
+  return true;
+}
+
+void write_file_atomic(const std::string& p, const std::string& data) {
+  const std::string tmp = p + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream f(tmp, std::ios::binary);
+    if (!f) return;
+    f.write(data.data(), (std::streamsize)data.size());
+    if (!f) return;
+  }
+  std::rename(tmp.c_str(), p.c_str());
+}
+
+void make_dirs(const std::string& d) {
+  for (size_t i = 1; i <= d.size(); ++i)
+    if (i == d.size() || d[i] == '/') mkdir(d.substr(0, i).c_str(), 0755);
+}
+
+bool compile(const std::string& src, const std::string& name, const std::string& arch, std::string* code,
+             std::string* lowered, std::string* err) {
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "pdd_spec.hip", kRtcHeaderCount, kRtcHeaderBodies, kRtcHeaderNames) !=
+      HIPRTC_SUCCESS) {
+    *err = "hiprtcCreateProgram failed";
+    return false;
+  }
+  hiprtcAddNameExpression(prog, name.c_str());
+  const std::string a = "--offload-arch=" + arch;
+  // the same code-generation flags as the precompiled kernels (no packed FP32)
+  const char* opts[] = {a.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    *err = std::string("runtime compilation failed: ") + hiprtcGetErrorString(r) + "\n" + log.substr(0, 4000);
+    hiprtcDestroyProgram(&prog);
+    return false;
+  }
+  const char* low = nullptr;
+  if (hiprtcGetLoweredName(prog, name.c_str(), &low) != HIPRTC_SUCCESS || low == nullptr) {
+    *err = "hiprtcGetLoweredName failed";
+    hiprtcDestroyProgram(&prog);
+    return false;
+  }
+  *lowered = low;
+  size_t n = 0;
+  hiprtcGetCodeSize(prog, &n);
+  code->assign(n, '\0');
+  if (n == 0 || hiprtcGetCode(prog, &(*code)[0]) != HIPRTC_SUCCESS) {
+    *err = "hiprtcGetCode failed";
+    hiprtcDestroyProgram(&prog);
+    return false;
+  }
+  hiprtcDestroyProgram(&prog);
+  return true;
+}
+
+std::mutex g_spec_mu;
+std::map<std::string, hipFunction_t> g_spec;   // (device, key) -> loaded kernel
+
+}  // namespace
+
+std::string spec_terms_source(const LinearParams& P, const std::vector<DevFactor>& fac) {
+  std::ostringstream term, sum;
+  bool first = true;
+  for (int w = 0; w < 6; ++w) {
+    const DevFun& F = fun_at(P, w);
+    if (F.n_terms <= 0) continue;
+    const char* el = first ? "" : "else ";
+    first = false;
+    term << "    " << el << "if constexpr (W == " << w << ") {  // " << kFunNames[w] << "\n";
+    sum << "    " << el << "if constexpr (W == " << w << ") {\n";
+    for (int t = 0; t < F.n_terms; ++t) {
+      term << "      " << (t ? "else " : "") << "if (t == " << t << ") {";
+      for (int j = 0; j < F.n_factors; ++j) {
+        const DevFactor& d = fac[(size_t)(F.fac_off + t * F.n_factors + j)];
+        std::string a, b;
+        if (!literal(d.ad, &a) || !literal(d.bd, &b)) return "";
+        term << "\n        v *= pdd::factor_fixed<R, DIM, " << d.fn << ", " << d.power << ">(x, " << d.dim << ", " << a
+             << ", " << b << ");";
+      }
+      term << "\n      }\n";
+      sum << "      s += c[" << (F.coef_off + t) << "] * term<R, DIM, W>(P, " << t << ", x);\n";
+    }
+    term << "    }\n";
+    sum << "    }\n";
+  }
+  std::ostringstream o;
+  o << "namespace pdd_spec {\n"
+       "struct SpecTerms {\n"
+       "  template <typename R, int DIM, int W>\n"
+       "  __device__ static __forceinline__ R term(const pdd::LinearParams& P, int t, const R* x) {\n"
+       "    (void)P;\n"
+       "    R v = (R)1;\n"
+    << term.str()
+    << "    return v;\n"
+       "  }\n"
+       "  template <typename R, int DIM, int W>\n"
+       "  __device__ static __forceinline__ R sum(const pdd::LinearParams& P, const R* x) {\n"
+       "    const R PDD_CONST_AS* c = pdd::coef_table<R>(P);\n"
+       "    (void)c;\n"
+       "    R s = (R)0;\n"
+    << sum.str()
+    << "    return s;\n"
+       "  }\n"
+       "};\n"
+       "}  // namespace pdd_spec\n";
+  return o.str();
+}
+
+bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc, int layout, bool adjoint,
+                      hipFunction_t* fn, std::string* err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *err = "hipGetDevice failed";
+    return false;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    *err = "hipGetDeviceProperties failed";
+    return false;
+  }
+  const std::string arch = prop.gcnArchName;
+  std::ostringstream nm;
+  nm << "pdd::k_walk<" << (fp32 ? "float" : "double") << ", " << dim << ", " << dfc << ", " << layout << ", true, "
+     << (adjoint ? "true" : "false") << ", false, pdd_spec::SpecTerms>";
+  const std::string name = nm.str();
+  const std::string src = "#include \"walk_kernels.hpp\"\n" + terms_src;
+  // the key covers the generated source, the instantiation, the target and
+  // the embedded device headers
+  std::string key = arch + "\n" + name + "\n" + src;
+  for (int i = 0; i < kRtcHeaderCount; ++i) key += std::string("\n") + kRtcHeaderBodies[i];
+  std::lock_guard<std::mutex> lk(g_spec_mu);
+  const std::string mkey = std::to_string(dev) + "\n" + key;
+  auto it = g_spec.find(mkey);
+  if (it != g_spec.end()) {
+    *fn = it->second;
+    return true;
+  }
+  // disk cache: <hash>.co (code object), <hash>.key (full key, checked), <hash>.sym
+  const std::string dir = cache_dir();
+  char hx[32];
+  std::snprintf(hx, sizeof hx, "%016llx", (unsigned long long)fnv1a(key));
+  const std::string stem = dir.empty() ? "" : dir + "/" + hx;
+  std::string code, lowered, stored_key;
+  bool have = false;
+  if (!stem.empty() && read_file(stem + ".key", &stored_key) && stored_key == key &&
+      read_file(stem + ".co", &code) && read_file(stem + ".sym", &lowered) && !code.empty() && !lowered.empty())
+    have = true;
+  if (!have) {
+    if (!compile(src, name, arch, &code, &lowered, err)) return false;
+    if (!stem.empty()) {
+      make_dirs(dir);
+      write_file_atomic(stem + ".co", code);
+      write_file_atomic(stem + ".sym", lowered);
+      write_file_atomic(stem + ".key", key);
+    }
+  }
+  hipModule_t mod;
+  hipError_t e = hipModuleLoadData(&mod, code.data());
+  if (e != hipSuccess && have) {
+    // a stale or damaged cache entry: compile afresh
+    (void)hipGetLastError();
+    if (!compile(src, name, arch, &code, &lowered, err)) return false;
+    e = hipModuleLoadData(&mod, code.data());
+  }
+  if (e != hipSuccess) {
+    *err = std::string("hipModuleLoadData: ") + hipGetErrorString(e);
+    return false;
+  }
+  hipFunction_t f;
+  e = hipModuleGetFunction(&f, mod, lowered.c_str());
+  if (e != hipSuccess) {
+    *err = std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
+    return false;
+  }
+  g_spec[mkey] = f;
+  *fn = f;
+  return true;
+}
+
+}  // namespace pdd

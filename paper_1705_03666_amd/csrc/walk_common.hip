@@ -105,6 +105,20 @@ hipError_t launch_walk_adj_f64(const WalkLaunch& L, hipStream_t st);
 hipError_t launch_walk_wos(const WalkLaunch& L, hipStream_t st);
 
 hipError_t launch_walk(const WalkLaunch& L, hipStream_t st) {
+  if (L.spec != nullptr) {
+    // same argument list as k_walk; the parameter block is passed by value
+    const WorkItem* items = L.items;
+    int n_items = L.n_items, grad_stride = L.grad_stride, refill = L.refill_groups;
+    uint32_t* qhead = L.qhead;
+    ItemStat* istat = L.istat;
+    double* igrad = L.igrad;
+    double* dump_phi = L.dump_phi;
+    int64_t* dump_steps = L.dump_steps;
+    const int64_t* dump_off = L.dump_off;
+    void* args[] = {(void*)L.P, &items, &n_items, &qhead, &istat, &igrad, &grad_stride, &dump_phi, &dump_steps,
+                    &dump_off, &refill};
+    return hipModuleLaunchKernel(L.spec, (unsigned)L.grid, 1, 1, kBlock, 1, 1, 0, st, args, nullptr);
+  }
   if (L.wos) return launch_walk_wos(L, st);
   if (!L.adjoint) return launch_walk_fwd(L, st);
   return L.fp32 ? launch_walk_adj_f32(L, st) : launch_walk_adj_f64(L, st);

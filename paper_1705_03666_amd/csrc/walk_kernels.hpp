@@ -18,10 +18,14 @@
 // (block, stream 0 | block >> 32, p, i): the path is a pure function of
 // (seed, i, p), independent of which lane or launch computes it.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include "pdd_device.hpp"
+#ifndef __HIPCC_RTC__
 #include "pdd_kernels.hpp"
+#endif
 
 namespace pdd {
 
@@ -89,25 +93,19 @@ __device__ __forceinline__ float sdt_of<float>(const LinearParams& P) { return P
 template <>
 __device__ __forceinline__ double sdt_of<double>(const LinearParams& P) { return P.sdt; }
 
-// Coefficient tables read through the constant address space compile to
-// scalar loads (the tables are not written while a walk kernel runs).  The
-// empty asm statement hides the table address from the optimiser at every
-// use, so the loads are issued next to the arithmetic that consumes them
-// rather than hoisted out of the stepping loop into scalar registers, which
-// would then spill into vector-register lanes.
-#define PDD_CONST_AS __attribute__((address_space(4)))
-
+// Coefficient tables of the dense polynomials, read as scalar loads (see
+// const_table).
 template <typename R>
 __device__ __forceinline__ const R PDD_CONST_AS* coef_table(const LinearParams& P);
 template <>
 __device__ __forceinline__ const float PDD_CONST_AS* coef_table<float>(const LinearParams& P) {
-  uint64_t a = (uint64_t)(uintptr_t)P.cf;
+  uint64_t a = reinterpret_cast<uint64_t>(P.cf);
   asm volatile("" : "+s"(a));
   return (const float PDD_CONST_AS*)a;
 }
 template <>
 __device__ __forceinline__ const double PDD_CONST_AS* coef_table<double>(const LinearParams& P) {
-  uint64_t a = (uint64_t)(uintptr_t)P.cd;
+  uint64_t a = reinterpret_cast<uint64_t>(P.cd);
   asm volatile("" : "+s"(a));
   return (const double PDD_CONST_AS*)a;
 }
@@ -121,16 +119,56 @@ __device__ __forceinline__ R poly_dot(const R PDD_CONST_AS* c, const R* mono) {
   return s;
 }
 
+// The six coefficient functions of a linear problem, as template arguments.
+enum : int { FUN_B0 = 0, FUN_B1 = 1, FUN_B2 = 2, FUN_C = 3, FUN_F = 4, FUN_G = 5 };
+
+template <int W>
+__device__ __forceinline__ const DevFun& fun_of(const LinearParams& P) {
+  if constexpr (W <= FUN_B2) return P.b[W];
+  else if constexpr (W == FUN_C) return P.c;
+  else if constexpr (W == FUN_F) return P.f;
+  else return P.g;
+}
+
+// Generic-term evaluation policies of k_walk.  TableTerms interprets the
+// staged factor records at run time (any problem).  A problem-specialised
+// policy, generated as source and compiled at run time, has the same two
+// members with the factor structure (functions, coordinates, scales, shifts,
+// powers) written in as constants and the coefficients still read from the
+// table; it evaluates the same products in the same order.
+//   sum<R, DIM, W>(P, x)      sum over the terms t of function W of coef_t term_t(x)
+//   term<R, DIM, W>(P, t, x)  term_t(x) without its coefficient
+struct TableTerms {
+  template <typename R, int DIM, int W>
+  __device__ static __forceinline__ R sum(const LinearParams& P, const R* x) {
+    return terms_sum<R, DIM>(P.fac, P.cd, P.cf, fun_of<W>(P), x);
+  }
+  template <typename R, int DIM, int W>
+  __device__ static __forceinline__ R term(const LinearParams& P, int t, const R* x) {
+    return term_value<R, DIM>(P.fac, fun_of<W>(P), t, x);
+  }
+};
+
 // b_k, c or f at X: generic terms (only when TERMS) plus the dense polynomial.
-template <typename R, int DIM, int DFC, bool TERMS>
-__device__ __forceinline__ R bcf_value(const LinearParams& P, const DevFun& F, const R* X, const R* mono) {
+template <typename R, int DIM, int DFC, bool TERMS, class TP, int W>
+__device__ __forceinline__ R bcf_value(const LinearParams& P, const R* X, const R* mono) {
+  const DevFun& F = fun_of<W>(P);
   R v = (R)0;
   if constexpr (TERMS) {
-    if (F.n_terms > 0) v = terms_sum<R, DIM>(P.fac, P.cd, P.cf, F, X);
+    if (F.n_terms > 0) v = TP::template sum<R, DIM, W>(P, X);
   }
   if constexpr (DFC >= 0) {
     if (F.poly_deg >= 0) v += poly_dot<R, GradedLex<DIM, DFC>::N>(coef_table<R>(P) + F.poly_off, mono);
   }
+  return v;
+}
+
+// g at the projected exit point: generic terms plus the nested polynomial.
+template <typename R, int DIM, class TP>
+__device__ __forceinline__ R g_value_tp(const LinearParams& P, const R* xp) {
+  R v = (R)0;
+  if (P.g.n_terms > 0) v = TP::template sum<R, DIM, FUN_G>(P, xp);
+  if (P.g.poly_deg >= 0) v += poly_nested<R, DIM>(P.cd, P.cf, P.g.poly_deg, P.g.poly_off, xp);
   return v;
 }
 
@@ -161,7 +199,7 @@ __device__ __forceinline__ R bcf_value(const LinearParams& P, const DevFun& F, c
 template <typename R, bool TERMS>
 constexpr int walk_min_waves() { return sizeof(R) == 4 ? (TERMS ? 2 : 4) : 1; }
 
-template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ, bool WOS = false>
+template <typename R, int DIM, int DFC, int LAYOUT, bool TERMS, bool ADJ, bool WOS = false, class TP = TableTerms>
 __global__ void __launch_bounds__(kBlock, (walk_min_waves<R, TERMS>()))
 k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, uint32_t* __restrict__ qhead,
        ItemStat* __restrict__ istat, double* __restrict__ igrad, int grad_stride,
@@ -296,7 +334,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           const R y = rec[DIM * kWave + lane], z = rec[(DIM + 1) * kWave + lane];
           const uint32_t pr = rec_i[wid][0][lane], nr = rec_i[wid][1][lane];
           project<R, DIM>(D, xe, xr);
-          const R gv = g_value<R, DIM>(P, xr);
+          const R gv = g_value_tp<R, DIM, TP>(P, xr);
           const R phi = gv * y + z;
           const double ph = (double)phi;
           wn += 1.0;
@@ -315,7 +353,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
             for (int j = 0; j < NP; ++j) Br[j] -= phi * rec[(DIM + 2 + j) * kWave + lane];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-              if (t < P.g.n_terms) Gr[t] += y * term_value<R, DIM>(P.fac, P.g, t, xr);
+              if (t < P.g.n_terms) Gr[t] += y * TP::template term<R, DIM, FUN_G>(P, t, xr);
             yr = y;
           }
         }
@@ -420,13 +458,13 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           if (alive && n < max_steps) {
             R mono[NM > 0 ? NM : 1];
             if constexpr (DFC >= 0) monomials<R, DIM, DFC>(X, mono);
-            const R fv = bcf_value<R, DIM, DFC, TERMS>(P, P.f, X, mono);
-            const R cv = bcf_value<R, DIM, DFC, TERMS>(P, P.c, X, mono);
+            const R fv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_F>(P, X, mono);
+            const R cv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_C>(P, X, mono);
             if constexpr (ADJ) {
               const R Ydt = Y * dt;
 #pragma unroll
               for (int t = 0; t < NT; ++t)
-                if (t < P.f.n_terms) Fr[t] += term_value<R, DIM>(P.fac, P.f, t, X) * Ydt;
+                if (t < P.f.n_terms) Fr[t] += TP::template term<R, DIM, FUN_F>(P, t, X) * Ydt;
               if constexpr (NM > 0) {
                 if (P.f.poly_deg >= 0) {
 #pragma unroll
@@ -442,7 +480,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
 #pragma unroll
               for (int t = 0; t < NT; ++t) {
                 if (t < P.c.n_terms) {
-                  const R e = term_value<R, DIM>(P.fac, P.c, t, X) * dt;
+                  const R e = TP::template term<R, DIM, FUN_C>(P, t, X) * dt;
                   S[t] += e;
                   Br[t] += e * Z;
                 }
@@ -460,8 +498,9 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
             if (P.has_c) Y = Y * fexp(-cv * dt);
             if (P.has_b) {
               R bv[DIM];
-#pragma unroll
-              for (int k = 0; k < DIM; ++k) bv[k] = bcf_value<R, DIM, DFC, TERMS>(P, P.b[k], X, mono);
+              bv[0] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B0>(P, X, mono);
+              if constexpr (DIM >= 2) bv[1] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B1>(P, X, mono);
+              if constexpr (DIM >= 3) bv[2] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B2>(P, X, mono);
 #pragma unroll
               for (int k = 0; k < DIM; ++k) X[k] = X[k] + bv[k] * dt + sdt * z[s * DIM + k];
             } else {
@@ -802,6 +841,7 @@ k_walk_plain_adj(const LinearParams P, int node, uint32_t n_paths, ItemStat* __r
   for (int j = 0; j < NP; ++j) put(col + j, -gv * Y * S[j] - A[j]);
 }
 
+#ifndef __HIPCC_RTC__
 // ---------------------------------------------------------------------------
 // Launch of one k_walk instantiation, dispatched on dimension and on whether
 // b, c, f have a polynomial part.
@@ -830,5 +870,7 @@ template <typename R, int LAYOUT, bool ADJ>
 static hipError_t launch_walk_terms(const WalkLaunch& L, hipStream_t st) {
   return L.terms ? launch_walk_dim<R, LAYOUT, true, ADJ>(L, st) : launch_walk_dim<R, LAYOUT, false, ADJ>(L, st);
 }
+
+#endif  // __HIPCC_RTC__
 
 }  // namespace pdd

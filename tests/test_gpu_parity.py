@@ -277,6 +277,48 @@ def test_graph_replay_reads_current_coefficients(pdd):
 
 
 # ----------------------------------------------------------------------------- full-size sampled parity
+# ----------------------------------------------------------------------------- problem-specialised kernels
+def _spec_cases():
+    P2, n2, dt2 = CASES["c2"]()
+    P5, n5, dt5 = CASES["c5"]()
+    return [("c2", P2, n2, dt2), ("c5_terms", P5, n5, dt5)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_specialised_kernel_matches_table_kernel_per_path(pdd, precision):
+    """The runtime-compiled kernel (factor structure written in as constants)
+    evaluates the same operations in the same order as the table-driven
+    kernel: the same step count and value for every path."""
+    for name, P, nodes, dt in _spec_cases():
+        paths = np.array([300 + 37 * i for i in range(len(nodes))], np.int64)
+        kw = dict(precision=precision, schedule="persistent", chunk_paths=128, dump=True)
+        log(f"specialised vs table: {name} {precision} {len(nodes)} nodes")
+        a = pdd.mc_interface(P, nodes, paths, dt, 5, specialize="on", **kw)
+        b = pdd.mc_interface(P, nodes, paths, dt, 5, specialize="off", **kw)
+        torch.cuda.synchronize()
+        same_steps = (a["path_steps"] == b["path_steps"]).float().mean().item()
+        d = ((a["phi"] - b["phi"]).abs() / b["phi"].abs().clamp(min=1.0)).max().item()
+        log(f"  paths with equal step counts {same_steps:.6f}, max rel diff {d:.3e}")
+        assert same_steps == 1.0
+        assert d <= (1e-13 if precision == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_specialised_adjoint_matches_table_adjoint(pdd, precision):
+    P, nodes = _c5_small(3, 4)
+    paths = np.array([700, 257, 1024, 300], np.int64)
+    w = np.array([0.5, -1.0, 2.0, 0.25])
+    kw = dict(precision=precision, schedule="persistent", chunk_paths=256, with_stats=True)
+    a = pdd.mc_adjoint(P, nodes, paths, 4e-3, 8, w, specialize="on", **kw)
+    b = pdd.mc_adjoint(P, nodes, paths, 4e-3, 8, w, specialize="off", **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(a["stats"]["steps"], b["stats"]["steps"])
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    for k in ("g_coef", "g_poly", "f_coef", "f_poly", "c_coef", "c_poly"):
+        x, y = a[k].cpu().numpy(), b[k].cpu().numpy()
+        assert np.allclose(x, y, rtol=tol, atol=tol * max(1.0, np.abs(y).max())), k
+
+
 def test_c5_full_size_sampled_nodes(pdd, orc):
     """The benchmark's launch configuration (4096 nodes, 1e5 paths, FP32 graph
     schedule); 4 sampled nodes recomputed by the oracle at the same budget."""
