@@ -292,8 +292,7 @@ def other_workloads(pdd, dev):
     """Throughput of the other synthetic workloads (FP32 stepping, default
     schedule, cached graphs; one warm-up call each): C3's 4096-node batch
     over 8 layouts with variance-targeted budgets, C2's drift/killing/source
-    problem on the disk (5e4 of its 1e6 paths per node), C4's KPP branching
-    estimator (1e4 of its 1e5 trees per point)."""
+    problem on the disk and C4's KPP branching estimator, both at full size."""
     import torch
     from workloads import configs as CF
 
@@ -344,13 +343,25 @@ def other_workloads(pdd, dev):
                                        "err_vs_exact_rms_se": zrms}
     log(f"bench: C3 batch (walk on spheres): {elw * 1e3:.1f} ms, {jumps / elw:.3e} jumps/s, "
         f"error vs exact max {zmax:.1f} SE, rms {zrms:.1f} SE")
-    c2 = CF.c2(scale=0.05)
+    # C2 at its full size (256 nodes x 1e6 paths, dt = 1e-4); the first call
+    # also compiles the problem-specialised kernel (timed separately)
+    c2 = CF.c2()
     n2 = torch.tensor(c2.nodes, device=dev)
-    r2, el2 = timed(lambda: pdd.mc_interface(c2.problem, n2, c2.paths, c2.dt, c2.seed, precision="fp32"))
+    c2call = lambda: pdd.mc_interface(c2.problem, n2, c2.paths, c2.dt, c2.seed, precision="fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c2call()
+    torch.cuda.synchronize()
+    first2 = time.perf_counter() - t0
+    r2, el2 = timed(c2call)
     ps2 = float(r2["steps"].sum().item())
-    res["c2"] = {"nodes": len(c2.paths), "paths_per_node": int(c2.paths[0]), "path_steps": ps2, "seconds": el2,
-                 "path_steps_per_s": ps2 / el2}
-    log(f"bench: C2: {ps2:.3e} path-steps in {el2 * 1e3:.1f} ms, {ps2 / el2:.3e} path-steps/s")
+    z2 = np.abs(r2["mean"].cpu().numpy() - CF.c2_exact(c2.nodes)) / r2["se"].cpu().numpy()
+    res["c2"] = {"nodes": len(c2.paths), "paths_per_node": int(c2.paths[0]), "dt": c2.dt, "path_steps": ps2,
+                 "seconds": el2, "path_steps_per_s": ps2 / el2, "nodes_per_s": len(c2.paths) / el2,
+                 "first_call_seconds_incl_kernel_compile": first2, "max_se": float(r2["se"].max().item()),
+                 "err_vs_exact_max_se": float(z2.max()), "err_vs_exact_rms_se": float(np.sqrt(np.mean(z2 ** 2)))}
+    log(f"bench: C2: {ps2:.3e} path-steps in {el2 * 1e3:.1f} ms, {ps2 / el2:.3e} path-steps/s (first call "
+        f"{first2:.2f} s); error vs exact max {z2.max():.1f} SE, rms {np.sqrt(np.mean(z2 ** 2)):.1f} SE")
     # boundary-corrected exit test vs the plain one: C1 (harmonic data, exact
     # u = g) at dt = 4e-3 with 1e6 FP32 paths per node; error in SE units
     c1 = CF.c1(scale=100.0, dt=4e-3)
@@ -366,7 +377,7 @@ def other_workloads(pdd, dev):
     res["c1_boundary_correction_dt_4e-3"] = acc
     log(f"bench: C1 dt=4e-3 error vs exact (SE units): plain max {acc['plain']['max_err_se']:.1f}, "
         f"corrected max {acc['corrected']['max_err_se']:.1f}")
-    c4 = CF.c4(scale=0.1)
+    c4 = CF.c4()
     p4 = torch.tensor(c4.points, device=dev)
     r4, el4 = timed(lambda: pdd.branching_eval(c4.problem, p4, c4.trees, c4.seed, precision="fp32"))
     segs = float(r4["steps"].sum().item())

@@ -151,8 +151,7 @@ struct TableTerms {
 
 // b_k, c or f at X: generic terms (only when TERMS) plus the dense polynomial.
 template <typename R, int DIM, int DFC, bool TERMS, class TP, int W>
-__device__ __forceinline__ R bcf_value(const LinearParams& P, const R* X, const R* mono) {
-  const DevFun& F = fun_of<W>(P);
+__device__ __forceinline__ R bcf_value(const LinearParams& P, const DevFun& F, const R* X, const R* mono) {
   R v = (R)0;
   if constexpr (TERMS) {
     if (F.n_terms > 0) v = TP::template sum<R, DIM, W>(P, X);
@@ -458,8 +457,8 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           if (alive && n < max_steps) {
             R mono[NM > 0 ? NM : 1];
             if constexpr (DFC >= 0) monomials<R, DIM, DFC>(X, mono);
-            const R fv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_F>(P, X, mono);
-            const R cv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_C>(P, X, mono);
+            const R fv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_F>(P, P.f, X, mono);
+            const R cv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_C>(P, P.c, X, mono);
             if constexpr (ADJ) {
               const R Ydt = Y * dt;
 #pragma unroll
@@ -498,9 +497,14 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
             if (P.has_c) Y = Y * fexp(-cv * dt);
             if (P.has_b) {
               R bv[DIM];
-              bv[0] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B0>(P, X, mono);
-              if constexpr (DIM >= 2) bv[1] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B1>(P, X, mono);
-              if constexpr (DIM >= 3) bv[2] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B2>(P, X, mono);
+              if constexpr (TERMS) {
+                bv[0] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B0>(P, P.b[0], X, mono);
+                if constexpr (DIM >= 2) bv[1] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B1>(P, P.b[1], X, mono);
+                if constexpr (DIM >= 3) bv[2] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B2>(P, P.b[2], X, mono);
+              } else {
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) bv[k] = bcf_value<R, DIM, DFC, false, TP, FUN_B0>(P, P.b[k], X, mono);
+              }
 #pragma unroll
               for (int k = 0; k < DIM; ++k) X[k] = X[k] + bv[k] * dt + sdt * z[s * DIM + k];
             } else {
