@@ -15,7 +15,7 @@ from typing import Optional
 
 import numpy as np
 
-from workloads.problem import (BranchingProblem, DOM_FREE, Fun, LinearProblem,
+from workloads.problem import (BranchingBoundary, BranchingProblem, DOM_FREE, Fun, LinearProblem,
                                monomial_exponents)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -66,6 +66,11 @@ class OBranching(C.Structure):
                 ("q", C.c_double * 5), ("psi", OFun)]
 
 
+class OBranchBoundary(C.Structure):
+    _fields_ = [("dom", ODomain), ("g", OFun), ("dt", C.c_double), ("n_times", C.c_int32), ("pad", C.c_int32),
+                ("times", C.POINTER(C.c_double))]
+
+
 class OStat(C.Structure):
     _fields_ = [("mean", C.c_double), ("m2", C.c_double), ("n", C.c_int64), ("steps", C.c_int64),
                 ("censored", C.c_int64)]
@@ -101,6 +106,8 @@ def lib():
                                         C.c_int, C.POINTER(OStat), dp, ip, ip]
         L.orc_branching_alg31.argtypes = [C.POINTER(OBranching), dp, C.c_int64, C.c_int64, C.c_uint64, C.c_int,
                                           C.c_int, C.POINTER(OStat), ip]
+        L.orc_branching_bvp.argtypes = [C.POINTER(OBranching), C.POINTER(OBranchBoundary), dp, C.c_int64, C.c_int64,
+                                        C.c_uint64, C.c_int, C.c_int, C.POINTER(OStat), dp, ip, ip]
         _lib = L
     return _lib
 
@@ -360,4 +367,40 @@ def branching_alg31(B: BranchingProblem, points, trees: int, seed: int, max_part
         raise ValueError("oracle rejected the branching arguments")
     res = _stats(out[:n])
     res["redrawn"] = int(red.value)
+    return res
+
+
+def branching_bvp(B: BranchingProblem, Bd: BranchingBoundary, points, trees: int, seed: int, layout: int = PAIR52,
+                  n_threads: Optional[int] = None, dump: bool = False) -> dict:
+    """Branching estimator with particles stopped on a Dirichlet boundary
+    (eq. 3.2), evaluated at every output time of one tree (Algorithm 3.1).
+    Statistics have shape (n_times, n_points); dumps (n_points, trees,
+    n_times) values and (n_points, trees) segment counts."""
+    keep = _Keep()
+    o = _obranching(B, keep)
+    ob = OBranchBoundary()
+    ob.dom = _odomain(Bd.domain)
+    ob.g = _ofun(Bd.g, B.ndim, keep)
+    ob.dt = float(Bd.dt)
+    times = keep.arr(np.asarray(Bd.times, np.float64), np.float64)
+    ob.n_times = len(times)
+    ob.times = _ptr(times, C.c_double)
+    pts = keep.arr(points, np.float64)
+    n = len(pts)
+    nt = len(times)
+    out = (OStat * max(1, n * nt))()
+    val = np.zeros(n * trees * nt if dump else 1)
+    segs = np.zeros(n * trees if dump else 1, np.int64)
+    red = C.c_int64(0)
+    rc = lib().orc_branching_bvp(C.byref(o), C.byref(ob), _ptr(pts, C.c_double), n, trees, seed, layout,
+                                 default_threads() if n_threads is None else n_threads, out,
+                                 _ptr(val, C.c_double) if dump else None, _ptr(segs, C.c_int64) if dump else None,
+                                 C.byref(red))
+    if rc != 0:
+        raise ValueError("oracle rejected the branching-with-boundary arguments")
+    per_time = [_stats(out[k * n:(k + 1) * n]) for k in range(nt)]
+    res = {key: np.stack([r[key] for r in per_time]) for key in per_time[0]} if n else {}
+    res["redrawn"] = int(red.value)
+    if dump:
+        res["value"], res["segments"] = val.reshape(n, trees, nt), segs.reshape(n, trees)
     return res

@@ -869,3 +869,234 @@ int orc_branching_alg31(const orc_branching* B, const double* points, int64_t n_
   free(C.redrawn_per_point);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Branching with a Dirichlet boundary and several output times (eq. 3.2 and
+ * Algorithm 3.1).  Eq. 3.2: the particles of the branching system started at
+ * x are stopped when they reach the boundary of the domain; the estimator of
+ * u(x, t) is the product, over the particles present at time t, of psi(X_t)
+ * for those still inside and g(X_tau, t - tau) for those stopped at time tau
+ * (times the marks alpha_I / q_I of every branching before t, Sec. 3.2).
+ * Algorithm 3.1 evaluates one simulated tree at every output time t_i.
+ *
+ * Scheme (the paper gives the representation, not a discretisation): a
+ * particle born at time s0 with lifetime E (stream 1, as in the free-space
+ * estimator) moves by exact Brownian increments over sub-steps that end at
+ * min(s + dt, its death time s0 + E, the horizon t_last, the next output time
+ * t_k > s), and is tested against the boundary after every sub-step; a
+ * particle found outside is projected onto the boundary and stopped at the
+ * end time s of that sub-step (the linear walk's exit rule).  For every
+ * output time t_i >= s its factor is g(P X, t_i - s).  A particle still inside
+ * when a sub-step ends on t_k multiplies factor k by psi(X).  The sub-step
+ * that ends at the particle's death (before t_last) is not tested: the
+ * offspring count I is drawn from q, every output time after the death picks
+ * up alpha_I / q_I, and the children start at X, where each is tested at its
+ * birth (a particle born outside is stopped at its birth time s0 with factor
+ * g(P X, t_i - s0)).  Testing at the death instead, before branching, would
+ * look ahead to the death time and bias the estimator by O(dt) even for
+ * spatially constant solutions.  The start point is tested the same way; an
+ * output time t_i = 0 takes psi(x) when it is inside.
+ *
+ * Gaussians of a particle: number n d + k (sub-step n, coordinate k) comes
+ * from Philox block j = (n d + k) / m, slot (n d + k) mod m (m = 4 for the
+ * QUAD24 lattice, 2 for PAIR52), counter word0 = low 32 bits of the label,
+ * word1 = 5 << 28 | attempt << 24 | bits 32..47 of the label << 8 | bits 8..15
+ * of j, word2 = tree, word3 = point (24 bits) | bits 0..7 of j << 24 (stream
+ * 5; j < 2^16, point < 2^24).  Segment count, pruning and redraws as in the
+ * free-space estimator; a censored tree is 0 at every output time. */
+static double bvp_normal(const uint32_t key[2], int layout, uint64_t label, int attempt, uint32_t tree,
+                         uint32_t point, uint64_t g) {
+  const uint64_t per = (layout == ORC_QUAD24) ? 4 : 2;
+  const uint32_t j = (uint32_t)(g / per);
+  const int slot = (int)(g % per);
+  uint32_t ctr[4], w[4];
+  double tmp[4];
+  ctr[0] = (uint32_t)label;
+  ctr[1] = (5u << 28) | ((uint32_t)attempt << 24) | ((uint32_t)((label >> 32) & 0xFFFFu) << 8) | ((j >> 8) & 0xFFu);
+  ctr[2] = tree;
+  ctr[3] = (point & 0xFFFFFFu) | ((j & 0xFFu) << 24);
+  orc_philox4x32_10(ctr, key, w);
+  if (layout == ORC_QUAD24) {
+    box_muller(u_quad24(w[0]), u_quad24(w[1]), &tmp[0], &tmp[1]);
+    box_muller(u_quad24(w[2]), u_quad24(w[3]), &tmp[2], &tmp[3]);
+  } else {
+    box_muller(u_pair52(w[0], w[1]), u_pair52(w[2], w[3]), &tmp[0], &tmp[1]);
+  }
+  return tmp[slot];
+}
+
+/* g at (boundary point, time argument): the time is coordinate index dim */
+static double bvp_g(const orc_branch_boundary* Bd, int d, const double* xp, double s) {
+  double xs[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < d; ++k) xs[k] = xp[k];
+  xs[d] = s;
+  return orc_fun_eval(&Bd->g, xs);
+}
+
+static double bvp_psi(const orc_branching* B, int d, const double* x) {
+  double xs[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < d; ++k) xs[k] = x[k];
+  return orc_fun_eval(&B->psi, xs);
+}
+
+/* one tree; P[i] receives the value at output time i.  Returns 1 if pruned. */
+static int bvp_tree_once(const orc_branching* B, const orc_branch_boundary* Bd, const double* x0,
+                         const uint32_t key[2], int layout, int attempt, uint32_t tree, uint32_t point,
+                         br_seg* stack, double* P, int64_t* segs_out, int64_t* substeps) {
+  const int d = B->dim, nt = Bd->n_times;
+  const double* tt = Bd->times;
+  const double tend = tt[nt - 1];
+  const int bounded = Bd->dom.kind != ORC_FREE;
+  const uint64_t base = (uint64_t)label_base(B);
+  int64_t segs = 0;
+  for (int i = 0; i < nt; ++i) P[i] = 1.0;
+  double x[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < d; ++k) x[k] = x0[k];
+  if (!bounded || orc_inside(&Bd->dom, x))
+    for (int i = 0; i < nt; ++i)
+      if (tt[i] <= 0.0) P[i] *= bvp_psi(B, d, x);
+  int top = 0;
+  stack[0].label = 1;
+  for (int k = 0; k < 3; ++k) stack[0].x[k] = x[k];
+  stack[0].t = 0.0;
+  top = 1;
+  while (top > 0) {
+    br_seg sg = stack[--top];
+    segs += 1;
+    if (segs > B->max_segments) { *segs_out = segs; return 1; }
+    if (bounded && !orc_inside(&Bd->dom, sg.x)) {
+      /* born outside (the start point, or the death point of its parent):
+         stopped at its birth time */
+      double xp[3];
+      orc_project(&Bd->dom, sg.x, xp);
+      for (int i = 0; i < nt; ++i)
+        if (tt[i] >= sg.t) P[i] *= bvp_g(Bd, d, xp, tt[i] - sg.t);
+      continue;
+    }
+    double ulife, utype;
+    branch_uniforms(key, layout, sg.label, attempt, tree, point, &ulife, &utype);
+    const double E = -log(ulife) / B->beta;
+    const double sdeath = sg.t + E;
+    const double send = sdeath < tend ? sdeath : tend;
+    double s = sg.t;
+    int k = 0;
+    while (k < nt && !(tt[k] > s)) ++k;
+    uint64_t gi = 0;
+    int stopped = 0;
+    while (s < send) {
+      double sn = s + Bd->dt;
+      if (send < sn) sn = send;
+      if (k < nt && tt[k] < sn) sn = tt[k];
+      const double sd = B->sigma * sqrt(sn - s);
+      *substeps += 1;
+      for (int c = 0; c < d; ++c) {
+        const double z = bvp_normal(key, layout, sg.label, attempt, tree, point, gi++);
+        sg.x[c] = sg.x[c] + sd * z;
+      }
+      s = sn;
+      /* the sub-step that ends at the particle's death is followed by the
+         branching, not by the boundary test: its children start there and
+         are tested at their birth */
+      const int dies = s == sdeath && sdeath < tend;
+      if (!dies && bounded && !orc_inside(&Bd->dom, sg.x)) {
+        double xp[3];
+        orc_project(&Bd->dom, sg.x, xp);
+        for (int i = 0; i < nt; ++i)
+          if (tt[i] >= s) P[i] *= bvp_g(Bd, d, xp, tt[i] - s);
+        stopped = 1;
+        break;
+      }
+      if (k < nt && s == tt[k]) {
+        P[k] *= bvp_psi(B, d, sg.x);
+        ++k;
+      }
+    }
+    if (stopped || !(sdeath < tend)) continue;
+    const int I = pick_type(B->q, utype);
+    const double wmark = B->alpha[I] / B->q[I];
+    for (int i = 0; i < nt; ++i)
+      if (tt[i] > sdeath) P[i] *= wmark;
+    for (int i = I - 1; i >= 0; --i) {
+      uint64_t child = base * sg.label + (uint64_t)i;
+      if (child >= (1ull << 48) || sg.label >= (1ull << 47) || top >= BR_MAX_STACK) { *segs_out = segs; return 1; }
+      stack[top].label = child;
+      for (int c = 0; c < 3; ++c) stack[top].x[c] = sg.x[c];
+      stack[top].t = sdeath;
+      top++;
+    }
+  }
+  *segs_out = segs;
+  return 0;
+}
+
+typedef struct {
+  const orc_branching* B;
+  const orc_branch_boundary* Bd;
+  const double* points;
+  int64_t n_points, trees;
+  uint32_t key[2];
+  int layout;
+  orc_stat* out;
+  double* dump_val;
+  int64_t* dump_segs;
+  int64_t* redrawn_per_point;
+} bvp_ctx;
+
+static void bvp_point(void* vctx, int64_t i, int worker) {
+  (void)worker;
+  bvp_ctx* C = (bvp_ctx*)vctx;
+  const int nt = C->Bd->n_times, d = C->B->dim;
+  br_seg* stack = (br_seg*)malloc(sizeof(br_seg) * BR_MAX_STACK);
+  double* P = (double*)malloc(sizeof(double) * (size_t)nt);
+  orc_stat* s = (orc_stat*)calloc((size_t)nt, sizeof(orc_stat));
+  int64_t redrawn = 0, subsum = 0, cens = 0;
+  for (int64_t t = 0; t < C->trees; ++t) {
+    int64_t segs = 0;
+    int ok = 0;
+    for (int attempt = 0; attempt < 16; ++attempt) {
+      if (bvp_tree_once(C->B, C->Bd, &C->points[i * d], C->key, C->layout, attempt, (uint32_t)t, (uint32_t)i,
+                        stack, P, &segs, &subsum) == 0) { ok = 1; break; }
+      redrawn += 1;
+    }
+    if (!ok) {
+      for (int k = 0; k < nt; ++k) P[k] = 0.0;
+      cens += 1;
+    }
+    for (int k = 0; k < nt; ++k) welford_push(&s[k], P[k]);
+    if (C->dump_val)
+      for (int k = 0; k < nt; ++k) C->dump_val[(i * C->trees + t) * nt + k] = P[k];
+    if (C->dump_segs) C->dump_segs[i * C->trees + t] = segs;
+  }
+  for (int k = 0; k < nt; ++k) {
+    s[k].steps = subsum;
+    s[k].censored = cens;
+    C->out[(int64_t)k * C->n_points + i] = s[k];
+  }
+  C->redrawn_per_point[i] = redrawn;
+  free(s); free(P); free(stack);
+}
+
+int orc_branching_bvp(const orc_branching* B, const orc_branch_boundary* Bd, const double* points,
+                      int64_t n_points, int64_t trees, uint64_t seed, int layout, int n_threads,
+                      orc_stat* out, double* dump_val, int64_t* dump_segs, int64_t* redrawn) {
+  if (B->dim < 1 || B->dim > 3 || !(B->beta > 0.0) || Bd->n_times < 1 || !(Bd->dt > 0.0)) return -1;
+  if (Bd->dom.kind != ORC_FREE && Bd->dom.dim != B->dim) return -1;
+  for (int i = 0; i < Bd->n_times; ++i)
+    if (!(Bd->times[i] >= 0.0) || (i > 0 && !(Bd->times[i] > Bd->times[i - 1]))) return -1;
+  if (n_points >= (1ll << 24)) return -1;
+  /* Gaussian blocks per particle stay below 2^16 */
+  const double per = layout == ORC_QUAD24 ? 4.0 : 2.0;
+  if ((ceil(Bd->times[Bd->n_times - 1] / Bd->dt) + Bd->n_times + 2.0) * B->dim / per >= 65536.0) return -1;
+  bvp_ctx C;
+  memset(&C, 0, sizeof(C));
+  C.B = B; C.Bd = Bd; C.points = points; C.n_points = n_points; C.trees = trees; C.layout = layout;
+  C.out = out; C.dump_val = dump_val; C.dump_segs = dump_segs;
+  C.redrawn_per_point = (int64_t*)calloc((size_t)n_points + 1, sizeof(int64_t));
+  make_key(seed, C.key);
+  run_pool(n_threads, n_points, bvp_point, &C);
+  int64_t tot = 0;
+  for (int64_t i = 0; i < n_points; ++i) tot += C.redrawn_per_point[i];
+  if (redrawn) *redrawn = tot;
+  free(C.redrawn_per_point);
+  return 0;
+}

@@ -19,7 +19,10 @@
  *   - the branching-diffusion estimator of Sec. 3.1 (eq. 3.1, the particle
  *     system described after Assumption 3.1) in its marked form of Sec. 3.2,
  *     simulated per particle (depth first) and, separately, in the
- *     global-clock form of Algorithm 3.1.
+ *     global-clock form of Algorithm 3.1;
+ *   - the same estimator with particles stopped on a Dirichlet boundary
+ *     (eq. 3.2) and evaluated at several output times of one tree
+ *     (Algorithm 3.1).
  *
  * Every free choice the paper leaves open is fixed as described in the
  * project's design notes (sign of c, exit test, quadrature, RNG layout,
@@ -79,6 +82,17 @@ typedef struct {
   orc_fun psi;
 } orc_branching;
 
+/* Dirichlet boundary and output times of the branching estimator (eq. 3.2,
+ * Algorithm 3.1).  g(x, s) is evaluated at (x_0, .., x_{dim-1}, s): a factor
+ * with coordinate index dim reads the time argument s.  FREE: no boundary. */
+typedef struct {
+  orc_domain dom;
+  orc_fun g;
+  double dt;                   /* step of the boundary test */
+  int32_t n_times, pad;
+  const double* times;         /* [n_times], increasing, >= 0; the last is the horizon */
+} orc_branch_boundary;
+
 typedef struct {
   double mean, m2;
   int64_t n, steps, censored;
@@ -128,6 +142,17 @@ int orc_branching_dfs(const orc_branching* B, const double* points, int64_t n_po
 int orc_branching_alg31(const orc_branching* B, const double* points, int64_t n_points,
                         int64_t trees, uint64_t seed, int max_particles, int n_threads,
                         orc_stat* out, int64_t* redrawn);
+
+/* branching with a Dirichlet boundary, evaluated at every output time of one
+   simulated tree: out[k * n_points + i] is the statistic of point i at time
+   times[k] (its steps = particle sub-steps of all draws of the point's trees,
+   the same for every k); dump_val[(i * trees + t) * n_times + k],
+   dump_segs[i * trees + t] (particles of the accepted draw).
+   Returns -1 on invalid arguments (including more than 2^16 Gaussian blocks
+   per particle, or 2^24 points or more). */
+int orc_branching_bvp(const orc_branching* B, const orc_branch_boundary* Bd, const double* points,
+                      int64_t n_points, int64_t trees, uint64_t seed, int layout, int n_threads,
+                      orc_stat* out, double* dump_val, int64_t* dump_segs, int64_t* redrawn);
 
 #ifdef __cplusplus
 }

@@ -430,6 +430,86 @@ def test_branching_pruning_redraws(orc):
     assert np.all(r["segments"] <= 3)
 
 
+# ----------------------------------------------------------------------------- branching with a boundary
+def test_branching_bvp_logistic_boundary_data_is_exact_at_every_time(orc):
+    """Eq. 3.2 with constant initial data c and boundary data equal to the
+    logistic solution L(s) of u' = beta (u^2 - u): u(x, t) = L(t) everywhere,
+    and since L is constant in space the estimator is unbiased for any dt
+    (optional stopping).  Pins the time argument t_i - tau of g, the per-time
+    products and marks, and the rule that a particle dying after a sub-step
+    branches before any boundary test (testing first looks ahead to the death
+    time and leaves an O(dt) bias, about 5e-3 at dt = 0.1)."""
+    times = (0.0, 0.25, 0.5, 1.0)
+    for dom, dt in ((box((-0.5,), (0.5,)), 0.1), (box((-0.5,), (0.5,)), 1e-2), (ball(2, 0.6), 0.05),
+                    (box((-0.5, -0.4, -0.3), (0.5, 0.4, 0.3)), 0.05)):
+        B, Bd = CF.kpp_bvp_logistic(dom, 0.3, 1.0, dt, times)
+        d = dom.ndim
+        pts = np.zeros((2, d))
+        pts[1, 0] = 0.3 if d > 1 else 0.2
+        r = orc.branching_bvp(B, Bd, pts, 30000, 7, layout=orc.PAIR52 if d != 2 else orc.QUAD24)
+        exact = CF.logistic(0.3, 1.0, np.asarray(times))[:, None]
+        assert np.all(r["mean"][0] == 0.3)
+        assert z_ok(r["mean"][1:], r["se"][1:], exact[1:]), (d, dt, (r["mean"] - exact) / np.maximum(r["se"], 1e-300))
+    # time-reversed boundary data L(-s) is far off: the test above can tell
+    # a wrong time argument of g apart
+    B, Bd = CF.kpp_bvp_logistic(box((-0.5,), (0.5,)), 0.3, 1.0, 1e-2, times)
+    wrong = CF.kpp_bvp_logistic(box((-0.5,), (0.5,)), 0.3, -1.0, 1e-2, times)[1].g
+    Bw = type(Bd)(Bd.domain, wrong, Bd.g_sup, Bd.dt, Bd.times)
+    rw = orc.branching_bvp(B, Bw, np.zeros((1, 1)), 30000, 7)
+    exact = CF.logistic(0.3, 1.0, np.asarray(times))
+    assert np.max(np.abs(rw["mean"][1:, 0] - exact[1:]) / rw["se"][1:, 0]) > 10.0
+
+
+def test_branching_bvp_paper_travelling_wave_with_boundary(orc):
+    """The paper's KPP travelling wave (Sec. 3.1) on a bounded interval with
+    the wave itself as Dirichlet data on both ends: the wave is the exact
+    solution of the boundary-value problem.  The discrete boundary test leaves
+    an O(sqrt dt) overshoot bias, bounded by 0.5826 sigma sqrt(dt) max|u_x|."""
+    times = (0.25, 0.5, 1.0)
+    B, Bd = CF.kpp_bvp_travelling_wave(-1.0, 1.5, 1e-3, times)
+    pts = np.array([[-0.6], [0.0], [0.8], [1.3]])
+    r = orc.branching_bvp(B, Bd, pts, 30000, 11)
+    exact = np.array([CF.travelling_wave(pts[:, 0], t) for t in times])
+    ux = 2.0 * (4.0 / 27.0) / math.sqrt(6.0)   # max |u_x| of the wave (at e^z = 1/2)
+    bias = 0.5826 * B.sigma * math.sqrt(Bd.dt) * ux
+    assert z_ok(r["mean"], r["se"], exact, extra=bias), (r["mean"] - exact) / r["se"]
+    # a reflected wave on the boundary (data of x -> -x) is clearly off
+    Bm, Bdm = CF.kpp_bvp_travelling_wave(-1.5, 1.0, 1e-3, times)
+    Bdx = type(Bd)(Bd.domain, Bdm.g, Bd.g_sup, Bd.dt, Bd.times)
+    rx = orc.branching_bvp(B, Bdx, pts, 30000, 11)
+    assert np.max(np.abs(rx["mean"] - exact) - 4 * rx["se"] - bias) > 0.0
+
+
+def test_branching_bvp_free_space_times_match_single_time_estimator(orc):
+    """Without a boundary the multi-time estimator at each output time t_i has
+    the law of the free-space estimator run to T = t_i (Algorithm 3.1 reads one
+    tree at every T_i); sub-steps at the output times must not change it."""
+    B4 = CF.c4_problem("tanh")
+    pts = np.array([[-0.7, 0.1, 0.0], [0.4, -0.5, 0.2]])
+    times = (0.3, 0.7, 1.0)
+    from workloads.problem import BranchingBoundary, free
+    Bd = BranchingBoundary(free(3), const_fun(0.0), 0.0, 0.05, times)
+    r = orc.branching_bvp(B4, Bd, pts, 30000, 13, layout=orc.QUAD24)
+    for k, t in enumerate(times):
+        Bt = BranchingProblem(3, B4.sigma, B4.beta, t, B4.alpha, B4.q, B4.psi, B4.psi_sup, B4.max_segments)
+        o = orc.branching(Bt, pts, 30000, 14)
+        assert np.all(np.abs(r["mean"][k] - o["mean"]) <= 4.0 * np.sqrt(r["se"][k] ** 2 + o["se"] ** 2)), t
+
+
+def test_branching_bvp_start_outside_and_pruning(orc):
+    """A start point outside the domain is stopped at time 0 (value g(P x, t_i));
+    a tiny segment cap redraws trees and never leaves a tree without values."""
+    times = (0.0, 0.5)
+    B, Bd = CF.kpp_bvp_logistic(box((-0.5,), (0.5,)), 0.3, 1.0, 0.05, times)
+    r = orc.branching_bvp(B, Bd, np.array([[0.9], [-2.0]]), 50, 1, dump=True)
+    assert np.allclose(r["value"][:, :, 0], 0.3, rtol=1e-14)
+    assert np.allclose(r["value"][:, :, 1], CF.logistic(0.3, 1.0, 0.5), rtol=1e-13)
+    Bp = BranchingProblem(1, 1.0, 2.0, 1.0, B.alpha, B.q, B.psi, B.psi_sup, max_segments=3)
+    Bd2 = type(Bd)(Bd.domain, Bd.g, Bd.g_sup, Bd.dt, (1.0,))
+    rp = orc.branching_bvp(Bp, Bd2, np.zeros((1, 1)), 500, 2, dump=True)
+    assert rp["redrawn"] > 0 and rp["n"][0, 0] == 500 and np.all(rp["segments"] <= 3)
+
+
 # ----------------------------------------------------------------------------- adjoint
 def _small_adjoint_problem(seed=0):
     rng = np.random.default_rng(seed)

@@ -31,7 +31,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from .problem import (BranchingProblem, Fun, LinearProblem, ball, box, const_fun,
+from .problem import (BranchingBoundary, BranchingProblem, Domain, Fun, LinearProblem, ball, box, const_fun,
                       factor, make_fun, monomial_exponents, n_monomials, zero_fun)
 
 
@@ -264,6 +264,71 @@ def kpp_travelling_wave_problem() -> BranchingProblem:
                     (-0.25, [factor("tanh", 0, a=k, power=2)])])
     return BranchingProblem(1, math.sqrt(2.0), 1.0, 1.0, (0.0, 0.0, 1.0, 0.0, 0.0),
                             (0.0, 0.0, 1.0, 0.0, 0.0), psi, 1.0, 127)
+
+
+# --------------------------------------------------------------------------- branching with a boundary
+def travelling_wave(x, t):
+    """The paper's KPP travelling wave u(x, t) = 1 - (1 + e^{x/sqrt6 - 5t/6})^-2."""
+    return 1.0 - (1.0 + np.exp(np.asarray(x) / math.sqrt(6.0) - 5.0 * np.asarray(t) / 6.0)) ** -2
+
+
+def kpp_bvp_travelling_wave(x1: float, x2: float, dt: float, times, max_segments: int = 255):
+    """The paper's KPP example on the interval (x1, x2) with Dirichlet data
+    equal to the travelling wave on both ends (eq. 3.2), so the travelling
+    wave is the exact solution.  With z = x/sqrt6 - 5s/6 the wave is
+    3/4 + T/2 - T^2/4, T = tanh(z/2); at an end point x_b it is a function of
+    the time argument s alone, and g interpolates the two ends linearly in x:
+    g(x, s) = sum_b w_b(x) u(x_b, s), w_1 = (x2 - x)/(x2 - x1), w_2 = (x - x1)/(x2 - x1)
+    (coordinate index 1 is s)."""
+    B = kpp_travelling_wave_problem()
+    B = BranchingProblem(B.ndim, B.sigma, B.beta, float(max(times)), B.alpha, B.q, B.psi, B.psi_sup, max_segments)
+    L = x2 - x1
+    terms = []
+    for xb, (wa, wb) in ((x1, (-1.0 / L, x2 / L)), (x2, (1.0 / L, -x1 / L))):
+        w = factor("pow", 0, a=wa, b=wb)
+        th = lambda p, xb=xb: factor("tanh", 1, a=-5.0 / 12.0, b=xb / (2.0 * math.sqrt(6.0)), power=p)
+        terms += [(0.75, [w, factor("pow", 0, power=0)]), (0.5, [w, th(1)]), (-0.25, [w, th(2)])]
+    Bd = BranchingBoundary(box((x1,), (x2,)), make_fun(terms), 1.0, float(dt), tuple(float(t) for t in times))
+    return B, Bd
+
+
+def kpp_bvp_logistic(domain: Domain, c: float, beta: float, dt: float, times, max_segments: int = 255):
+    """Binary branching (alpha_2 = 1) with constant initial data c and boundary
+    data equal to the logistic solution L(s) = 1 / (1 + ((1 - c)/c) e^{beta s})
+    of u' = beta (u^2 - u): the solution is L(t) at every point, and the
+    estimator is unbiased for any dt (the solution is constant in space).
+    L(s) = 1/2 - tanh(beta s / 2 + ln((1 - c)/c) / 2) / 2."""
+    d = domain.ndim
+    B = BranchingProblem(d, 1.0, beta, float(max(times)), (0.0, 0.0, 1.0, 0.0, 0.0), (0.0, 0.0, 1.0, 0.0, 0.0),
+                         const_fun(c), abs(c), max_segments)
+    g = make_fun([(0.5, []), (-0.5, [factor("tanh", d, a=beta / 2.0, b=0.5 * math.log((1.0 - c) / c))])])
+    return B, BranchingBoundary(domain, g, 1.0, float(dt), tuple(float(t) for t in times))
+
+
+def logistic(c: float, beta: float, t):
+    return 1.0 / (1.0 + (1.0 - c) / c * np.exp(beta * np.asarray(t)))
+
+
+@dataclass
+class BranchingBvpWorkload:
+    name: str
+    problem: BranchingProblem
+    boundary: BranchingBoundary
+    points: np.ndarray
+    trees: int
+    seed: int
+
+
+def c6(scale: float = 1.0, seed: int = 0, n_points: int = 1024, dt: float = 1e-3) -> BranchingBvpWorkload:
+    """The paper's KPP PDD setting (Sec. 3.1, Algorithm 3.1) on a bounded
+    interval: u_t = u_xx + u^2 - u on (-5, 5) (the interval of the paper's
+    error comparison) with travelling-wave initial and boundary data, 11
+    output times 0, 0.1, .., 1 (the paper's Theta), n_points interior points
+    evenly spaced (the interface nodes of a fine partition), 1e5 trees per
+    point (the paper's N), boundary test every dt."""
+    B, Bd = kpp_bvp_travelling_wave(-5.0, 5.0, dt, tuple(0.1 * k for k in range(11)))
+    pts = (-5.0 + 10.0 * (np.arange(n_points) + 0.5) / n_points).reshape(-1, 1)
+    return BranchingBvpWorkload("C6 KPP with boundary, 11 times", B, Bd, pts, _budget(100_000, scale), seed)
 
 
 # --------------------------------------------------------------------------- C5

@@ -175,3 +175,20 @@ class BranchingProblem:
     psi: Fun
     psi_sup: float
     max_segments: int = 127
+
+
+@dataclass
+class BranchingBoundary:
+    """Dirichlet boundary and output times for the branching estimator
+    (eq. 3.2, Algorithm 3.1): particles stop on the boundary of `domain`
+    (BOX or BALL; FREE means no boundary) and contribute g(X_tau, t - tau) to
+    every output time t >= tau.  `g` is evaluated at (x_0, .., x_{ndim-1}, s):
+    a factor with coordinate index ndim reads the time argument s (the
+    polynomial part is in x only).  `g_sup` bounds |g| (admissibility), `dt`
+    is the step of the boundary test and `times` are the output times
+    (increasing; the last one is the horizon)."""
+    domain: Domain
+    g: Fun
+    g_sup: float
+    dt: float
+    times: Tuple[float, ...]
