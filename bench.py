@@ -64,8 +64,8 @@ OPS_PER_PS_ADJ = 182.0
 # calibration (x 2.000 / x 1.000).  Valid only for the kernel sources they
 # were counted on: any change to them makes the bench report null.
 TRAFFIC_SOURCES = ['paper_1705_03666_amd/csrc/walk_kernels.hpp', 'paper_1705_03666_amd/csrc/pdd_device.hpp', 'paper_1705_03666_amd/csrc/pdd_internal.hpp', 'paper_1705_03666_amd/csrc/walk_adj_f32.hip']
-TRAFFIC_SHA256 = "b8cb9e23f96fe42deecd1c689b5988effa3c45e290d3359182427a0758461794"
-TRAFFIC_BYTES = 36.90e6 + 95.37e6
+TRAFFIC_SHA256 = "d4fad38258d8098589a2f8ba40a3ad1179b86856d2c64b1b60a23da6625e3289"
+TRAFFIC_BYTES = 37.06e6 + 95.38e6
 
 
 def traffic_bytes():
@@ -292,7 +292,8 @@ def other_workloads(pdd, dev):
     """Throughput of the other synthetic workloads (FP32 stepping, default
     schedule, cached graphs; one warm-up call each): C3's 4096-node batch
     over 8 layouts with variance-targeted budgets, C2's drift/killing/source
-    problem on the disk and C4's KPP branching estimator, both at full size."""
+    problem on the disk and C4's KPP branching estimator, both at full size;
+    C6, the branching estimator with a Dirichlet boundary at 11 output times."""
     import torch
     from workloads import configs as CF
 
@@ -385,6 +386,23 @@ def other_workloads(pdd, dev):
     res["c4"] = {"points": len(c4.points), "trees_per_point": c4.trees, "segments": segs, "seconds": el4,
                  "trees_per_s": trees / el4, "segments_per_s": segs / el4}
     log(f"bench: C4: {trees:.3e} trees, {segs:.3e} segments in {el4 * 1e3:.1f} ms")
+    # C6: KPP with a Dirichlet boundary and 11 output times (eq. 3.2,
+    # Algorithm 3.1); the travelling wave is the exact solution
+    c6 = CF.c6()
+    p6 = torch.tensor(c6.points, device=dev)
+    r6, el6 = timed(lambda: pdd.branching_bvp(c6.problem, c6.boundary, p6, c6.trees, c6.seed, precision="fp32"))
+    sub = float(r6["steps"][0].sum().item())
+    tr6 = float(len(c6.points) * c6.trees)
+    ex6 = np.array([CF.travelling_wave(c6.points[:, 0], t) for t in c6.boundary.times])
+    z6 = (np.abs(r6["mean"].cpu().numpy() - ex6) / np.maximum(r6["se"].cpu().numpy(), 1e-300))[1:]
+    res["c6_branching_boundary"] = {"points": len(c6.points), "trees_per_point": c6.trees,
+                                    "output_times": len(c6.boundary.times), "dt": c6.boundary.dt,
+                                    "particle_substeps": sub, "seconds": el6, "trees_per_s": tr6 / el6,
+                                    "substeps_per_s": sub / el6, "err_vs_exact_max_se": float(z6.max()),
+                                    "err_vs_exact_rms_se": float(np.sqrt(np.mean(z6 ** 2)))}
+    log(f"bench: C6: {tr6:.3e} trees x {len(c6.boundary.times)} times, {sub:.3e} particle sub-steps in "
+        f"{el6 * 1e3:.1f} ms ({sub / el6:.3e}/s); error vs exact max {z6.max():.1f} SE, "
+        f"rms {np.sqrt(np.mean(z6 ** 2)):.1f} SE")
     return res
 
 
@@ -456,6 +474,8 @@ def main():
                     help="run only the timed value+Jacobian steps (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 256 MiB (reference for the FETCH/WRITE counters)")
+    ap.add_argument("--c2-only", action="store_true",
+                    help="only run C2 at full size twice (the first call compiles its kernel; for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
@@ -468,6 +488,22 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}), flush=True)
+        return
+    if args.c2_only:
+        import torch
+        import paper_1705_03666_amd as pdd
+        from workloads import configs as CF
+        c2 = CF.c2()
+        n2 = torch.tensor(c2.nodes, device="cuda")
+        for i in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = pdd.mc_interface(c2.problem, n2, c2.paths, c2.dt, c2.seed, precision="fp32")
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            ps = float(r["steps"].sum().item())
+            print(json.dumps({"workload": "C2", "call": i + 1, "path_steps": ps, "seconds": el,
+                              "path_steps_per_s": ps / el}), flush=True)
         return
     out = run(args)
     print(json.dumps(out), flush=True)

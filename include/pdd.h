@@ -130,6 +130,28 @@ typedef struct {
   pdd_fun psi;
 } pdd_branching_problem;
 
+/* Dirichlet boundary and output times of the branching estimator (eq. 3.2:
+ * particles are stopped on the boundary of `domain`; Algorithm 3.1: one tree
+ * is evaluated at several times T_0 < T_1 < ...).  domain: BOX or BALL of the
+ * problem's dim, or FREE (no boundary: the free-space estimator at several
+ * times).  g: boundary data g(x, s) at a boundary point x and time argument s;
+ * a factor whose dim equals the problem's dim reads s (its polynomial part is
+ * in x only).  g_sup bounds |g| (admissibility, with psi_sup, over
+ * [0, last time]).  dt: the particles move by exact Brownian increments over
+ * sub-steps of at most dt that also end at every output time and at the
+ * particle's death, and are tested against the boundary after each sub-step
+ * (not the one ending at the death: children are tested at birth).  times:
+ * host [n_times], 1 <= n_times <= 12, finite, >= 0, strictly increasing; the
+ * last one is the horizon (problem.T is not used). */
+typedef struct {
+  pdd_domain domain;
+  pdd_fun g;
+  double g_sup;
+  double dt;
+  int32_t n_times, pad;
+  const double* times;
+} pdd_branching_boundary;
+
 /* ---------------------------------------------------------------- options */
 
 typedef enum {
@@ -228,6 +250,27 @@ pdd_status pdd_wos_interface(const pdd_linear_problem* problem, const double* no
 pdd_status pdd_branching_eval(const pdd_branching_problem* problem, const double* points_dev,
                               int64_t n_points, int64_t trees_per_point, uint64_t seed,
                               const pdd_options* options, pdd_node_stat* out_dev, void* hip_stream);
+
+/* Branching estimator with a Dirichlet boundary, evaluated at every output
+ * time of one simulated tree (eq. 3.2 and Algorithm 3.1, the paper's KPP
+ * setting for PDD).  For a point x and output time t the tree's value is the
+ * product of psi(X_t) over the particles inside the domain at t, of
+ * g(X_tau, t - tau) over those stopped on the boundary at tau <= t (projected
+ * onto it), and of alpha_I / q_I over the branchings before t.
+ *  out_dev: device [n_times][n_points] (time-major: one pdd_node_stat array
+ *  per output time); steps = particle sub-steps simulated for the point (all
+ *  draws), the same for every time; censored = trees that failed 16 draws
+ *  (value 0 at every time).
+ *  options->dump_phi: optional device [n_points][trees][n_times] values;
+ *  options->dump_steps: optional device [n_points][trees] segment counts.
+ * Limits: n_points < 2^24; at most 2^16 Gaussian blocks per particle, i.e.
+ * (ceil(t_last / dt) + n_times + 2) dim / m < 2^16 (m = 4 normals per block
+ * for QUAD24, 2 for PAIR52), else PDD_ERR_UNSUPPORTED.  Counter layout of the
+ * particle Gaussians: stream 5 (word1 = 5 << 28 | attempt << 24 | label bits
+ * 32..47 << 8 | block >> 8, word3 = point | (block & 255) << 24). */
+pdd_status pdd_branching_bvp(const pdd_branching_problem* problem, const pdd_branching_boundary* boundary,
+                             const double* points_dev, int64_t n_points, int64_t trees_per_point, uint64_t seed,
+                             const pdd_options* options, pdd_node_stat* out_dev, void* hip_stream);
 
 /* Gradient of sum_i w_i u_i with respect to the coefficient arrays of g, f and c
  * (the exact derivative of the discrete estimator, same paths as

@@ -390,6 +390,58 @@ def branching_eval(problem, points, trees: int, seed: int = 0, precision: str = 
     return res
 
 
+def branching_bvp(problem, boundary, points, trees: int, seed: int = 0, precision: str = "fp32",
+                  layout: Optional[str] = None, dump: bool = False, chunk_paths: int = 0,
+                  blocks_per_cu: int = 0) -> Dict[str, torch.Tensor]:
+    """Branching estimator with particles stopped on a Dirichlet boundary,
+    evaluated at every output time of one tree (pdd_branching_bvp).
+    `boundary` is a workloads.problem.BranchingBoundary.  Statistics have
+    shape [n_times, n_points]; with dump=True also `value` [n, trees, n_times]
+    and `segments` [n, trees]."""
+    _need_gpu()
+    keep = _Keep()
+    b = A.pdd_branching_problem()
+    b.dim = int(problem.ndim)
+    b.max_segments = int(problem.max_segments)
+    b.sigma, b.beta, b.T = float(problem.sigma), float(problem.beta), float(problem.T)
+    for k in range(5):
+        b.alpha[k] = float(problem.alpha[k]) if k < len(problem.alpha) else 0.0
+        b.q[k] = float(problem.q[k]) if k < len(problem.q) else 0.0
+    b.psi_sup = float(problem.psi_sup)
+    b.psi = _fun(problem.psi, keep)
+    bd = A.pdd_branching_boundary()
+    D = boundary.domain
+    bd.domain.kind, bd.domain.dim = int(D.kind), int(D.ndim)
+    for k in range(3):
+        bd.domain.lo[k], bd.domain.hi[k], bd.domain.center[k] = float(D.lo[k]), float(D.hi[k]), float(D.center[k])
+    bd.domain.radius = float(D.radius)
+    bd.g = _fun(boundary.g, keep)
+    bd.g_sup = float(boundary.g_sup)
+    bd.dt = float(boundary.dt)
+    times = np.ascontiguousarray(np.asarray(boundary.times, dtype=np.float64).reshape(-1))
+    keep.append(times)
+    bd.n_times = int(times.shape[0])
+    bd.times = times.ctypes.data_as(C.POINTER(C.c_double))
+    nt = bd.n_times
+    pt = _nodes_tensor(points, b.dim)
+    n = pt.shape[0]
+    raw = torch.empty((max(n * nt, 1), 5), dtype=torch.float64, device="cuda")
+    dv = ds = None
+    if dump:
+        dv = torch.empty(max(n * trees * nt, 1), dtype=torch.float64, device="cuda")
+        ds = torch.empty(max(n * trees, 1), dtype=torch.int64, device="cuda")
+    o = _options(precision, layout, 0, "persistent", chunk_paths, blocks_per_cu, 0, dv, ds)
+    st = library().pdd_branching_bvp(C.byref(b), C.byref(bd), pt.data_ptr() if n else None, n, int(trees),
+                                     int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(), _stream_handle())
+    _check(st, "pdd_branching_bvp")
+    res = {k: v.reshape(nt, n) for k, v in _stats(raw[:n * nt]).items()}
+    if dump:
+        res["value"] = dv[:n * trees * nt].reshape(n, trees, nt)
+        res["segments"] = ds[:n * trees].reshape(n, trees)
+    res["_keep"] = keep
+    return res
+
+
 def query_warnings():
     """Synchronizes the current stream; returns (censored paths, redrawn trees)
     since the last query."""

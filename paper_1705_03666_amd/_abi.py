@@ -15,7 +15,8 @@ PDD_FP64_PLAIN, PDD_FP64, PDD_FP32_STEP = 0, 1, 2
 PDD_RNG_PAIR52, PDD_RNG_QUAD24 = 0, 1
 PDD_SCHED_AUTO, PDD_SCHED_PERSISTENT, PDD_SCHED_PERSISTENT_GRAPH = 0, 1, 2
 
-EXPORTED = ["pdd_mc_interface", "pdd_wos_interface", "pdd_branching_eval", "pdd_mc_adjoint", "pdd_mc_value_jacobian",
+EXPORTED = ["pdd_mc_interface", "pdd_wos_interface", "pdd_branching_eval", "pdd_branching_bvp", "pdd_mc_adjoint",
+            "pdd_mc_value_jacobian",
             "pdd_param_count", "pdd_query_warnings", "pdd_release_workspace", "pdd_status_string", "pdd_last_error",
             "pdd_version"]
 
@@ -46,6 +47,11 @@ class pdd_branching_problem(C.Structure):
                 ("psi", pdd_fun)]
 
 
+class pdd_branching_boundary(C.Structure):
+    _fields_ = [("domain", pdd_domain), ("g", pdd_fun), ("g_sup", C.c_double), ("dt", C.c_double),
+                ("n_times", C.c_int32), ("pad", C.c_int32), ("times", C.POINTER(C.c_double))]
+
+
 class pdd_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("rng_layout", C.c_int32), ("max_steps", C.c_int64),
                 ("dump_phi", C.c_void_p), ("dump_steps", C.c_void_p), ("schedule", C.c_int32),
@@ -72,6 +78,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.pdd_branching_eval.argtypes = [C.POINTER(pdd_branching_problem), C.c_void_p, C.c_int64, C.c_int64, C.c_uint64,
                                      C.POINTER(pdd_options), C.c_void_p, C.c_void_p]
     L.pdd_branching_eval.restype = C.c_int
+    L.pdd_branching_bvp.argtypes = [C.POINTER(pdd_branching_problem), C.POINTER(pdd_branching_boundary), C.c_void_p,
+                                    C.c_int64, C.c_int64, C.c_uint64, C.POINTER(pdd_options), C.c_void_p,
+                                    C.c_void_p]
+    L.pdd_branching_bvp.restype = C.c_int
     L.pdd_mc_adjoint.argtypes = [C.POINTER(pdd_linear_problem), C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                  C.c_double, C.c_uint64, C.POINTER(pdd_options), C.c_void_p,
                                  C.POINTER(pdd_fun_grad), C.c_void_p, C.c_void_p]

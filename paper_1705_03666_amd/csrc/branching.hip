@@ -292,6 +292,390 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Branching with a Dirichlet boundary, several output times (eq. 3.2,
+// Algorithm 3.1).  One tree per lane, depth first as above; a particle now
+// moves by exact Brownian increments over sub-steps that end at
+// min(s + dt, its death time, the last output time, the next output time),
+// and is tested against the boundary after each sub-step except the one that
+// ends at its death (the children are tested at their birth instead; a test
+// there would anticipate the death time).  A particle found outside is
+// projected and stopped: every output time t_i >= s picks up g(P X, t_i - s).
+// A particle inside at an output time t_k multiplies factor k by psi(X); a
+// branching at time s multiplies every factor with t_i > s by alpha_I / q_I.
+// The per-tree factors are FP64 products; per-lane FP64 Welford triples per
+// output time are merged across the wavefront at the end of a work item.
+// The statistics' step count is the number of particle sub-steps.
+//
+// Gaussians: number n DIM + c of a particle (sub-step n, coordinate c) is
+// slot (n DIM + c) mod m of Philox block j = (n DIM + c) / m (m normals per
+// block), counter (label_lo, 5 << 28 | attempt << 24 | label_hi16 << 8 |
+// j >> 8, tree, point | (j & 255) << 24).
+template <typename R>
+struct BvScalars;
+template <>
+struct BvScalars<float> {
+  __device__ static float dt(const BranchBoundary& B) { return B.dtf; }
+  __device__ static float t(const BranchBoundary& B, int i) { return B.timesf[i]; }
+};
+template <>
+struct BvScalars<double> {
+  __device__ static double dt(const BranchBoundary& B) { return B.dt; }
+  __device__ static double t(const BranchBoundary& B, int i) { return B.times[i]; }
+};
+
+template <typename R>
+__device__ __forceinline__ Dom<R> bvp_dom(const BranchBoundary& B);
+template <>
+__device__ __forceinline__ Dom<float> bvp_dom<float>(const BranchBoundary& B) {
+  Dom<float> D;
+  D.kind = B.dom_kind;
+  for (int k = 0; k < 3; ++k) { D.lo[k] = B.lof[k]; D.hi[k] = B.hif[k]; D.ctr[k] = B.ctrf[k]; }
+  D.rad = B.radf;
+  D.rad2 = B.rad2f;
+  return D;
+}
+template <>
+__device__ __forceinline__ Dom<double> bvp_dom<double>(const BranchBoundary& B) {
+  Dom<double> D;
+  D.kind = B.dom_kind;
+  for (int k = 0; k < 3; ++k) { D.lo[k] = B.lo[k]; D.hi[k] = B.hi[k]; D.ctr[k] = B.ctr[k]; }
+  D.rad = B.rad;
+  D.rad2 = B.rad2;
+  return D;
+}
+
+// g at (boundary point xp, time argument ts)
+template <typename R, int DIM>
+__device__ __forceinline__ R bvp_g(const BranchParams& P, const BranchBoundary& B, const R* xp, R ts) {
+  R xs[DIM + 1];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) xs[k] = xp[k];
+  xs[DIM] = ts;
+  R v = (R)0;
+  if (B.g.n_terms > 0) v = terms_sum<R, DIM + 1>(P.fac, P.cd, P.cf, B.g, xs);
+  if (B.g.poly_deg >= 0) v += poly_nested<R, DIM>(P.cd, P.cf, B.g.poly_deg, B.g.poly_off, xp);
+  return v;
+}
+
+template <typename R, int DIM, int LAYOUT>
+__global__ void __launch_bounds__(kBlock)
+k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __restrict__ items, int n_items,
+             uint32_t* __restrict__ qhead, ItemStat* __restrict__ istat, double* __restrict__ dump_val,
+             int64_t* __restrict__ dump_segs, int64_t trees, StackEntry<R>* __restrict__ spill,
+             int64_t spill_entries) {
+  using NZr = Normals<R, LAYOUT>;
+  constexpr int kPer = NZr::kPerBlock;
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int wid = (int)(threadIdx.x / kWave);
+  const int64_t glane = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t nlanes = (int64_t)gridDim.x * kBlock;
+  constexpr int kLdsDepth = lds_depth<R>();
+  __shared__ StackEntry<R> lds[kBlock / kWave][kLdsDepth][kWave];
+
+  const uint32_t k0 = P.key0, k1 = P.key1;
+  const R sigma = BrScalars<R>::sigma(P);
+  const R dt = BvScalars<R>::dt(BB);
+  const int nt = BB.n_times;
+  const R tend = BvScalars<R>::t(BB, nt - 1);
+  const bool bounded = BB.dom_kind != DOM_FREE;
+  const Dom<R> D = bvp_dom<R>(BB);
+  const uint64_t B = (uint64_t)P.label_base;
+
+  for (;;) {
+    const uint32_t it_idx = pop_item(qhead);
+    if (it_idx >= (uint32_t)n_items) break;
+    const WorkItem it = items[it_idx];
+    const int point = it.node;
+    const uint32_t pend = it.p0 + it.count;
+    R x0[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) x0[k] = (R)P.points[(size_t)point * DIM + k];
+    // output times at 0 take psi at the start point when it is inside
+    const bool x0_in = !bounded || inside<R, DIM>(D, x0);
+    const double psi0 = x0_in ? (double)psi_value<R, DIM>(P, x0) : 1.0;
+
+    uint32_t tree = it.p0 + (uint32_t)lane;
+    bool active = tree < pend;
+    uint32_t cursor = it.p0 + (it.count < (uint32_t)kWave ? it.count : (uint32_t)kWave);
+
+    // particle state
+    uint64_t label = 1;
+    R X[DIM];
+    R s = (R)0, sdeath = (R)0, utype = (R)0;
+    uint32_t gidx = 0;
+    int kout = 0, zblk = -1;
+    R zc[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) zc[q] = (R)0;
+    bool fresh = true;
+    // tree state
+    double Pt[kMaxTimes];
+    int segs = 0, sp = 0, attempt = 0;
+    auto start_tree = [&]() {
+      label = 1;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) X[k] = x0[k];
+      s = (R)0;
+      fresh = true;
+      segs = 0;
+      sp = 0;
+#pragma unroll
+      for (int i = 0; i < kMaxTimes; ++i) Pt[i] = (i < nt && !(BvScalars<R>::t(BB, i) > (R)0)) ? psi0 : 1.0;
+    };
+    start_tree();
+
+    double wn = 0.0;
+    double wmean[kMaxTimes], wm2[kMaxTimes];
+#pragma unroll
+    for (int i = 0; i < kMaxTimes; ++i) { wmean[i] = 0.0; wm2[i] = 0.0; }
+    int64_t lsub = 0, lcens = 0, lredraw = 0;
+
+    while (__any(active)) {
+      bool done = false, censored = false;
+      if (active) {
+        bool fail = false, pop = false, stop = false;
+        if (fresh) {
+          ++segs;
+          if (segs > P.max_segments) {
+            fail = true;
+          } else if (bounded && !inside<R, DIM>(D, X)) {
+            stop = true;   // born outside: stopped at its birth time
+          } else {
+            R ulife;
+            br_uniforms<R, LAYOUT>(label, attempt, tree, (uint32_t)point, k0, k1, ulife, utype);
+            sdeath = s + BrScalars<R>::lifetime(P, ulife);
+            kout = 0;
+#pragma unroll
+            for (int i = 0; i < kMaxTimes; ++i)
+              if (i < nt && !(BvScalars<R>::t(BB, i) > s)) kout = i + 1;
+            gidx = 0;
+            zblk = -1;
+            fresh = false;
+          }
+        } else {
+          // one sub-step
+          const R send = sdeath < tend ? sdeath : tend;
+          R sn = s + dt;
+          if (send < sn) sn = send;
+          R tk = tend;
+#pragma unroll
+          for (int i = 0; i < kMaxTimes; ++i)
+            if (i == kout) tk = BvScalars<R>::t(BB, i);
+          if (kout < nt && tk < sn) sn = tk;
+          R z[DIM];
+#pragma unroll
+          for (int c = 0; c < DIM; ++c) {
+            const uint32_t g = gidx++;
+            const int j = (int)(g / (uint32_t)kPer);
+            if (j != zblk) {
+              const uint32_t c0 = (uint32_t)label;
+              const uint32_t c1 = (5u << 28) | ((uint32_t)attempt << 24) |
+                                  ((uint32_t)((label >> 32) & 0xFFFFu) << 8) | (((uint32_t)j >> 8) & 0xFFu);
+              const uint32_t c3 = ((uint32_t)point & 0xFFFFFFu) | (((uint32_t)j & 0xFFu) << 24);
+              NZr::gen(c0, c1, tree, c3, k0, k1, zc);
+              zblk = j;
+            }
+            const int slot = (int)(g % (uint32_t)kPer);
+            R v = zc[0];
+#pragma unroll
+            for (int q = 1; q < kPer; ++q) v = slot == q ? zc[q] : v;
+            z[c] = v;
+          }
+          const R sd = sigma * fsqrt(sn - s);
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) X[k] = X[k] + sd * z[k];
+          s = sn;
+          ++lsub;
+          const bool dies = s == sdeath && sdeath < tend;
+          if (!dies && bounded && !inside<R, DIM>(D, X)) {
+            stop = true;
+          } else {
+            if (kout < nt && s == tk) {
+              const double pv = (double)psi_value<R, DIM>(P, X);
+#pragma unroll
+              for (int i = 0; i < kMaxTimes; ++i)
+                if (i == kout) Pt[i] *= pv;
+              ++kout;
+            }
+            if (!(s < send)) {
+              if (dies) {
+                // offspring count: smallest I with u < q_0 + ... + q_I (among q_I > 0)
+                int I = 0, last = 0;
+                bool found = false;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                  if (P.q[k] > 0.0) {
+                    last = k;
+                    const bool hit = sizeof(R) == 4 ? ((float)utype < P.qcumf[k]) : ((double)utype < P.qcum[k]);
+                    if (!found && hit) { I = k; found = true; }
+                  }
+                }
+                if (!found) I = last;
+                double ratio = P.ratio[0];
+#pragma unroll
+                for (int k = 1; k < 5; ++k) if (I == k) ratio = P.ratio[k];
+#pragma unroll
+                for (int i = 0; i < kMaxTimes; ++i)
+                  if (i < nt && BvScalars<R>::t(BB, i) > sdeath) Pt[i] *= ratio;
+                if (I == 0) {
+                  pop = true;
+                } else {
+                  const uint64_t first = B * label;
+                  if (label >= (1ull << 47) || first + (uint64_t)(I - 1) >= (1ull << 48) ||
+                      sp + I - 1 > spill_entries + kLdsDepth) {
+                    fail = true;
+                  } else {
+                    for (int i = I - 1; i >= 1; --i) {
+                      StackEntry<R> e;
+                      const uint64_t cl = first + (uint64_t)i;
+                      e.lo = (uint32_t)cl;
+                      e.hi = (uint32_t)(cl >> 32);
+#pragma unroll
+                      for (int k = 0; k < 3; ++k) e.x[k] = k < DIM ? X[k] : (R)0;
+                      e.t = sdeath;
+                      if (sp < kLdsDepth) lds[wid][sp][lane] = e;
+                      else spill[(int64_t)(sp - kLdsDepth) * nlanes + glane] = e;
+                      ++sp;
+                    }
+                    label = first;
+                    s = sdeath;
+                    fresh = true;
+                  }
+                }
+              } else {
+                pop = true;   // reached the last output time
+              }
+            }
+          }
+        }
+        if (stop) {
+          // projected onto the boundary and stopped at time s
+          R xp[3];
+          project<R, DIM>(D, X, xp);
+#pragma unroll
+          for (int i = 0; i < kMaxTimes; ++i) {
+            const R ti = BvScalars<R>::t(BB, i);
+            if (i < nt && ti >= s) Pt[i] *= (double)bvp_g<R, DIM>(P, BB, xp, ti - s);
+          }
+          pop = true;
+        }
+        if (!fail && pop) {
+          if (sp == 0) {
+            done = true;
+          } else {
+            --sp;
+            const StackEntry<R> e = sp < kLdsDepth ? lds[wid][sp][lane]
+                                                   : spill[(int64_t)(sp - kLdsDepth) * nlanes + glane];
+            label = (uint64_t)e.lo | ((uint64_t)e.hi << 32);
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) X[k] = e.x[k];
+            s = e.t;
+            fresh = true;
+          }
+        }
+        if (fail) {
+          ++lredraw;
+          ++attempt;
+          if (attempt >= 16) {
+            done = true;
+            censored = true;
+            ++lcens;
+          } else {
+            start_tree();
+          }
+        }
+        if (done) {
+          if (censored) {
+#pragma unroll
+            for (int i = 0; i < kMaxTimes; ++i) Pt[i] = 0.0;
+          }
+          wn += 1.0;
+#pragma unroll
+          for (int i = 0; i < kMaxTimes; ++i) {
+            if (i < nt) {
+              const double d1 = Pt[i] - wmean[i];
+              wmean[i] += d1 / wn;
+              wm2[i] += d1 * (Pt[i] - wmean[i]);
+            }
+          }
+          if (dump_val != nullptr) {
+            const int64_t o = ((int64_t)point * trees + (int64_t)tree) * nt;
+#pragma unroll
+            for (int i = 0; i < kMaxTimes; ++i)
+              if (i < nt) dump_val[o + i] = Pt[i];
+            if (dump_segs != nullptr) dump_segs[(int64_t)point * trees + (int64_t)tree] = segs;
+          }
+        }
+      }
+      // refill
+      const uint64_t dmask = ballot(done);
+      if (dmask != 0) {
+        const uint32_t ntr = cursor + (uint32_t)lane_rank(dmask);
+        cursor += (uint32_t)__popcll(dmask);
+        if (done) {
+          if (ntr < pend) {
+            tree = ntr;
+            attempt = 0;
+            start_tree();
+          } else {
+            active = false;
+          }
+        }
+      }
+    }
+
+    lsub = wave_sum(lsub);
+    lcens = wave_sum(lcens);
+    lredraw = wave_sum(lredraw);
+#pragma unroll
+    for (int i = 0; i < kMaxTimes; ++i) {
+      if (i < nt) {
+        double n = wn, m = wmean[i], q = wm2[i];
+        wave_welford(n, m, q);
+        if (lane == 0) {
+          ItemStat st;
+          st.mean = m;
+          st.m2 = q;
+          st.n = (int64_t)n;
+          st.steps = lsub;
+          st.censored = lcens;
+          st.redrawn = i == 0 ? lredraw : 0;
+          istat[(int64_t)i * n_items + it.slot] = st;
+        }
+      }
+    }
+  }
+}
+
+template <typename R, int LAYOUT>
+static hipError_t launch_branch_bvp_t(const BranchBvpLaunch& L, hipStream_t st) {
+  switch (L.P->dim) {
+    case 1:
+      hipLaunchKernelGGL((k_branch_bvp<R, 1, LAYOUT>), dim3(L.grid), dim3(kBlock), 0, st, *L.P, *L.B, L.items,
+                         L.n_items, L.qhead, L.istat, L.dump_val, L.dump_segs, L.trees, (StackEntry<R>*)L.stack,
+                         L.stack_entries);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_branch_bvp<R, 2, LAYOUT>), dim3(L.grid), dim3(kBlock), 0, st, *L.P, *L.B, L.items,
+                         L.n_items, L.qhead, L.istat, L.dump_val, L.dump_segs, L.trees, (StackEntry<R>*)L.stack,
+                         L.stack_entries);
+      break;
+    default:
+      hipLaunchKernelGGL((k_branch_bvp<R, 3, LAYOUT>), dim3(L.grid), dim3(kBlock), 0, st, *L.P, *L.B, L.items,
+                         L.n_items, L.qhead, L.istat, L.dump_val, L.dump_segs, L.trees, (StackEntry<R>*)L.stack,
+                         L.stack_entries);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_branch_bvp(const BranchBvpLaunch& L, hipStream_t st) {
+  if (L.fp32) return launch_branch_bvp_t<float, RNG_QUAD24>(L, st);
+  if (L.layout == RNG_QUAD24) return launch_branch_bvp_t<double, RNG_QUAD24>(L, st);
+  return launch_branch_bvp_t<double, RNG_PAIR52>(L, st);
+}
+
 template <typename R, int LAYOUT>
 static hipError_t launch_branch_t(const BranchLaunch& L, hipStream_t st) {
   switch (L.P->dim) {

@@ -220,7 +220,11 @@ struct Plan {
 
   LinearParams lp{};
   BranchParams bp{};
+  BranchBoundary bb{};
   bool branch = false;
+  bool bvp = false;          // branching with a boundary: istat is [n_times][n_items]
+  int n_times = 1;
+  BranchBvpLaunch bvl{};
   bool plain = false;
   bool adjoint = false;
   WalkLaunch wl{};
@@ -265,7 +269,15 @@ struct Plan {
       if (!adjoint) return launch_finalize_nodes(d_istat, d_first, n_nodes, out, ctr, st);
     } else {
       if ((e = launch_fill_u32(d_qhead, 1, 0u, st)) != hipSuccess) return e;
-      if (branch) {
+      if (bvp) {
+        if ((e = launch_branch_bvp(bvl, st)) != hipSuccess) return e;
+        for (int k = 0; k < n_times; ++k)
+          if ((e = launch_finalize_nodes(d_istat + (size_t)k * n_items, d_first, n_nodes,
+                                         (pdd_node_stat*)out + (size_t)k * n_nodes, k == 0 ? ctr : nullptr,
+                                         st)) != hipSuccess)
+            return e;
+        return hipSuccess;
+      } else if (branch) {
         if ((e = launch_branch(bl, st)) != hipSuccess) return e;
       } else {
         if ((e = launch_walk(wl, st)) != hipSuccess) return e;
@@ -900,11 +912,8 @@ bool admissible(const pdd_branching_problem& B, std::string* why) {
   return false;
 }
 
-pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, int64_t n_points, int64_t trees,
-                         uint64_t seed, const pdd_options* op, pdd_node_stat* out, hipStream_t st) {
-  if (Bp == nullptr || op == nullptr) return fail(PDD_ERR_INVALID_ARG, "problem or options is NULL");
-  const pdd_branching_problem& B = *Bp;
-  const pdd_options& o = *op;
+// Branching problem checks shared by pdd_branching_eval and pdd_branching_bvp.
+pdd_status check_branching(const pdd_branching_problem& B, const pdd_options& o, int64_t trees, int64_t n_points) {
   if (B.dim < 1 || B.dim > 3) return fail(PDD_ERR_INVALID_ARG, "dim must be 1..3");
   if (!(B.sigma >= 0.0) || !std::isfinite(B.sigma)) return fail(PDD_ERR_INVALID_ARG, "sigma must be >= 0");
   if (!(B.beta > 0.0) || !std::isfinite(B.beta)) return fail(PDD_ERR_INVALID_ARG, "beta must be positive");
@@ -925,24 +934,10 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   if (o.precision == PDD_FP32_STEP && o.rng_layout != PDD_RNG_QUAD24)
     return fail(PDD_ERR_INVALID_ARG, "FP32 positions require the QUAD24 layout");
   if (o.dump_steps && !o.dump_phi) return fail(PDD_ERR_INVALID_ARG, "dump_steps needs dump_phi");
-  pdd_status s;
-  if ((s = check_fun(B.psi, B.dim, "psi", kMaxTerms, kMaxPolyG)) != PDD_OK) return s;
-  std::string why;
-  if (!admissible(B, &why)) return fail(PDD_ERR_NOT_ADMISSIBLE, why);
-  if (n_points > 0) {
-    if ((s = check_device_ptr(points, "points_dev")) != PDD_OK) return s;
-    if ((s = check_device_ptr(out, "out_dev")) != PDD_OK) return s;
-  }
-  if (n_points == 0) return PDD_OK;
-  const bool fp32 = o.precision == PDD_FP32_STEP;
+  return check_fun(B.psi, B.dim, "psi", kMaxTerms, kMaxPolyG);
+}
 
-  std::unique_ptr<Plan> plan(new Plan());
-  Plan& pl = *plan;
-  pl.branch = true;
-  PDD_HIP(hipGetDevice(&pl.device));
-  if ((s = counters(&pl.ctr)) != PDD_OK) return s;
-  Tables T;
-  BranchParams& bp = pl.bp;
+void fill_branch_params(const pdd_branching_problem& B, uint64_t seed, Tables& T, BranchParams& bp) {
   bp.dim = B.dim;
   bp.max_segments = B.max_segments;
   int L = 0;
@@ -968,7 +963,32 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   bp.key1 = (uint32_t)(seed >> 32);
   bp.psi = T.add(B.psi, B.dim, 0, true);
   bp.n_fac = (int)T.fac.size();
+}
 
+pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, int64_t n_points, int64_t trees,
+                         uint64_t seed, const pdd_options* op, pdd_node_stat* out, hipStream_t st) {
+  if (Bp == nullptr || op == nullptr) return fail(PDD_ERR_INVALID_ARG, "problem or options is NULL");
+  const pdd_branching_problem& B = *Bp;
+  const pdd_options& o = *op;
+  pdd_status s;
+  if ((s = check_branching(B, o, trees, n_points)) != PDD_OK) return s;
+  std::string why;
+  if (!admissible(B, &why)) return fail(PDD_ERR_NOT_ADMISSIBLE, why);
+  if (n_points > 0) {
+    if ((s = check_device_ptr(points, "points_dev")) != PDD_OK) return s;
+    if ((s = check_device_ptr(out, "out_dev")) != PDD_OK) return s;
+  }
+  if (n_points == 0) return PDD_OK;
+  const bool fp32 = o.precision == PDD_FP32_STEP;
+
+  std::unique_ptr<Plan> plan(new Plan());
+  Plan& pl = *plan;
+  pl.branch = true;
+  PDD_HIP(hipGetDevice(&pl.device));
+  if ((s = counters(&pl.ctr)) != PDD_OK) return s;
+  Tables T;
+  BranchParams& bp = pl.bp;
+  fill_branch_params(B, seed, T, bp);
   const Tuning tune = choose_branch_tuning(B.dim, fp32, o, device_cus());
   Items items = make_items(n_points, nullptr, trees, tune.chunk_paths, {});
   const int n_items = (int)items.q.size();
@@ -1036,6 +1056,154 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   return PDD_OK;
 }
 
+pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branching_boundary* Dp, const double* points,
+                             int64_t n_points, int64_t trees, uint64_t seed, const pdd_options* op, pdd_node_stat* out,
+                             hipStream_t st) {
+  if (Bp == nullptr || Dp == nullptr || op == nullptr)
+    return fail(PDD_ERR_INVALID_ARG, "problem, boundary or options is NULL");
+  const pdd_branching_problem& B = *Bp;
+  const pdd_branching_boundary& Bd = *Dp;
+  const pdd_options& o = *op;
+  pdd_status s;
+  if ((s = check_branching(B, o, trees, n_points)) != PDD_OK) return s;
+  const pdd_domain& D = Bd.domain;
+  if (D.kind != PDD_DOM_BOX && D.kind != PDD_DOM_BALL && D.kind != PDD_DOM_FREE)
+    return fail(PDD_ERR_INVALID_ARG, "unknown domain kind");
+  if (D.kind != PDD_DOM_FREE) {
+    if (D.dim != B.dim) return fail(PDD_ERR_INVALID_ARG, "boundary domain dim differs from the problem's");
+    if (D.kind == PDD_DOM_BOX)
+      for (int k = 0; k < D.dim; ++k)
+        if (!(D.lo[k] < D.hi[k]) || !std::isfinite(D.lo[k]) || !std::isfinite(D.hi[k]))
+          return fail(PDD_ERR_INVALID_ARG, "box needs finite lo < hi");
+    if (D.kind == PDD_DOM_BALL && !(D.radius > 0.0 && std::isfinite(D.radius)))
+      return fail(PDD_ERR_INVALID_ARG, "ball radius must be positive");
+  }
+  // g reads coordinates 0..dim-1 and the time argument as coordinate dim
+  if ((s = check_fun(Bd.g, B.dim + 1, "g", kMaxTerms, kMaxPolyG)) != PDD_OK) return s;
+  if (!(Bd.g_sup >= 0.0) || !std::isfinite(Bd.g_sup)) return fail(PDD_ERR_INVALID_ARG, "g_sup must be >= 0");
+  if (!(Bd.dt > 0.0) || !std::isfinite(Bd.dt)) return fail(PDD_ERR_INVALID_ARG, "dt must be positive");
+  if (Bd.n_times < 1 || Bd.n_times > kMaxTimes)
+    return fail(PDD_ERR_UNSUPPORTED, "n_times must be 1.." + std::to_string(kMaxTimes));
+  if (Bd.times == nullptr) return fail(PDD_ERR_INVALID_ARG, "times_host is NULL");
+  for (int i = 0; i < Bd.n_times; ++i)
+    if (!(Bd.times[i] >= 0.0) || !std::isfinite(Bd.times[i]) || (i > 0 && !(Bd.times[i] > Bd.times[i - 1])))
+      return fail(PDD_ERR_INVALID_ARG, "times must be finite, >= 0 and increasing");
+  const double tlast = Bd.times[Bd.n_times - 1];
+  const double per = o.precision == PDD_FP32_STEP || o.rng_layout == PDD_RNG_QUAD24 ? 4.0 : 2.0;
+  if ((std::ceil(tlast / Bd.dt) + Bd.n_times + 2.0) * B.dim / per >= 65536.0)
+    return fail(PDD_ERR_UNSUPPORTED, "more than 2^16 Gaussian blocks per particle: raise dt");
+  if (n_points >= ((int64_t)1 << 24)) return fail(PDD_ERR_UNSUPPORTED, "n_points must be below 2^24");
+  pdd_branching_problem Ba = B;   // admissibility over [0, t_last] with sup |psi| and sup |g|
+  Ba.T = tlast;
+  Ba.psi_sup = std::max(B.psi_sup, Bd.g_sup);
+  std::string why;
+  if (!admissible(Ba, &why)) return fail(PDD_ERR_NOT_ADMISSIBLE, why);
+  if (n_points > 0) {
+    if ((s = check_device_ptr(points, "points_dev")) != PDD_OK) return s;
+    if ((s = check_device_ptr(out, "out_dev")) != PDD_OK) return s;
+  }
+  if (n_points == 0) return PDD_OK;
+  const bool fp32 = o.precision == PDD_FP32_STEP;
+
+  std::unique_ptr<Plan> plan(new Plan());
+  Plan& pl = *plan;
+  pl.branch = true;
+  pl.bvp = true;
+  pl.n_times = Bd.n_times;
+  PDD_HIP(hipGetDevice(&pl.device));
+  if ((s = counters(&pl.ctr)) != PDD_OK) return s;
+  Tables T;
+  BranchParams& bp = pl.bp;
+  fill_branch_params(Ba, seed, T, bp);
+  BranchBoundary& bb = pl.bb;
+  bb.dom_kind = D.kind;
+  bb.n_times = Bd.n_times;
+  for (int k = 0; k < 3; ++k) {
+    bb.lo[k] = D.lo[k]; bb.hi[k] = D.hi[k]; bb.ctr[k] = D.center[k];
+    bb.lof[k] = (float)D.lo[k]; bb.hif[k] = (float)D.hi[k]; bb.ctrf[k] = (float)D.center[k];
+  }
+  bb.rad = D.radius;
+  bb.rad2 = D.radius * D.radius;
+  bb.radf = (float)bb.rad;
+  bb.rad2f = (float)bb.rad2;
+  bb.dt = Bd.dt;
+  bb.dtf = (float)Bd.dt;
+  for (int i = 0; i < kMaxTimes; ++i) {
+    bb.times[i] = i < Bd.n_times ? Bd.times[i] : tlast;
+    bb.timesf[i] = (float)bb.times[i];
+  }
+  bb.g = T.add(Bd.g, B.dim, 0, true);
+  bp.n_fac = (int)T.fac.size();
+
+  const Tuning tune = choose_branch_tuning(B.dim, fp32, o, device_cus());
+  Items items = make_items(n_points, nullptr, trees, tune.chunk_paths, {});
+  const int n_items = (int)items.q.size();
+  const int max_blocks = tune.blocks_per_cu * device_cus();
+  const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
+  const int grid = std::max(1, std::min(max_blocks, need));
+  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32));
+
+  Arena A;
+  const size_t o_jobs = A.add(sizeof(StageJob) * std::max<size_t>(1, T.jobs.size()));
+  const size_t o_perm = A.add(sizeof(int32_t) * std::max<size_t>(1, T.perm.size()));
+  const size_t o_fac = A.add(sizeof(DevFactor) * std::max<size_t>(1, T.fac.size()));
+  const size_t o_cd = A.add(sizeof(double) * std::max(1, T.ncoef));
+  const size_t o_cf = A.add(sizeof(float) * std::max(1, T.ncoef));
+  const size_t o_q = A.add(sizeof(uint32_t) * 4);
+  const size_t o_items = A.add(sizeof(WorkItem) * std::max(1, n_items));
+  const size_t o_istat = A.add(sizeof(ItemStat) * (size_t)std::max(1, n_items) * (size_t)Bd.n_times);
+  const size_t o_first = A.add(sizeof(int64_t) * ((size_t)n_points + 1));
+  const size_t o_spill =
+      A.add(branch_stack_entry_bytes(fp32) * (size_t)std::max<int64_t>(1, spill_entries) * (size_t)grid * kBlock);
+  PDD_HIP(hipMallocAsync(&pl.arena, A.total, st));
+  char* base = (char*)pl.arena;
+  pl.d_jobs = (StageJob*)(base + o_jobs);
+  pl.n_jobs = (int)T.jobs.size();
+  pl.d_perm = (int32_t*)(base + o_perm);
+  pl.d_cd = (double*)(base + o_cd);
+  pl.d_cf = (float*)(base + o_cf);
+  pl.d_qhead = (uint32_t*)(base + o_q);
+  pl.d_istat = (ItemStat*)(base + o_istat);
+  pl.d_first = (int64_t*)(base + o_first);
+  pl.n_nodes = n_points;
+  pl.n_items = n_items;
+  pl.out = out;
+  bp.fac = (const DevFactor*)(base + o_fac);
+  bp.cd = pl.d_cd;
+  bp.cf = pl.d_cf;
+  bp.points = points;
+  std::vector<Upload> ups;
+  put(ups, o_jobs, T.jobs);
+  put(ups, o_perm, T.perm);
+  put(ups, o_fac, T.fac);
+  put(ups, o_first, items.first);
+  put(ups, o_items, items.q);
+  for (const auto& u : ups)
+    if (!u.bytes.empty()) PDD_HIP(hipMemcpyAsync(base + u.off, u.bytes.data(), u.bytes.size(), hipMemcpyHostToDevice, st));
+  BranchBvpLaunch& L = pl.bvl;
+  L.P = &pl.bp;
+  L.B = &pl.bb;
+  L.fp32 = fp32;
+  L.layout = o.rng_layout;
+  L.grid = grid;
+  L.items = (const WorkItem*)(base + o_items);
+  L.n_items = n_items;
+  L.qhead = pl.d_qhead;
+  L.istat = pl.d_istat;
+  L.dump_val = o.dump_phi;
+  L.dump_segs = o.dump_steps;
+  L.trees = trees;
+  L.stack = base + o_spill;
+  L.stack_entries = spill_entries;
+  hipError_t e = pl.enqueue(st);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(pl.arena, st);
+    return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+  PDD_HIP(hipFreeAsync(pl.arena, st));
+  return PDD_OK;
+}
+
 }  // namespace
 
 // ============================================================================= C ABI
@@ -1065,6 +1233,19 @@ pdd_status pdd_wos_interface(const pdd_linear_problem* problem, const double* no
                      nullptr, 0};
     a.wos = true;
     return run_linear(a, (hipStream_t)hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_branching_bvp(const pdd_branching_problem* problem, const pdd_branching_boundary* boundary,
+                             const double* points_dev, int64_t n_points, int64_t trees_per_point, uint64_t seed,
+                             const pdd_options* options, pdd_node_stat* out_dev, void* hip_stream) {
+  try {
+    return run_branching_bvp(problem, boundary, points_dev, n_points, trees_per_point, seed, options, out_dev,
+                             (hipStream_t)hip_stream);
   } catch (const std::bad_alloc&) {
     return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
   } catch (...) {

@@ -164,11 +164,14 @@ __device__ __forceinline__ double coef_at<double>(const double* __restrict__ cd,
   return cd[i];
 }
 
+// Coordinate d of x (DIM coordinates; DIM = 4 when a time argument follows
+// three space coordinates).
 template <typename R, int DIM>
 __device__ __forceinline__ R pick(const R* x, int d) {
   if (DIM == 1) return x[0];
   if (DIM == 2) return d == 0 ? x[0] : x[1];
-  return d == 0 ? x[0] : (d == 1 ? x[1] : x[2]);
+  if (DIM == 3) return d == 0 ? x[0] : (d == 1 ? x[1] : x[2]);
+  return d == 0 ? x[0] : (d == 1 ? x[1] : (d == 2 ? x[2] : x[3]));
 }
 
 // One factor.  The factor record is wave-uniform (scalar loads), so the switch

@@ -74,6 +74,21 @@ struct BranchParams {
   const double* points;
 };
 
+// Dirichlet boundary and output times of the branching estimator with a
+// boundary (eq. 3.2, Algorithm 3.1).  g is evaluated at (x, s): a factor
+// whose coordinate index equals dim reads the time argument s.
+constexpr int kMaxTimes = 12;
+struct BranchBoundary {
+  int32_t dom_kind, n_times;
+  double lo[3], hi[3], ctr[3], rad, rad2;
+  float lof[3], hif[3], ctrf[3], radf, rad2f;
+  double dt;
+  float dtf, pad0;
+  double times[kMaxTimes];
+  float timesf[kMaxTimes];
+  DevFun g;
+};
+
 // One unit of work for a wavefront: `count` consecutive paths (trees) of one
 // node starting at path index p0.  `slot` is the item's position in
 // node-major order, where its partial result is written.

@@ -68,10 +68,30 @@ struct BranchLaunch {
   int64_t stack_entries;     // entries per lane
 };
 
+// Branching with a Dirichlet boundary and output times; istat is
+// [n_times][n_items].
+struct BranchBvpLaunch {
+  const BranchParams* P;
+  const BranchBoundary* B;
+  bool fp32;
+  int layout;
+  int grid;
+  const WorkItem* items;
+  int n_items;
+  uint32_t* qhead;
+  ItemStat* istat;
+  double* dump_val;          // [points][trees][n_times]
+  int64_t* dump_segs;        // [points][trees]
+  int64_t trees;
+  void* stack;
+  int64_t stack_entries;
+};
+
 hipError_t launch_walk(const WalkLaunch& L, hipStream_t st);
 hipError_t launch_plain(const PlainLaunch& L, hipStream_t st);
 hipError_t launch_plain_adj(const PlainLaunch& L, hipStream_t st);
 hipError_t launch_branch(const BranchLaunch& L, hipStream_t st);
+hipError_t launch_branch_bvp(const BranchBvpLaunch& L, hipStream_t st);
 size_t branch_stack_entry_bytes(bool fp32);
 int branch_lds_depth(bool fp32);
 hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, int64_t n_nodes, void* out,

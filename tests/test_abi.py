@@ -43,6 +43,7 @@ def test_struct_sizes_match_header_layout(abi):
     assert C.sizeof(abi.pdd_fun) == 40
     assert C.sizeof(abi.pdd_domain) == 8 + 10 * 8
     assert C.sizeof(abi.pdd_options) == 56
+    assert C.sizeof(abi.pdd_branching_boundary) == 88 + 40 + 8 + 8 + 8 + 8
 
 
 def _problem(abi, **kw):
@@ -149,6 +150,63 @@ def test_branching_admissibility_is_checked_on_the_host(abi):
     b.alpha[0] = 0.1
     st = lib.pdd_branching_eval(C.byref(b), None, 1, 10, 0, C.byref(o), None, None)
     assert st == abi.PDD_ERR_INVALID_ARG
+
+
+def test_branching_bvp_arguments_are_checked_on_the_host(abi):
+    """pdd_branching_bvp: output times, dt, the per-particle Gaussian-block
+    limit, the domain, the time coordinate of g and admissibility over
+    [0, last time] with max(psi_sup, g_sup) are checked before any GPU work."""
+    lib = abi.load()
+    b = abi.pdd_branching_problem()
+    b.dim, b.max_segments = 1, 127
+    b.sigma, b.beta, b.T = 1.0, 1.0, 1.0
+    b.alpha[2] = 1.0
+    b.q[2] = 1.0
+    b.psi_sup = 0.5
+    b.psi.poly_degree = -1
+    coef = (C.c_double * 1)(1.0)
+    fac = (abi.pdd_factor * 1)()
+    fac[0].fn, fac[0].dim, fac[0].power, fac[0].a = 4, 1, 1, 1.0    # tanh of the time argument
+    bd = abi.pdd_branching_boundary()
+    bd.domain.kind, bd.domain.dim = abi.PDD_DOM_BOX, 1
+    bd.domain.lo[0], bd.domain.hi[0] = -1.0, 1.0
+    bd.g.n_terms, bd.g.n_factors = 1, 1
+    bd.g.factors = C.cast(fac, C.POINTER(abi.pdd_factor))
+    bd.g.coef = C.cast(coef, C.c_void_p).value
+    bd.g.poly_degree = -1
+    bd.g_sup = 0.5
+    bd.dt = 1e-2
+    times = (C.c_double * 3)(0.0, 0.5, 1.0)
+    bd.n_times = 3
+    bd.times = C.cast(times, C.POINTER(C.c_double))
+    o = _opts(abi)
+
+    def call():
+        return lib.pdd_branching_bvp(C.byref(b), C.byref(bd), None, 1, 10, 0, C.byref(o), None, None)
+
+    assert call() == abi.PDD_ERR_INVALID_ARG          # valid problem; the NULL points pointer is what fails
+    assert "points_dev" in lib.pdd_last_error().decode()
+    times[1] = 1.5
+    assert call() == abi.PDD_ERR_INVALID_ARG          # not increasing
+    times[1] = 0.5
+    bd.n_times = 13
+    assert call() == abi.PDD_ERR_UNSUPPORTED          # more than 12 output times
+    bd.n_times = 3
+    bd.dt = 1e-6
+    assert call() == abi.PDD_ERR_UNSUPPORTED          # 1e6 sub-steps: above 2^16 Gaussian blocks
+    bd.dt = 0.0
+    assert call() == abi.PDD_ERR_INVALID_ARG
+    bd.dt = 1e-2
+    fac[0].dim = 2                                      # coordinate beyond (x, s)
+    assert call() == abi.PDD_ERR_INVALID_ARG
+    fac[0].dim = 1
+    bd.domain.dim = 2
+    assert call() == abi.PDD_ERR_INVALID_ARG          # domain dim differs from the problem's
+    bd.domain.dim = 1
+    bd.g_sup = 2.0                                      # |g| up to 2 blows up before t = 1
+    assert call() == abi.PDD_ERR_NOT_ADMISSIBLE
+    bd.g_sup = 0.5
+    assert lib.pdd_branching_bvp(None, C.byref(bd), None, 1, 10, 0, C.byref(o), None, None) == abi.PDD_ERR_INVALID_ARG
 
 
 def test_status_strings(abi):

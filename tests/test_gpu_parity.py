@@ -365,6 +365,78 @@ def test_branching_fp64_matches_oracle_per_tree(pdd, orc, case, layout):
     stats_close(g, o)
 
 
+# ----------------------------------------------------------------------------- branching with a boundary
+def _bvp_marked_box3():
+    from workloads.problem import BranchingBoundary
+    B = BranchingProblem(3, 1.0, 1.3, 1.0, (0.1, 0.0, 0.9, 0.0, 0.0), (0.2, 0.0, 0.8, 0.0, 0.0),
+                         make_fun([(0.3, []), (0.1, [factor("cos", 0)])]), 0.4, max_segments=200)
+    g = make_fun([(0.5, []), (-0.5, [factor("tanh", 3, a=0.5, b=-0.2)]), (0.2, [factor("sin", 2, a=1.3)])])
+    Bd = BranchingBoundary(box((-0.5, -0.5, -0.5), (0.5, 0.5, 0.5)), g, 1.0, 0.05, (0.0, 0.25, 0.5, 1.0))
+    return B, Bd, np.array([[-0.3, 0.1, 0.05], [0.0, -0.2, 0.3], [0.35, 0.0, -0.1], [0.7, 0.0, 0.0]])
+
+
+BVP_CASES = {
+    "tw_interval": lambda: (*CF.kpp_bvp_travelling_wave(-1.0, 1.5, 0.01, (0.0, 0.25, 0.5, 1.0)),
+                            np.array([[-0.6], [0.0], [0.8], [1.3], [2.0]])),
+    "logistic_disk": lambda: (*CF.kpp_bvp_logistic(ball(2, 0.6), 0.3, 1.0, 0.05, (0.25, 0.5, 1.0)),
+                              np.array([[0.0, 0.0], [0.3, 0.1], [0.5, -0.2]])),
+    "marked_box3": _bvp_marked_box3,
+}
+
+
+@pytest.mark.parametrize("case", sorted(BVP_CASES))
+@pytest.mark.parametrize("layout", ["pair52", "quad24"])
+def test_branching_bvp_fp64_matches_oracle_per_tree(pdd, orc, case, layout):
+    """Per-tree values at every output time and segment counts equal the
+    oracle's on the same Philox streams (start point outside included)."""
+    B, Bd, pts = BVP_CASES[case]()
+    trees = 400
+    log(f"branching-with-boundary fp64 per-tree: case={case} layout={layout}")
+    o = orc.branching_bvp(B, Bd, pts, trees, 9, layout=orc.PAIR52 if layout == "pair52" else orc.QUAD24, dump=True)
+    g = pdd.branching_bvp(B, Bd, pts, trees, 9, precision="fp64", layout=layout, dump=True, chunk_paths=150)
+    torch.cuda.synchronize()
+    assert np.all(g["segments"].cpu().numpy() == o["segments"])
+    nbad, worst = per_path_close(g["value"].cpu().numpy().ravel(), o["value"].ravel())
+    assert nbad == 0, (nbad, worst)
+    for k in range(len(Bd.times)):
+        gm = g["mean"][k].cpu().numpy()
+        assert np.allclose(gm, o["mean"][k], rtol=1e-12, atol=1e-12)
+        assert np.allclose(g["m2"][k].cpu().numpy(), o["m2"][k], rtol=1e-9, atol=1e-12)
+        assert np.all(g["n"][k].cpu().numpy() == o["n"][k])
+        assert np.all(g["steps"][k].cpu().numpy() == o["steps"][k])
+
+
+def test_branching_bvp_fp32_statistical(pdd, orc):
+    """FP32 positions and times against the FP64 oracle (independent streams:
+    the FP32 time grid differs), and against the exact solutions."""
+    for name in ("tw_interval", "logistic_disk"):
+        B, Bd, pts = BVP_CASES[name]()
+        pts = pts[:3]
+        g = pdd.branching_bvp(B, Bd, pts, 40000, 21, precision="fp32")
+        o = orc.branching_bvp(B, Bd, pts, 40000, 22)
+        torch.cuda.synchronize()
+        gm, gs = g["mean"].cpu().numpy(), g["se"].cpu().numpy()
+        assert np.all(np.abs(gm - o["mean"]) <= 4.0 * np.sqrt(gs ** 2 + o["se"] ** 2) + 1e-5), name
+        if name == "logistic_disk":
+            exact = CF.logistic(0.3, 1.0, np.asarray(Bd.times))[:, None]
+            assert np.all(np.abs(gm - exact) <= 4.0 * gs + 1e-5)
+
+
+def test_branching_bvp_pruning_redraws_match_oracle(pdd, orc):
+    """A small segment cap redraws trees (attempt counter in the Philox word);
+    a point outside the domain is stopped at time 0."""
+    B, Bd = CF.kpp_bvp_logistic(box((-0.5,), (0.5,)), 0.3, 2.0, 0.05, (0.5, 1.0), max_segments=4)
+    pts = np.array([[0.0], [0.3], [0.9]])
+    o = orc.branching_bvp(B, Bd, pts, 600, 5, dump=True)
+    assert o["redrawn"] > 0
+    g = pdd.branching_bvp(B, Bd, pts, 600, 5, precision="fp64", dump=True)
+    torch.cuda.synchronize()
+    assert np.all(g["segments"].cpu().numpy() == o["segments"])
+    nbad, worst = per_path_close(g["value"].cpu().numpy().ravel(), o["value"].ravel())
+    assert nbad == 0, (nbad, worst)
+    assert np.all(g["censored"].cpu().numpy() == o["censored"])
+
+
 def test_branching_deep_trees_spill_and_redraw(pdd, orc):
     """Long horizon: stacks deeper than the LDS part spill to global memory and
     some trees hit the segment cap and are redrawn."""
