@@ -386,6 +386,21 @@ def other_workloads(pdd, dev):
     res["c4"] = {"points": len(c4.points), "trees_per_point": c4.trees, "segments": segs, "seconds": el4,
                  "trees_per_s": trees / el4, "segments_per_s": segs / el4}
     log(f"bench: C4: {trees:.3e} trees, {segs:.3e} segments in {el4 * 1e3:.1f} ms")
+    # C7: the CVA construction of Sec. 3.3 (signed quartic, marks q ~ |alpha|),
+    # 1024 points x 1e5 trees, compared with the method-of-lines solution of
+    # the same polynomial PDE
+    c7 = CF.c7()
+    p7 = torch.tensor(c7.points, device=dev)
+    r7, el7 = timed(lambda: pdd.branching_eval(c7.problem, p7, c7.trees, c7.seed, precision="fp32"))
+    segs7 = float(r7["steps"].sum().item())
+    ref7 = CF.c7_reference(c7.points[:, 0])
+    z7 = np.abs(c7.scale * r7["mean"].cpu().numpy() - ref7) / (c7.scale * r7["se"].cpu().numpy())
+    res["c7_cva_marked"] = {"points": len(c7.points), "trees_per_point": c7.trees, "segments": segs7,
+                            "seconds": el7, "trees_per_s": len(c7.points) * c7.trees / el7,
+                            "segments_per_s": segs7 / el7, "err_vs_pde_max_se": float(z7.max()),
+                            "err_vs_pde_rms_se": float(np.sqrt(np.mean(z7 ** 2)))}
+    log(f"bench: C7 (CVA, marked signed quartic): {len(c7.points) * c7.trees:.3e} trees, {segs7:.3e} segments in "
+        f"{el7 * 1e3:.1f} ms; error vs PDE solve max {z7.max():.1f} SE, rms {np.sqrt(np.mean(z7 ** 2)):.1f} SE")
     # C6: KPP with a Dirichlet boundary and 11 output times (eq. 3.2,
     # Algorithm 3.1); the travelling wave is the exact solution
     c6 = CF.c6()

@@ -347,7 +347,18 @@ BR_CASES = {
     "marked": lambda: (BranchingProblem(1, 1.0, 1.0, 0.5, (0.0586, 0.5, 0.8199, 0.0, -0.4095),
                                         (0.25, 0.25, 0.25, 0.0, 0.25), make_fun([(0.6, [factor("tanh", 0)])]), 0.6),
                        np.array([[0.5], [-0.5]])),
+    # the Sec. 3.3 construction: u_t = 0.5 Lap u + (max(u, 0) - u) in 2-D,
+    # psi = 2 tanh(x) cos(y), rescaled by psi_sup and fitted by a quartic,
+    # marks from variance_marks
+    "cva_rescaled": lambda: (_cva_rescaled(), np.array([[0.3, 0.0], [-0.8, 0.5], [1.2, -1.0]])),
 }
+
+
+def _cva_rescaled():
+    from paper_1705_03666_amd import nonlinear as NL
+    psi = make_fun([(2.0, [factor("tanh", 0), factor("cos", 1)])])
+    prob, _ = NL.rescaled_problem(2, 1.0, lambda u: np.maximum(u, 0.0) - u, psi, 2.0, 0.4, beta=1.0)
+    return prob
 
 
 @pytest.mark.parametrize("case", sorted(BR_CASES))

@@ -331,6 +331,60 @@ def c6(scale: float = 1.0, seed: int = 0, n_points: int = 1024, dt: float = 1e-3
     return BranchingBvpWorkload("C6 KPP with boundary, 11 times", B, Bd, pts, _budget(100_000, scale), seed)
 
 
+# --------------------------------------------------------------------------- C7
+@dataclass
+class CvaWorkload:
+    name: str
+    problem: BranchingProblem
+    scale: float
+    points: np.ndarray
+    trees: int
+    seed: int
+
+
+def c7_nonlinearity(u):
+    """The CVA-type nonlinearity of Sec. 3.3 with r_0 = -1, r_1 = 1:
+    f(u) = max(u, 0) - u (so the branching rate is 1)."""
+    return np.maximum(u, 0.0) - u
+
+
+def c7(scale: float = 1.0, seed: int = 0, n_points: int = 1024) -> CvaWorkload:
+    """The CVA construction of Sec. 3.3 in one dimension (the paper leaves the
+    operator, payoff and horizon open; chosen here): u_t = 0.5 u_xx + f(u),
+    f = max(u, 0) - u, payoff psi = 2 tanh(x) (bounded, signed), T = 0.5.
+    u / 2 is the rescaled unknown, its nonlinearity is fitted by a quartic on
+    [-1, 1] (Sec. 3.3's least-squares fit), marks q ~ |alpha|; 1024 points
+    evenly spaced in [-3, 3], 1e5 trees each."""
+    from paper_1705_03666_amd.nonlinear import rescaled_problem
+    psi = make_fun([(2.0, [factor("tanh", 0)])])
+    prob, s = rescaled_problem(1, 1.0, c7_nonlinearity, psi, 2.0, 0.5, beta=1.0)
+    pts = np.linspace(-3.0, 3.0, n_points).reshape(-1, 1)
+    return CvaWorkload("C7 CVA marked branching", prob, s, pts, _budget(100_000, scale), seed)
+
+
+def c7_reference(xq, L: float = 12.0, n: int = 2401) -> np.ndarray:
+    """Method-of-lines solution (second-order differences, stiff BDF) at T of
+    the PDE the C7 estimator represents: u_t = 0.5 u_xx + s P(u / s), P the
+    fitted quartic of the rescaled nonlinearity, s = 2, u(., 0) = 2 tanh x."""
+    from scipy import integrate
+    from scipy.sparse import diags
+    from paper_1705_03666_amd.nonlinear import fit_polynomial
+    s, T = 2.0, 0.5
+    a = fit_polynomial(lambda v: c7_nonlinearity(s * v) / s)
+    x = np.linspace(-L, L, n)
+    h = x[1] - x[0]
+
+    def rhs(t, u):
+        du = np.zeros_like(u)
+        v = u[1:-1] / s
+        du[1:-1] = 0.5 * (u[2:] - 2 * u[1:-1] + u[:-2]) / h ** 2 + s * sum(a[i] * v ** i for i in range(len(a)))
+        return du
+
+    sol = integrate.solve_ivp(rhs, (0, T), 2.0 * np.tanh(x), method="BDF", rtol=1e-10, atol=1e-12,
+                              jac_sparsity=diags([1, 1, 1], [-1, 0, 1], shape=(n, n)))
+    return np.interp(np.asarray(xq), x, sol.y[:, -1])
+
+
 # --------------------------------------------------------------------------- C5
 def real_solid_harmonics_poly(lmax: int = 7) -> np.ndarray:
     """Matrix (n_mono(3, lmax), (lmax+1)^2) whose column k holds the dense
