@@ -418,6 +418,13 @@ def other_workloads(pdd, dev):
     log(f"bench: C6: {tr6:.3e} trees x {len(c6.boundary.times)} times, {sub:.3e} particle sub-steps in "
         f"{el6 * 1e3:.1f} ms ({sub / el6:.3e}/s); error vs exact max {z6.max():.1f} SE, "
         f"rms {np.sqrt(np.mean(z6 ** 2)):.1f} SE")
+    r6c, el6c = timed(lambda: pdd.branching_bvp(c6.problem, c6.boundary, p6, c6.trees, c6.seed, precision="fp32",
+                                                boundary_correction=True))
+    z6c = (np.abs(r6c["mean"].cpu().numpy() - ex6) / np.maximum(r6c["se"].cpu().numpy(), 1e-300))[1:]
+    res["c6_branching_boundary"]["corrected"] = {"seconds": el6c, "err_vs_exact_max_se": float(z6c.max()),
+                                                 "err_vs_exact_rms_se": float(np.sqrt(np.mean(z6c ** 2)))}
+    log(f"bench: C6 with the per-sub-step boundary correction: {el6c * 1e3:.1f} ms; error vs exact max "
+        f"{z6c.max():.1f} SE, rms {np.sqrt(np.mean(z6c ** 2)):.1f} SE")
     return res
 
 

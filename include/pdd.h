@@ -185,7 +185,9 @@ typedef struct {
                                   their schemes): the path stops once X leaves D shrunk by
                                   c0 sigma sqrt(dt), c0 = -zeta(1/2)/sqrt(2 pi) ~ 0.5826, which removes
                                   the O(sqrt dt) overshoot bias; g is still taken at the projection of
-                                  X onto the boundary of D.  Ignored by pdd_branching_eval. */
+                                  X onto the boundary of D.  pdd_branching_bvp: the test after a
+                                  sub-step of length h uses the domain shrunk by c0 sigma sqrt(h).
+                                  Ignored by pdd_branching_eval. */
   int32_t specialize;     /* batched linear walks (PDD_FP64, PDD_FP32_STEP) whose b, c or f have generic
                              terms: 0 = auto: compile, at run time, a kernel with the problem's factor
                              structure (functions, coordinates, scales, shifts, powers) written in as

@@ -68,7 +68,7 @@ class OBranching(C.Structure):
 
 class OBranchBoundary(C.Structure):
     _fields_ = [("dom", ODomain), ("g", OFun), ("dt", C.c_double), ("n_times", C.c_int32), ("pad", C.c_int32),
-                ("times", C.POINTER(C.c_double))]
+                ("times", C.POINTER(C.c_double)), ("boundary_shift", C.c_double)]
 
 
 class OStat(C.Structure):
@@ -371,7 +371,7 @@ def branching_alg31(B: BranchingProblem, points, trees: int, seed: int, max_part
 
 
 def branching_bvp(B: BranchingProblem, Bd: BranchingBoundary, points, trees: int, seed: int, layout: int = PAIR52,
-                  n_threads: Optional[int] = None, dump: bool = False) -> dict:
+                  n_threads: Optional[int] = None, dump: bool = False, boundary_shift: float = 0.0) -> dict:
     """Branching estimator with particles stopped on a Dirichlet boundary
     (eq. 3.2), evaluated at every output time of one tree (Algorithm 3.1).
     Statistics have shape (n_times, n_points); dumps (n_points, trees,
@@ -385,6 +385,7 @@ def branching_bvp(B: BranchingProblem, Bd: BranchingBoundary, points, trees: int
     times = keep.arr(np.asarray(Bd.times, np.float64), np.float64)
     ob.n_times = len(times)
     ob.times = _ptr(times, C.c_double)
+    ob.boundary_shift = float(boundary_shift)
     pts = keep.arr(points, np.float64)
     n = len(pts)
     nt = len(times)

@@ -895,7 +895,10 @@ int orc_branching_alg31(const orc_branching* B, const double* points, int64_t n_
  * g(P X, t_i - s0)).  Testing at the death instead, before branching, would
  * look ahead to the death time and bias the estimator by O(dt) even for
  * spatially constant solutions.  The start point is tested the same way; an
- * output time t_i = 0 takes psi(x) when it is inside.
+ * output time t_i = 0 takes psi(x) when it is inside.  With boundary_shift =
+ * c0 > 0 the test after a sub-step of length h uses the domain shrunk by
+ * c0 sigma sqrt(h) (the walk's boundary correction, per sub-step); the test
+ * at birth uses the domain itself.
  *
  * Gaussians of a particle: number n d + k (sub-step n, coordinate k) comes
  * from Philox block j = (n d + k) / m, slot (n d + k) mod m (m = 4 for the
@@ -923,6 +926,15 @@ static double bvp_normal(const uint32_t key[2], int layout, uint64_t label, int 
     box_muller(u_pair52(w[0], w[1]), u_pair52(w[2], w[3]), &tmp[0], &tmp[1]);
   }
   return tmp[slot];
+}
+
+/* inside the domain shrunk by delta (box: every face moved in; ball: radius
+ * R - delta, at least 0) */
+static int inside_shrunk(const orc_domain* D, const double* x, double delta) {
+  orc_domain S = *D;
+  for (int k = 0; k < 3; ++k) { S.lo[k] += delta; S.hi[k] -= delta; }
+  S.radius = D->radius - delta > 0.0 ? D->radius - delta : 0.0;
+  return orc_inside(&S, x);
 }
 
 /* g at (boundary point, time argument): the time is coordinate index dim */
@@ -998,7 +1010,9 @@ static int bvp_tree_once(const orc_branching* B, const orc_branch_boundary* Bd, 
          branching, not by the boundary test: its children start there and
          are tested at their birth */
       const int dies = s == sdeath && sdeath < tend;
-      if (!dies && bounded && !orc_inside(&Bd->dom, sg.x)) {
+      const int out = bounded && (Bd->boundary_shift > 0.0 ? !inside_shrunk(&Bd->dom, sg.x, Bd->boundary_shift * sd)
+                                                            : !orc_inside(&Bd->dom, sg.x));
+      if (!dies && out) {
         double xp[3];
         orc_project(&Bd->dom, sg.x, xp);
         for (int i = 0; i < nt; ++i)

@@ -91,6 +91,9 @@ typedef struct {
   double dt;                   /* step of the boundary test */
   int32_t n_times, pad;
   const double* times;         /* [n_times], increasing, >= 0; the last is the horizon */
+  double boundary_shift;       /* 0: plain test; c0 > 0: after a sub-step of length h the
+                                  test uses the domain shrunk by c0 sigma sqrt(h) (Gobet and
+                                  Menozzi's correction, as for the walk) */
 } orc_branch_boundary;
 
 typedef struct {

@@ -392,7 +392,7 @@ def branching_eval(problem, points, trees: int, seed: int = 0, precision: str = 
 
 def branching_bvp(problem, boundary, points, trees: int, seed: int = 0, precision: str = "fp32",
                   layout: Optional[str] = None, dump: bool = False, chunk_paths: int = 0,
-                  blocks_per_cu: int = 0) -> Dict[str, torch.Tensor]:
+                  blocks_per_cu: int = 0, boundary_correction: bool = False) -> Dict[str, torch.Tensor]:
     """Branching estimator with particles stopped on a Dirichlet boundary,
     evaluated at every output time of one tree (pdd_branching_bvp).
     `boundary` is a workloads.problem.BranchingBoundary.  Statistics have
@@ -430,7 +430,7 @@ def branching_bvp(problem, boundary, points, trees: int, seed: int = 0, precisio
     if dump:
         dv = torch.empty(max(n * trees * nt, 1), dtype=torch.float64, device="cuda")
         ds = torch.empty(max(n * trees, 1), dtype=torch.int64, device="cuda")
-    o = _options(precision, layout, 0, "persistent", chunk_paths, blocks_per_cu, 0, dv, ds)
+    o = _options(precision, layout, 0, "persistent", chunk_paths, blocks_per_cu, 0, dv, ds, boundary_correction)
     st = library().pdd_branching_bvp(C.byref(b), C.byref(bd), pt.data_ptr() if n else None, n, int(trees),
                                      int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(), _stream_handle())
     _check(st, "pdd_branching_bvp")

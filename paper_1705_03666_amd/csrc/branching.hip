@@ -299,7 +299,8 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
 // min(s + dt, its death time, the last output time, the next output time),
 // and is tested against the boundary after each sub-step except the one that
 // ends at its death (the children are tested at their birth instead; a test
-// there would anticipate the death time).  A particle found outside is
+// there would anticipate the death time).  With the boundary correction the
+// test after a sub-step of length h uses D shrunk by c0 sigma sqrt(h).  A particle found outside is
 // projected and stopped: every output time t_i >= s picks up g(P X, t_i - s).
 // A particle inside at an output time t_k multiplies factor k by psi(X); a
 // branching at time s multiplies every factor with t_i > s by alpha_I / q_I.
@@ -317,12 +318,34 @@ template <>
 struct BvScalars<float> {
   __device__ static float dt(const BranchBoundary& B) { return B.dtf; }
   __device__ static float t(const BranchBoundary& B, int i) { return B.timesf[i]; }
+  __device__ static float shift(const BranchBoundary& B) { return B.shiftf; }
 };
 template <>
 struct BvScalars<double> {
   __device__ static double dt(const BranchBoundary& B) { return B.dt; }
   __device__ static double t(const BranchBoundary& B, int i) { return B.times[i]; }
+  __device__ static double shift(const BranchBoundary& B) { return B.shift; }
 };
+
+// inside D shrunk by delta >= 0 (box faces moved in; ball radius R - delta, at least 0)
+template <typename R, int DIM>
+__device__ __forceinline__ bool inside_shrunk(const Dom<R>& D, const R* x, R delta) {
+  if (D.kind == DOM_BOX) {
+    bool in = true;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) in = in && (x[k] > D.lo[k] + delta) && (x[k] < D.hi[k] - delta);
+    return in;
+  }
+  R r2 = (R)0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const R d = x[k] - D.ctr[k];
+    r2 += d * d;
+  }
+  R rs = D.rad - delta;
+  rs = rs > (R)0 ? rs : (R)0;
+  return r2 < rs * rs;
+}
 
 template <typename R>
 __device__ __forceinline__ Dom<R> bvp_dom(const BranchBoundary& B);
@@ -376,6 +399,7 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
   const uint32_t k0 = P.key0, k1 = P.key1;
   const R sigma = BrScalars<R>::sigma(P);
   const R dt = BvScalars<R>::dt(BB);
+  const R shift = BvScalars<R>::shift(BB);
   const int nt = BB.n_times;
   const R tend = BvScalars<R>::t(BB, nt - 1);
   const bool bounded = BB.dom_kind != DOM_FREE;
@@ -488,7 +512,8 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
           s = sn;
           ++lsub;
           const bool dies = s == sdeath && sdeath < tend;
-          if (!dies && bounded && !inside<R, DIM>(D, X)) {
+          const bool out = bounded && (shift > (R)0 ? !inside_shrunk<R, DIM>(D, X, shift * sd) : !inside<R, DIM>(D, X));
+          if (!dies && out) {
             stop = true;
           } else {
             if (kout < nt && s == tk) {

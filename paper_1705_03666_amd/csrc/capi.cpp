@@ -934,6 +934,8 @@ pdd_status check_branching(const pdd_branching_problem& B, const pdd_options& o,
   if (o.precision == PDD_FP32_STEP && o.rng_layout != PDD_RNG_QUAD24)
     return fail(PDD_ERR_INVALID_ARG, "FP32 positions require the QUAD24 layout");
   if (o.dump_steps && !o.dump_phi) return fail(PDD_ERR_INVALID_ARG, "dump_steps needs dump_phi");
+  if (o.boundary_correction < 0 || o.boundary_correction > 1)
+    return fail(PDD_ERR_INVALID_ARG, "boundary_correction must be 0 or 1");
   return check_fun(B.psi, B.dim, "psi", kMaxTerms, kMaxPolyG);
 }
 
@@ -1128,6 +1130,9 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   bb.rad2f = (float)bb.rad2;
   bb.dt = Bd.dt;
   bb.dtf = (float)Bd.dt;
+  // boundary correction per sub-step (c0 = -zeta(1/2)/sqrt(2 pi), as for the walk)
+  bb.shift = o.boundary_correction ? 1.4603545088095868 / std::sqrt(2.0 * M_PI) : 0.0;
+  bb.shiftf = (float)bb.shift;
   for (int i = 0; i < kMaxTimes; ++i) {
     bb.times[i] = i < Bd.n_times ? Bd.times[i] : tlast;
     bb.timesf[i] = (float)bb.times[i];

@@ -84,6 +84,8 @@ struct BranchBoundary {
   float lof[3], hif[3], ctrf[3], radf, rad2f;
   double dt;
   float dtf, pad0;
+  double shift;                  // 0, or c0 of the per-sub-step boundary correction
+  float shiftf, pad1;
   double times[kMaxTimes];
   float timesf[kMaxTimes];
   DevFun g;

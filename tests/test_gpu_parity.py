@@ -417,6 +417,18 @@ def test_branching_bvp_fp64_matches_oracle_per_tree(pdd, orc, case, layout):
         assert np.all(g["steps"][k].cpu().numpy() == o["steps"][k])
 
 
+@pytest.mark.parametrize("case", ["tw_interval", "marked_box3"])
+def test_branching_bvp_boundary_correction_matches_oracle_per_tree(pdd, orc, case):
+    B, Bd, pts = BVP_CASES[case]()
+    o = orc.branching_bvp(B, Bd, pts, 300, 19, dump=True, boundary_shift=orc.GOBET_MENOZZI_C0)
+    g = pdd.branching_bvp(B, Bd, pts, 300, 19, precision="fp64", layout="pair52", dump=True, chunk_paths=100,
+                          boundary_correction=True)
+    torch.cuda.synchronize()
+    assert np.all(g["segments"].cpu().numpy() == o["segments"])
+    nbad, worst = per_path_close(g["value"].cpu().numpy().ravel(), o["value"].ravel())
+    assert nbad == 0, (nbad, worst)
+
+
 def test_branching_bvp_fp32_statistical(pdd, orc):
     """FP32 positions and times against the FP64 oracle (independent streams:
     the FP32 time grid differs), and against the exact solutions."""

@@ -480,6 +480,26 @@ def test_branching_bvp_paper_travelling_wave_with_boundary(orc):
     assert np.max(np.abs(rx["mean"] - exact) - 4 * rx["se"] - bias) > 0.0
 
 
+def test_branching_bvp_boundary_correction_cuts_the_overshoot_bias(orc):
+    """The walk's boundary correction applied per sub-step (domain shrunk by
+    c0 sigma sqrt(h) after a sub-step of length h): on the travelling-wave
+    problem at dt = 1e-2 the largest error against the exact solution falls
+    to under half of the plain test's (0.0087 -> 0.0026 at 1e5 trees); on
+    spatially constant data (logistic) both stay exact."""
+    times = (0.25, 0.5, 1.0)
+    B, Bd = CF.kpp_bvp_travelling_wave(-1.0, 1.5, 1e-2, times)
+    pts = np.array([[-0.9], [-0.6], [0.0], [0.8], [1.3], [1.45]])
+    exact = np.array([CF.travelling_wave(pts[:, 0], t) for t in times])
+    err = {}
+    for name, sh in (("plain", 0.0), ("corrected", orc.GOBET_MENOZZI_C0)):
+        r = orc.branching_bvp(B, Bd, pts, 60000, 11, boundary_shift=sh)
+        err[name] = np.max(np.abs(r["mean"] - exact))
+    assert err["corrected"] < 0.5 * err["plain"], err
+    Bl, Bdl = CF.kpp_bvp_logistic(box((-0.5,), (0.5,)), 0.3, 1.0, 0.05, times)
+    rl = orc.branching_bvp(Bl, Bdl, np.array([[0.0], [0.3]]), 30000, 5, boundary_shift=orc.GOBET_MENOZZI_C0)
+    assert z_ok(rl["mean"], rl["se"], CF.logistic(0.3, 1.0, np.asarray(times))[:, None])
+
+
 def test_branching_bvp_free_space_times_match_single_time_estimator(orc):
     """Without a boundary the multi-time estimator at each output time t_i has
     the law of the free-space estimator run to T = t_i (Algorithm 3.1 reads one
