@@ -168,6 +168,13 @@ typedef enum {
   PDD_SCHED_PERSISTENT_GRAPH = 2  /* persistent kernel captured once into a hipGraph and replayed */
 } pdd_schedule;
 
+/* Partial statistics of one work item (48 bytes): the Welford triple of its
+ * paths, their total steps, censored paths and redrawn trees. */
+typedef struct {
+  double mean, m2;
+  int64_t n, steps, censored, redrawn;
+} pdd_item_stat;
+
 typedef struct {
   int32_t precision;      /* pdd_precision */
   int32_t rng_layout;     /* pdd_rng_layout; PDD_FP32_STEP requires QUAD24 */
@@ -197,6 +204,20 @@ typedef struct {
                              same operations in the same order.  Coefficients stay run-time data, so
                              one compiled kernel (cached in memory and in $PDD_JIT_CACHE, default
                              ~/.cache/pdd_jit) serves every coefficient value.  Ignored elsewhere. */
+  /* Failure / resume (pdd_mc_interface and pdd_wos_interface with PDD_FP64 or
+   * PDD_FP32_STEP; else PDD_ERR_UNSUPPORTED).  A call's paths are cut into
+   * pdd_item_count() work items whose partial statistics sit in fixed
+   * node-major slots and are merged in slot order, and every path is a pure
+   * function of (seed, node, path index); so an item lost to a fault can be
+   * recomputed alone and the merged result is bit-identical to a full run.
+   *  partials: device [n_items] or NULL.  When given, the call keeps the
+   *    per-item partials there: it writes the slot of every item it runs and
+   *    reads the slot of every item it skips.  It is the checkpoint.
+   *  skip_items: host [n_items] or NULL; nonzero = do not run this item in
+   *    this call (requires `partials`; its partial is taken from there).
+   * A call with either set is never captured into a cached graph. */
+  const uint8_t* skip_items;
+  pdd_item_stat* partials;
 } pdd_options;
 
 /* Per-node result: mean and sum of squared deviations (variance = m2/(n-1),
@@ -308,6 +329,12 @@ int64_t pdd_param_count(const pdd_linear_problem* problem);
  * redrawn-tree counters of the work enqueued since the last query:
  * PDD_WARN_CENSORED / PDD_WARN_REDRAWN if non-zero, else PDD_OK. */
 pdd_status pdd_query_warnings(void* hip_stream, int64_t* censored_out, int64_t* redrawn_out);
+
+/* Number of work items (partials slots) pdd_mc_interface / pdd_wos_interface
+ * cut these budgets into with these options on the current device (the item
+ * size depends on the schedule options, the precision, the total path count
+ * and the device's compute units).  Negative pdd_status on invalid input. */
+int64_t pdd_item_count(int64_t n_nodes, const int64_t* paths_host, const pdd_options* options);
 
 /* Frees cached launch plans and their device memory (synchronizes the device). */
 pdd_status pdd_release_workspace(void);

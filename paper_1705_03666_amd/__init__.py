@@ -26,7 +26,8 @@ import torch
 
 from . import _abi as A
 
-__all__ = ["mc_interface", "mc_adjoint", "mc_value_jacobian", "branching_eval", "PDDInterface", "PddError",
+__all__ = ["mc_interface", "mc_adjoint", "mc_value_jacobian", "branching_eval", "branching_bvp", "wos_interface",
+           "item_count", "PDDInterface", "PddError",
            "release_workspace", "query_warnings", "library", "version", "param_layout", "jacobian_blocks"]
 
 
@@ -186,11 +187,14 @@ def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str
                  layout: Optional[str] = None, max_steps: int = 0, dump: bool = False, schedule: str = "auto",
                  chunk_paths: int = 0, blocks_per_cu: int = 0, refill_groups: int = 0,
                  coefs: Optional[Dict[str, torch.Tensor]] = None,
-                 boundary_correction: bool = False, specialize: str = "auto") -> Dict[str, torch.Tensor]:
+                 boundary_correction: bool = False, specialize: str = "auto",
+                 partials: Optional[torch.Tensor] = None, skip_items=None) -> Dict[str, torch.Tensor]:
     """Monte Carlo value of the linear problem at every node (pdd_mc_interface).
     Returns device tensors mean, m2, n, steps, censored, var, se (and, with
     dump=True, the per-path values `phi` and step counts `path_steps`,
-    node-major)."""
+    node-major).  `partials` (float64 device tensor [item_count(...), 6], the
+    pdd_item_stat slots) and `skip_items` (bool array [item_count(...)])
+    checkpoint and resume a call item by item."""
     _need_gpu()
     keep = _Keep()
     p = _linear(problem, keep, coefs)
@@ -207,6 +211,15 @@ def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str
         dst = torch.empty(max(total, 1), dtype=torch.int64, device="cuda")
     o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups, dphi, dst,
                  boundary_correction, specialize)
+    if partials is not None:
+        if not (partials.is_cuda and partials.dtype == torch.float64 and partials.is_contiguous()
+                and partials.dim() == 2 and partials.shape[1] == 6):
+            raise ValueError("partials must be a contiguous float64 CUDA tensor of shape [n_items, 6]")
+        o.partials = partials.data_ptr()
+    if skip_items is not None:
+        sk = np.ascontiguousarray(np.asarray(skip_items, dtype=np.uint8).reshape(-1))
+        keep.append(sk)
+        o.skip_items = sk.ctypes.data
     st = library().pdd_mc_interface(C.byref(p), nt.data_ptr() if n else None, n,
                                     ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt), int(seed) & (2 ** 64 - 1),
                                     C.byref(o), raw.data_ptr(), _stream_handle())
@@ -440,6 +453,18 @@ def branching_bvp(problem, boundary, points, trees: int, seed: int = 0, precisio
         res["segments"] = ds[:n * trees].reshape(n, trees)
     res["_keep"] = keep
     return res
+
+
+def item_count(paths, precision: str = "fp32", layout: Optional[str] = None, schedule: str = "auto",
+               chunk_paths: int = 0, blocks_per_cu: int = 0, refill_groups: int = 0) -> int:
+    """Work items (partials slots) mc_interface cuts these budgets into with
+    these schedule options on the current device (pdd_item_count)."""
+    ph = np.ascontiguousarray(np.asarray(paths, dtype=np.int64).reshape(-1))
+    o = _options(precision, layout, 0, schedule, chunk_paths, blocks_per_cu, refill_groups)
+    n = int(library().pdd_item_count(ph.shape[0], ph.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(o)))
+    if n < 0:
+        _check(n, "pdd_item_count")
+    return n
 
 
 def query_warnings():

@@ -16,7 +16,7 @@ PDD_RNG_PAIR52, PDD_RNG_QUAD24 = 0, 1
 PDD_SCHED_AUTO, PDD_SCHED_PERSISTENT, PDD_SCHED_PERSISTENT_GRAPH = 0, 1, 2
 
 EXPORTED = ["pdd_mc_interface", "pdd_wos_interface", "pdd_branching_eval", "pdd_branching_bvp", "pdd_mc_adjoint",
-            "pdd_mc_value_jacobian",
+            "pdd_mc_value_jacobian", "pdd_item_count",
             "pdd_param_count", "pdd_query_warnings", "pdd_release_workspace", "pdd_status_string", "pdd_last_error",
             "pdd_version"]
 
@@ -56,7 +56,13 @@ class pdd_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("rng_layout", C.c_int32), ("max_steps", C.c_int64),
                 ("dump_phi", C.c_void_p), ("dump_steps", C.c_void_p), ("schedule", C.c_int32),
                 ("chunk_paths", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill_groups", C.c_int32),
-                ("boundary_correction", C.c_int32), ("specialize", C.c_int32)]
+                ("boundary_correction", C.c_int32), ("specialize", C.c_int32),
+                ("skip_items", C.c_void_p), ("partials", C.c_void_p)]
+
+
+class pdd_item_stat(C.Structure):
+    _fields_ = [("mean", C.c_double), ("m2", C.c_double), ("n", C.c_int64), ("steps", C.c_int64),
+                ("censored", C.c_int64), ("redrawn", C.c_int64)]
 
 
 class pdd_node_stat(C.Structure):
@@ -90,6 +96,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                         C.POINTER(C.c_int64), C.c_double, C.c_uint64, C.POINTER(pdd_options),
                                         C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
     L.pdd_mc_value_jacobian.restype = C.c_int
+    L.pdd_item_count.argtypes = [C.c_int64, C.POINTER(C.c_int64), C.POINTER(pdd_options)]
+    L.pdd_item_count.restype = C.c_int64
     L.pdd_param_count.argtypes = [C.POINTER(pdd_linear_problem)]
     L.pdd_param_count.restype = C.c_int64
     L.pdd_query_warnings.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]

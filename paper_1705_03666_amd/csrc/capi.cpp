@@ -476,6 +476,15 @@ pdd_status validate_linear(const LinearPlanArgs& a) {
   if (o.boundary_correction < 0 || o.boundary_correction > 1)
     return fail(PDD_ERR_INVALID_ARG, "boundary_correction must be 0 or 1");
   if (o.specialize < -1 || o.specialize > 1) return fail(PDD_ERR_INVALID_ARG, "specialize must be -1, 0 or 1");
+  if (o.skip_items || o.partials) {
+    if (a.adjoint || o.precision == PDD_FP64_PLAIN)
+      return fail(PDD_ERR_UNSUPPORTED, "skip_items / partials apply to the batched forward walk only");
+    if (o.skip_items && !o.partials) return fail(PDD_ERR_INVALID_ARG, "skip_items needs partials");
+    if (o.partials && a.n_nodes > 0) {
+      pdd_status s2 = check_device_ptr(o.partials, "options->partials");
+      if (s2 != PDD_OK) return s2;
+    }
+  }
   if (a.wos) {
     auto zero = [](const pdd_fun& F) { return F.n_terms == 0 && F.poly_degree < 0; };
     bool ok = zero(P.c) && zero(P.f);
@@ -510,7 +519,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   const bool plain = o.precision == PDD_FP64_PLAIN;
   const bool fp32 = o.precision == PDD_FP32_STEP;
   const bool graph = !plain && (o.schedule == PDD_SCHED_AUTO || o.schedule == PDD_SCHED_PERSISTENT_GRAPH) &&
-                     o.dump_phi == nullptr;
+                     o.dump_phi == nullptr && o.skip_items == nullptr && o.partials == nullptr;
 
   // ---- plan cache lookup
   std::string key;
@@ -620,8 +629,17 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   Items items;
   std::vector<int64_t> plain_first;
   std::vector<PlainLaunch> plain_launches;
+  int n_slots = 0;
   if (!plain) {
     items = make_items(a.n_nodes, a.paths, 0, tune.chunk_paths, cost);
+    n_slots = (int)items.q.size();
+    if (o.skip_items) {
+      // resume: queue only the items not skipped; all slots stay in place
+      std::vector<WorkItem> keep;
+      for (const WorkItem& w : items.q)
+        if (!o.skip_items[w.slot]) keep.push_back(w);
+      items.q.swap(keep);
+    }
   }
   int n_items = (int)items.q.size();
   pl.n_items = n_items;
@@ -658,7 +676,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
       pl.n_items = n_items;
     }
   } else {
-    n_stat = n_items;
+    n_stat = n_slots;
     o_items = A.add(sizeof(WorkItem) * std::max(1, n_items));
   }
   o_istat = A.add(sizeof(ItemStat) * std::max<int64_t>(1, n_stat));
@@ -733,7 +751,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   pl.d_cd = (double*)(base + o_cd);
   pl.d_cf = (float*)(base + o_cf);
   pl.d_qhead = (uint32_t*)(base + o_q);
-  pl.d_istat = (ItemStat*)(base + o_istat);
+  pl.d_istat = o.partials ? (ItemStat*)o.partials : (ItemStat*)(base + o_istat);
   pl.d_first = (int64_t*)(base + o_first);
   int64_t* d_doff = (int64_t*)(base + o_doff);
   pl.out = a.out;
@@ -1322,6 +1340,30 @@ pdd_status pdd_query_warnings(void* hip_stream, int64_t* censored_out, int64_t* 
   if (h[0] > 0) return PDD_WARN_CENSORED;
   if (h[1] > 0) return PDD_WARN_REDRAWN;
   return PDD_OK;
+}
+
+int64_t pdd_item_count(int64_t n_nodes, const int64_t* paths_host, const pdd_options* options) {
+  try {
+    if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
+    if (n_nodes < 0 || n_nodes > (int64_t)1 << 30) return fail(PDD_ERR_INVALID_ARG, "n_nodes out of range");
+    if (n_nodes > 0 && paths_host == nullptr) return fail(PDD_ERR_INVALID_ARG, "paths_host is NULL");
+    const pdd_options& o = *options;
+    if (o.chunk_paths < 0 || o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.refill_groups < 0 ||
+        o.refill_groups > 64)
+      return fail(PDD_ERR_INVALID_ARG, "schedule override out of range");
+    int64_t total = 0;
+    for (int64_t i = 0; i < n_nodes; ++i) {
+      if (paths_host[i] < 0 || paths_host[i] > (int64_t)0x7FFFFFFF)
+        return fail(PDD_ERR_INVALID_ARG, "paths per node must be in [0, 2^31)");
+      total += paths_host[i];
+    }
+    const Tuning tune = choose_tuning(0, o.precision == PDD_FP32_STEP, false, o, device_cus(), total);
+    return (int64_t)make_items(n_nodes, paths_host, 0, tune.chunk_paths, {}).q.size();
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
 }
 
 pdd_status pdd_release_workspace(void) {

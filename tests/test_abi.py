@@ -42,7 +42,8 @@ def test_struct_sizes_match_header_layout(abi):
     assert C.sizeof(abi.pdd_factor) == 32
     assert C.sizeof(abi.pdd_fun) == 40
     assert C.sizeof(abi.pdd_domain) == 8 + 10 * 8
-    assert C.sizeof(abi.pdd_options) == 56
+    assert C.sizeof(abi.pdd_options) == 72
+    assert C.sizeof(abi.pdd_item_stat) == 48
     assert C.sizeof(abi.pdd_branching_boundary) == 88 + 40 + 8 + 8 + 8 + 8
 
 
@@ -207,6 +208,49 @@ def test_branching_bvp_arguments_are_checked_on_the_host(abi):
     assert call() == abi.PDD_ERR_NOT_ADMISSIBLE
     bd.g_sup = 0.5
     assert lib.pdd_branching_bvp(None, C.byref(bd), None, 1, 10, 0, C.byref(o), None, None) == abi.PDD_ERR_INVALID_ARG
+
+
+def _items_expected(paths, fp32=True, cus=256):
+    """The library's default item decomposition, restated: item size 16384
+    halved (down to 1024) until the call has about four items per resident
+    wavefront; per node, items of that size, then about the last eighth in
+    items of size/8 (at least 256)."""
+    waves = (8 if fp32 else 4) * cus * 4
+    total = int(np.sum(paths))
+    chunk = 16384
+    while chunk > 1024 and total // chunk < 4 * waves:
+        chunk //= 2
+    small = max(min(256, chunk), chunk // 8)
+    n = 0
+    for N in paths:
+        nb = (N - N // 8) // chunk if N > chunk else 0
+        n += nb + -(-(N - nb * chunk) // small)
+    return n
+
+
+def test_item_count_and_resume_options_on_the_host(abi):
+    """pdd_item_count follows the documented decomposition (no GPU here, so the
+    library assumes 256 compute units); skip_items needs partials; the adjoint
+    and the plain baseline refuse them."""
+    lib = abi.load()
+    o = _opts(abi)
+    for paths in ([100000] * 10, [1000, 20000, 3, 0, 77777], [5000] * 3000):
+        ph = (C.c_int64 * len(paths))(*paths)
+        assert lib.pdd_item_count(len(paths), ph, C.byref(o)) == _items_expected(paths)
+    o64 = _opts(abi, precision=abi.PDD_FP64, layout=abi.PDD_RNG_PAIR52)
+    ph = (C.c_int64 * 3)(300000, 1, 40000)
+    assert lib.pdd_item_count(3, ph, C.byref(o64)) == _items_expected([300000, 1, 40000], fp32=False)
+    assert lib.pdd_item_count(1, None, C.byref(o)) == abi.PDD_ERR_INVALID_ARG
+    p = _problem(abi)
+    paths = (C.c_int64 * 1)(10)
+    skip = (C.c_uint8 * 4)(0, 1, 0, 0)
+    o.skip_items = C.cast(skip, C.c_void_p).value
+    assert lib.pdd_mc_interface(C.byref(p), None, 1, paths, 1e-3, 0, C.byref(o), None, None) == abi.PDD_ERR_INVALID_ARG
+    assert "partials" in lib.pdd_last_error().decode()
+    o.partials = 1
+    op = _opts(abi, precision=abi.PDD_FP64_PLAIN, layout=abi.PDD_RNG_PAIR52)
+    op.partials = 1
+    assert lib.pdd_mc_interface(C.byref(p), None, 1, paths, 1e-3, 0, C.byref(op), None, None) == abi.PDD_ERR_UNSUPPORTED
 
 
 def test_status_strings(abi):

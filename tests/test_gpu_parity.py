@@ -258,6 +258,35 @@ def test_schedule_independence_and_determinism(pdd):
     assert torch.equal(again["mean"], ref["mean"]) and torch.equal(again["m2"], ref["m2"])
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fault_and_resume_reproduce_the_full_run_bitwise(pdd, precision):
+    """Items lost to a fault (skipped) and recomputed alone in a second call
+    give the same per-item partials and node statistics, bit for bit, as one
+    uninterrupted run: paths are pure functions of their counters and the
+    partials are merged in fixed slot order."""
+    parts = CF.c3(scale=0.02)
+    p = parts[7]
+    nodes, paths = p.nodes[:40], p.paths[:40] * 3
+    kw = dict(precision=precision, schedule="persistent", chunk_paths=512)
+    n_items = pdd.item_count(paths, **kw)
+    assert n_items > 40
+    full_p = torch.zeros((n_items, 6), dtype=torch.float64, device="cuda")
+    full = pdd.mc_interface(p.problem, nodes, paths, p.dt, 4, partials=full_p, **kw)
+    lost = np.random.default_rng(0).random(n_items) < 0.3
+    part = torch.zeros_like(full_p)
+    hit = pdd.mc_interface(p.problem, nodes, paths, p.dt, 4, partials=part, skip_items=lost, **kw)
+    torch.cuda.synchronize()
+    assert not torch.equal(hit["n"], full["n"])              # the fault lost paths
+    res = pdd.mc_interface(p.problem, nodes, paths, p.dt, 4, partials=part, skip_items=~lost, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(part, full_p)
+    for k in ("mean", "m2", "n", "steps", "censored"):
+        assert torch.equal(res[k], full[k]), k
+    plain = pdd.mc_interface(p.problem, nodes, paths, p.dt, 4, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(plain["mean"], full["mean"])
+
+
 def test_graph_replay_reads_current_coefficients(pdd):
     P, nodes, dt = CASES["c5"]()
     paths = np.full(len(nodes), 500, np.int64)
