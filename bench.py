@@ -77,6 +77,61 @@ def traffic_bytes():
     return TRAFFIC_BYTES if h.hexdigest() == TRAFFIC_SHA256 else None
 
 
+class ClockSampler:
+    """Samples the GPU shader clock while the timed steps run, from the
+    amdgpu driver's sysfs table (the active DPM level is marked '*'), or once
+    from amd-smi when sysfs is not readable.  Reports MHz, or None."""
+
+    def __init__(self, period: float = 0.05):
+        import glob
+        import threading
+        self.files = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+        self.period = period
+        self.samples = []
+        self._stop = threading.Event()
+        self._t = threading.Thread(target=self._run, daemon=True)
+
+    def _read(self):
+        vals = []
+        for f in self.files:
+            try:
+                for line in open(f):
+                    if "*" in line:
+                        vals.append(float(line.split(":")[1].strip().lower().replace("*", "").replace("mhz", "")))
+            except (OSError, ValueError, IndexError):
+                pass
+        return max(vals) if vals else None
+
+    def _run(self):
+        while not self._stop.is_set():
+            v = self._read()
+            if v is not None:
+                self.samples.append(v)
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        if self.files:
+            self._t.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self.files:
+            self._t.join()
+
+    def result(self):
+        if self.samples:
+            return {"source": "sysfs pp_dpm_sclk", "median_mhz": float(np.median(self.samples)),
+                    "min_mhz": float(min(self.samples)), "samples": len(self.samples)}
+        import subprocess
+        try:
+            txt = subprocess.run(["amd-smi", "metric", "-g", "0", "--clock"], capture_output=True, text=True,
+                                 timeout=20).stdout
+            return {"source": "amd-smi metric --clock (after the steps)", "text": txt.strip()[:600]}
+        except (OSError, subprocess.SubprocessError):
+            return None
+
+
 def run(args):
     import torch
     import paper_1705_03666_amd as pdd
@@ -157,17 +212,19 @@ def run(args):
     step_ms, vj_ms = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for i in range(args.steps):
-        ev[0].record()
-        r, grad = step()
-        ev[2].record()
+    with ClockSampler() as clock:
+        for i in range(args.steps):
+            ev[0].record()
+            r, grad = step()
+            ev[2].record()
+            torch.cuda.synchronize()
+            step_ms.append(ev[0].elapsed_time(ev[2]))
+            vj_ms.append(ev_vj[0].elapsed_time(ev_vj[1]))
+            stats["fwd"] = r
+            log(f"bench: step {i + 1}/{args.steps}: value+jacobian+gradient {step_ms[-1]:.1f} ms")
         torch.cuda.synchronize()
-        step_ms.append(ev[0].elapsed_time(ev[2]))
-        vj_ms.append(ev_vj[0].elapsed_time(ev_vj[1]))
-        stats["fwd"] = r
-        log(f"bench: step {i + 1}/{args.steps}: value+jacobian+gradient {step_ms[-1]:.1f} ms")
-    torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    sclk = clock.result()
     ms_step = wall * 1e3 / args.steps
 
     if args.steps_only:
@@ -276,6 +333,7 @@ def run(args):
         "plain_sample_nodes": k_pl,
         "speedup_vs_plain_fp64_at_se_1e-3": nodes_per_s / plain_nodes_per_s,
         "mean_steps_per_path": float(mean_steps.mean().item()),
+        "gpu_clock_during_steps": sclk,
         "roofline": {"bound": "alu", "kernel": f"k_walk ({dominant}, FP32, DIM 3)", "achieved": achieved,
                      "peak": peak, "unit": "Top/s", "frac": achieved / peak, "traffic": traffic_bytes(),
                      "ops_per_path_step": OPS_PER_PS_ADJ if dominant == "adjoint" else OPS_PER_PS_FWD,
@@ -498,6 +556,8 @@ def main():
                     help="only run a device-to-device copy of 256 MiB (reference for the FETCH/WRITE counters)")
     ap.add_argument("--c2-only", action="store_true",
                     help="only run C2 at full size twice (the first call compiles its kernel; for profiler runs)")
+    ap.add_argument("--c6-only", action="store_true",
+                    help="only run C6 (branching with a boundary, 11 output times) twice (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
@@ -510,6 +570,22 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}), flush=True)
+        return
+    if args.c6_only:
+        import torch
+        import paper_1705_03666_amd as pdd
+        from workloads import configs as CF
+        c6 = CF.c6(scale=args.scale)
+        p6 = torch.tensor(c6.points, device="cuda")
+        for i in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = pdd.branching_bvp(c6.problem, c6.boundary, p6, c6.trees, c6.seed, precision="fp32")
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            sub = float(r["steps"][0].sum().item())
+            print(json.dumps({"workload": "C6", "call": i + 1, "trees": len(c6.points) * c6.trees,
+                              "particle_substeps": sub, "seconds": el, "substeps_per_s": sub / el}), flush=True)
         return
     if args.c2_only:
         import torch

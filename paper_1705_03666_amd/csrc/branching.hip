@@ -304,8 +304,11 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
 // projected and stopped: every output time t_i >= s picks up g(P X, t_i - s).
 // A particle inside at an output time t_k multiplies factor k by psi(X); a
 // branching at time s multiplies every factor with t_i > s by alpha_I / q_I.
-// The per-tree factors are FP64 products; per-lane FP64 Welford triples per
-// output time are merged across the wavefront at the end of a work item.
+// The per-tree factors are FP64 products; a finished tree enters the
+// wavefront's FP64 Welford triple of every output time (kept in LDS, lanes
+// in order).  Lanes run up to eight sub-steps per round and stop at their
+// first event (output time, stop, death, end), which is handled after the
+// round, so the rare event code is not interleaved with every sub-step.
 // The statistics' step count is the number of particle sub-steps.
 //
 // Gaussians: number n DIM + c of a particle (sub-step n, coordinate c) is
@@ -381,6 +384,9 @@ __device__ __forceinline__ R bvp_g(const BranchParams& P, const BranchBoundary& 
   return v;
 }
 
+// Events of a particle found at the end of a sub-step.
+enum : int { EV_OUT = 1, EV_STOP = 2, EV_DEATH = 4, EV_END = 8 };
+
 template <typename R, int DIM, int LAYOUT>
 __global__ void __launch_bounds__(kBlock)
 k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __restrict__ items, int n_items,
@@ -389,12 +395,15 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
              int64_t spill_entries) {
   using NZr = Normals<R, LAYOUT>;
   constexpr int kPer = NZr::kPerBlock;
+  constexpr int kSub = 8;          // sub-steps per round between event handling
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const int wid = (int)(threadIdx.x / kWave);
   const int64_t glane = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t nlanes = (int64_t)gridDim.x * kBlock;
   constexpr int kLdsDepth = lds_depth<R>();
   __shared__ StackEntry<R> lds[kBlock / kWave][kLdsDepth][kWave];
+  // per-wave Welford triples per output time, updated by lane 0 tree by tree
+  __shared__ double wst[kBlock / kWave][2 * kMaxTimes + 1];
 
   const uint32_t k0 = P.key0, k1 = P.key1;
   const R sigma = BrScalars<R>::sigma(P);
@@ -405,6 +414,7 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
   const bool bounded = BB.dom_kind != DOM_FREE;
   const Dom<R> D = bvp_dom<R>(BB);
   const uint64_t B = (uint64_t)P.label_base;
+  double* const W = &wst[wid][0];
 
   for (;;) {
     const uint32_t it_idx = pop_item(qhead);
@@ -418,15 +428,20 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
     // output times at 0 take psi at the start point when it is inside
     const bool x0_in = !bounded || inside<R, DIM>(D, x0);
     const double psi0 = x0_in ? (double)psi_value<R, DIM>(P, x0) : 1.0;
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0)
+      for (int i = 0; i < 2 * kMaxTimes + 1; ++i) W[i] = 0.0;
+    __builtin_amdgcn_wave_barrier();
 
     uint32_t tree = it.p0 + (uint32_t)lane;
     bool active = tree < pend;
     uint32_t cursor = it.p0 + (it.count < (uint32_t)kWave ? it.count : (uint32_t)kWave);
 
-    // particle state
+    // particle state: position, time, death time, end of its stepping
+    // (min(death, last output time)), next output index and time
     uint64_t label = 1;
     R X[DIM];
-    R s = (R)0, sdeath = (R)0, utype = (R)0;
+    R s = (R)0, sdeath = (R)0, send = (R)0, tk = (R)0, utype = (R)0;
     uint32_t gidx = 0;
     int kout = 0, zblk = -1;
     R zc[kPer];
@@ -448,44 +463,72 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
       for (int i = 0; i < kMaxTimes; ++i) Pt[i] = (i < nt && !(BvScalars<R>::t(BB, i) > (R)0)) ? psi0 : 1.0;
     };
     start_tree();
-
-    double wn = 0.0;
-    double wmean[kMaxTimes], wm2[kMaxTimes];
-#pragma unroll
-    for (int i = 0; i < kMaxTimes; ++i) { wmean[i] = 0.0; wm2[i] = 0.0; }
     int64_t lsub = 0, lcens = 0, lredraw = 0;
 
     while (__any(active)) {
-      bool done = false, censored = false;
-      if (active) {
-        bool fail = false, pop = false, stop = false;
-        if (fresh) {
+      bool done = false, censored = false, fail = false;
+      // ---- births: test at birth, lifetime and type (a lane whose particle
+      // is stopped at birth pops and may meet another birth: loop)
+      for (;;) {
+        const bool need = active && fresh && !done && !fail;
+        if (!__any(need)) break;
+        if (need) {
+          bool stop0 = false;
           ++segs;
           if (segs > P.max_segments) {
             fail = true;
           } else if (bounded && !inside<R, DIM>(D, X)) {
-            stop = true;   // born outside: stopped at its birth time
+            stop0 = true;   // born outside: stopped at its birth time
           } else {
             R ulife;
             br_uniforms<R, LAYOUT>(label, attempt, tree, (uint32_t)point, k0, k1, ulife, utype);
             sdeath = s + BrScalars<R>::lifetime(P, ulife);
+            send = sdeath < tend ? sdeath : tend;
             kout = 0;
+            tk = tend;
 #pragma unroll
-            for (int i = 0; i < kMaxTimes; ++i)
-              if (i < nt && !(BvScalars<R>::t(BB, i) > s)) kout = i + 1;
+            for (int i = kMaxTimes - 1; i >= 0; --i) {
+              const R ti = BvScalars<R>::t(BB, i);
+              if (i < nt && ti > s) { kout = i; tk = ti; }
+            }
+            if (!(tk > s)) kout = nt;   // no output time after s
             gidx = 0;
             zblk = -1;
             fresh = false;
           }
-        } else {
-          // one sub-step
-          const R send = sdeath < tend ? sdeath : tend;
+          if (stop0) {
+            R xp[3];
+            project<R, DIM>(D, X, xp);
+#pragma unroll
+            for (int i = 0; i < kMaxTimes; ++i) {
+              const R ti = BvScalars<R>::t(BB, i);
+              if (i < nt && ti >= s) Pt[i] *= (double)bvp_g<R, DIM>(P, BB, xp, ti - s);
+            }
+            if (sp == 0) {
+              done = true;
+            } else {
+              --sp;
+              const StackEntry<R> e = sp < kLdsDepth ? lds[wid][sp][lane]
+                                                     : spill[(int64_t)(sp - kLdsDepth) * nlanes + glane];
+              label = (uint64_t)e.lo | ((uint64_t)e.hi << 32);
+#pragma unroll
+              for (int k = 0; k < DIM; ++k) X[k] = e.x[k];
+              s = e.t;
+            }
+          }
+        }
+      }
+      // ---- up to kSub sub-steps per stepping lane; a lane stops at its first event
+      int ev = 0;
+      bool stepping = active && !fresh && !done && !fail;
+      for (int q = 0; q < kSub; ++q) {
+        if (stepping && !(s < send)) {   // nothing left to step (a last output time of 0)
+          ev = EV_END;
+          stepping = false;
+        }
+        if (stepping) {
           R sn = s + dt;
           if (send < sn) sn = send;
-          R tk = tend;
-#pragma unroll
-          for (int i = 0; i < kMaxTimes; ++i)
-            if (i == kout) tk = BvScalars<R>::t(BB, i);
           if (kout < nt && tk < sn) sn = tk;
           R z[DIM];
 #pragma unroll
@@ -503,7 +546,7 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
             const int slot = (int)(g % (uint32_t)kPer);
             R v = zc[0];
 #pragma unroll
-            for (int q = 1; q < kPer; ++q) v = slot == q ? zc[q] : v;
+            for (int m = 1; m < kPer; ++m) v = slot == m ? zc[m] : v;
             z[c] = v;
           }
           const R sd = sigma * fsqrt(sn - s);
@@ -512,69 +555,31 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
           s = sn;
           ++lsub;
           const bool dies = s == sdeath && sdeath < tend;
-          const bool out = bounded && (shift > (R)0 ? !inside_shrunk<R, DIM>(D, X, shift * sd) : !inside<R, DIM>(D, X));
+          const bool out =
+              bounded && (shift > (R)0 ? !inside_shrunk<R, DIM>(D, X, shift * sd) : !inside<R, DIM>(D, X));
           if (!dies && out) {
-            stop = true;
+            ev = EV_STOP;
           } else {
-            if (kout < nt && s == tk) {
-              const double pv = (double)psi_value<R, DIM>(P, X);
-#pragma unroll
-              for (int i = 0; i < kMaxTimes; ++i)
-                if (i == kout) Pt[i] *= pv;
-              ++kout;
-            }
-            if (!(s < send)) {
-              if (dies) {
-                // offspring count: smallest I with u < q_0 + ... + q_I (among q_I > 0)
-                int I = 0, last = 0;
-                bool found = false;
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                  if (P.q[k] > 0.0) {
-                    last = k;
-                    const bool hit = sizeof(R) == 4 ? ((float)utype < P.qcumf[k]) : ((double)utype < P.qcum[k]);
-                    if (!found && hit) { I = k; found = true; }
-                  }
-                }
-                if (!found) I = last;
-                double ratio = P.ratio[0];
-#pragma unroll
-                for (int k = 1; k < 5; ++k) if (I == k) ratio = P.ratio[k];
-#pragma unroll
-                for (int i = 0; i < kMaxTimes; ++i)
-                  if (i < nt && BvScalars<R>::t(BB, i) > sdeath) Pt[i] *= ratio;
-                if (I == 0) {
-                  pop = true;
-                } else {
-                  const uint64_t first = B * label;
-                  if (label >= (1ull << 47) || first + (uint64_t)(I - 1) >= (1ull << 48) ||
-                      sp + I - 1 > spill_entries + kLdsDepth) {
-                    fail = true;
-                  } else {
-                    for (int i = I - 1; i >= 1; --i) {
-                      StackEntry<R> e;
-                      const uint64_t cl = first + (uint64_t)i;
-                      e.lo = (uint32_t)cl;
-                      e.hi = (uint32_t)(cl >> 32);
-#pragma unroll
-                      for (int k = 0; k < 3; ++k) e.x[k] = k < DIM ? X[k] : (R)0;
-                      e.t = sdeath;
-                      if (sp < kLdsDepth) lds[wid][sp][lane] = e;
-                      else spill[(int64_t)(sp - kLdsDepth) * nlanes + glane] = e;
-                      ++sp;
-                    }
-                    label = first;
-                    s = sdeath;
-                    fresh = true;
-                  }
-                }
-              } else {
-                pop = true;   // reached the last output time
-              }
-            }
+            if (kout < nt && s == tk) ev |= EV_OUT;
+            if (!(s < send)) ev |= dies ? EV_DEATH : EV_END;
           }
+          stepping = ev == 0;
         }
-        if (stop) {
+      }
+      // ---- events
+      if (ev != 0) {
+        bool pop = false;
+        if (ev & EV_OUT) {
+          const double pv = (double)psi_value<R, DIM>(P, X);
+#pragma unroll
+          for (int i = 0; i < kMaxTimes; ++i)
+            if (i == kout) Pt[i] *= pv;
+          ++kout;
+#pragma unroll
+          for (int i = 0; i < kMaxTimes; ++i)
+            if (i == kout) tk = BvScalars<R>::t(BB, i);
+        }
+        if (ev & EV_STOP) {
           // projected onto the boundary and stopped at time s
           R xp[3];
           project<R, DIM>(D, X, xp);
@@ -584,8 +589,54 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
             if (i < nt && ti >= s) Pt[i] *= (double)bvp_g<R, DIM>(P, BB, xp, ti - s);
           }
           pop = true;
+        } else if (ev & EV_END) {
+          pop = true;   // reached the last output time
+        } else if (ev & EV_DEATH) {
+          // offspring count: smallest I with u < q_0 + ... + q_I (among q_I > 0)
+          int I = 0, last = 0;
+          bool found = false;
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            if (P.q[k] > 0.0) {
+              last = k;
+              const bool hit = sizeof(R) == 4 ? ((float)utype < P.qcumf[k]) : ((double)utype < P.qcum[k]);
+              if (!found && hit) { I = k; found = true; }
+            }
+          }
+          if (!found) I = last;
+          double ratio = P.ratio[0];
+#pragma unroll
+          for (int k = 1; k < 5; ++k) if (I == k) ratio = P.ratio[k];
+#pragma unroll
+          for (int i = 0; i < kMaxTimes; ++i)
+            if (i < nt && BvScalars<R>::t(BB, i) > sdeath) Pt[i] *= ratio;
+          if (I == 0) {
+            pop = true;
+          } else {
+            const uint64_t first = B * label;
+            if (label >= (1ull << 47) || first + (uint64_t)(I - 1) >= (1ull << 48) ||
+                sp + I - 1 > spill_entries + kLdsDepth) {
+              fail = true;
+            } else {
+              for (int i = I - 1; i >= 1; --i) {
+                StackEntry<R> e;
+                const uint64_t cl = first + (uint64_t)i;
+                e.lo = (uint32_t)cl;
+                e.hi = (uint32_t)(cl >> 32);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) e.x[k] = k < DIM ? X[k] : (R)0;
+                e.t = sdeath;
+                if (sp < kLdsDepth) lds[wid][sp][lane] = e;
+                else spill[(int64_t)(sp - kLdsDepth) * nlanes + glane] = e;
+                ++sp;
+              }
+              label = first;
+              s = sdeath;
+              fresh = true;
+            }
+          }
         }
-        if (!fail && pop) {
+        if (pop && !fail) {
           if (sp == 0) {
             done = true;
           } else {
@@ -599,45 +650,56 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
             fresh = true;
           }
         }
-        if (fail) {
-          ++lredraw;
-          ++attempt;
-          if (attempt >= 16) {
-            done = true;
-            censored = true;
-            ++lcens;
-          } else {
-            start_tree();
-          }
-        }
-        if (done) {
-          if (censored) {
-#pragma unroll
-            for (int i = 0; i < kMaxTimes; ++i) Pt[i] = 0.0;
-          }
-          wn += 1.0;
-#pragma unroll
-          for (int i = 0; i < kMaxTimes; ++i) {
-            if (i < nt) {
-              const double d1 = Pt[i] - wmean[i];
-              wmean[i] += d1 / wn;
-              wm2[i] += d1 * (Pt[i] - wmean[i]);
-            }
-          }
-          if (dump_val != nullptr) {
-            const int64_t o = ((int64_t)point * trees + (int64_t)tree) * nt;
-#pragma unroll
-            for (int i = 0; i < kMaxTimes; ++i)
-              if (i < nt) dump_val[o + i] = Pt[i];
-            if (dump_segs != nullptr) dump_segs[(int64_t)point * trees + (int64_t)tree] = segs;
-          }
+      }
+      if (fail) {
+        ++lredraw;
+        ++attempt;
+        if (attempt >= 16) {
+          done = true;
+          censored = true;
+          ++lcens;
+        } else {
+          start_tree();
         }
       }
+      if (done) {
+        if (censored) {
+#pragma unroll
+          for (int i = 0; i < kMaxTimes; ++i) Pt[i] = 0.0;
+        }
+        if (dump_val != nullptr) {
+          const int64_t o = ((int64_t)point * trees + (int64_t)tree) * nt;
+#pragma unroll
+          for (int i = 0; i < kMaxTimes; ++i)
+            if (i < nt) dump_val[o + i] = Pt[i];
+          if (dump_segs != nullptr) dump_segs[(int64_t)point * trees + (int64_t)tree] = segs;
+        }
+      }
+      // finished trees enter the wave's Welford triples in lane order
+      uint64_t dmask = ballot(done);
+      const uint64_t dmask0 = dmask;
+      while (dmask != 0) {
+        const int l = __builtin_ctzll(dmask);
+        dmask &= dmask - 1;
+        if (lane == 0) W[2 * kMaxTimes] += 1.0;
+        const double n = W[2 * kMaxTimes];
+#pragma unroll
+        for (int i = 0; i < kMaxTimes; ++i) {
+          if (i < nt) {
+            const double v = __shfl(Pt[i], l);
+            if (lane == 0) {
+              const double d1 = v - W[i];
+              W[i] += d1 / n;
+              W[kMaxTimes + i] += d1 * (v - W[i]);
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
       // refill
-      const uint64_t dmask = ballot(done);
-      if (dmask != 0) {
-        const uint32_t ntr = cursor + (uint32_t)lane_rank(dmask);
-        cursor += (uint32_t)__popcll(dmask);
+      if (dmask0 != 0) {
+        const uint32_t ntr = cursor + (uint32_t)lane_rank(dmask0);
+        cursor += (uint32_t)__popcll(dmask0);
         if (done) {
           if (ntr < pend) {
             tree = ntr;
@@ -653,21 +715,17 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
     lsub = wave_sum(lsub);
     lcens = wave_sum(lcens);
     lredraw = wave_sum(lredraw);
-#pragma unroll
-    for (int i = 0; i < kMaxTimes; ++i) {
-      if (i < nt) {
-        double n = wn, m = wmean[i], q = wm2[i];
-        wave_welford(n, m, q);
-        if (lane == 0) {
-          ItemStat st;
-          st.mean = m;
-          st.m2 = q;
-          st.n = (int64_t)n;
-          st.steps = lsub;
-          st.censored = lcens;
-          st.redrawn = i == 0 ? lredraw : 0;
-          istat[(int64_t)i * n_items + it.slot] = st;
-        }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      for (int i = 0; i < nt; ++i) {
+        ItemStat st;
+        st.mean = W[i];
+        st.m2 = W[kMaxTimes + i];
+        st.n = (int64_t)W[2 * kMaxTimes];
+        st.steps = lsub;
+        st.censored = lcens;
+        st.redrawn = i == 0 ? lredraw : 0;
+        istat[(int64_t)i * n_items + it.slot] = st;
       }
     }
   }
