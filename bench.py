@@ -64,8 +64,8 @@ OPS_PER_PS_ADJ = 182.0
 # calibration (x 2.000 / x 1.000).  Valid only for the kernel sources they
 # were counted on: any change to them makes the bench report null.
 TRAFFIC_SOURCES = ['paper_1705_03666_amd/csrc/walk_kernels.hpp', 'paper_1705_03666_amd/csrc/pdd_device.hpp', 'paper_1705_03666_amd/csrc/pdd_internal.hpp', 'paper_1705_03666_amd/csrc/walk_adj_f32.hip']
-TRAFFIC_SHA256 = "d4fad38258d8098589a2f8ba40a3ad1179b86856d2c64b1b60a23da6625e3289"
-TRAFFIC_BYTES = 37.06e6 + 95.38e6
+TRAFFIC_SHA256 = "180228a995beb3e9857b8c0a36fda1df6a39d2c4f1990b4dd789fa273b987614"
+TRAFFIC_BYTES = 36.88e6 + 95.35e6
 
 
 def traffic_bytes():
