@@ -395,7 +395,12 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
              int64_t spill_entries) {
   using NZr = Normals<R, LAYOUT>;
   constexpr int kPer = NZr::kPerBlock;
-  constexpr int kSub = 8;          // sub-steps per round between event handling
+  // sub-steps per round between event handling, and the Philox blocks a
+  // round may draw on: every stepping lane generates kNB blocks at the start
+  // of a round (all lanes together), starting with the block that holds its
+  // next Gaussian
+  constexpr int kSub = DIM == 1 ? 8 : (DIM == 2 ? 4 : 2);
+  constexpr int kNB = (kPer - 1 + kSub * DIM + kPer - 1) / kPer;
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const int wid = (int)(threadIdx.x / kWave);
   const int64_t glane = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -443,10 +448,7 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
     R X[DIM];
     R s = (R)0, sdeath = (R)0, send = (R)0, tk = (R)0, utype = (R)0;
     uint32_t gidx = 0;
-    int kout = 0, zblk = -1;
-    R zc[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) zc[q] = (R)0;
+    int kout = 0;
     bool fresh = true;
     // tree state
     double Pt[kMaxTimes];
@@ -493,7 +495,6 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
             }
             if (!(tk > s)) kout = nt;   // no output time after s
             gidx = 0;
-            zblk = -1;
             fresh = false;
           }
           if (stop0) {
@@ -521,6 +522,21 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
       // ---- up to kSub sub-steps per stepping lane; a lane stops at its first event
       int ev = 0;
       bool stepping = active && !fresh && !done && !fail;
+      R zb[kNB * kPer];
+      int o0 = 0;
+      if (stepping) {
+        const uint32_t j0 = gidx / (uint32_t)kPer;
+        o0 = (int)(gidx % (uint32_t)kPer);
+#pragma unroll
+        for (int b = 0; b < kNB; ++b) {
+          const uint32_t j = j0 + (uint32_t)b;
+          const uint32_t c0 = (uint32_t)label;
+          const uint32_t c1 = (5u << 28) | ((uint32_t)attempt << 24) | ((uint32_t)((label >> 32) & 0xFFFFu) << 8) |
+                              ((j >> 8) & 0xFFu);
+          const uint32_t c3 = ((uint32_t)point & 0xFFFFFFu) | ((j & 0xFFu) << 24);
+          NZr::gen(c0, c1, tree, c3, k0, k1, &zb[b * kPer]);
+        }
+      }
       for (int q = 0; q < kSub; ++q) {
         if (stepping && !(s < send)) {   // nothing left to step (a last output time of 0)
           ev = EV_END;
@@ -530,25 +546,17 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
           R sn = s + dt;
           if (send < sn) sn = send;
           if (kout < nt && tk < sn) sn = tk;
+          // Gaussians gidx .. gidx + DIM - 1 sit at o0 + q DIM + c of the round's blocks
           R z[DIM];
 #pragma unroll
           for (int c = 0; c < DIM; ++c) {
-            const uint32_t g = gidx++;
-            const int j = (int)(g / (uint32_t)kPer);
-            if (j != zblk) {
-              const uint32_t c0 = (uint32_t)label;
-              const uint32_t c1 = (5u << 28) | ((uint32_t)attempt << 24) |
-                                  ((uint32_t)((label >> 32) & 0xFFFFu) << 8) | (((uint32_t)j >> 8) & 0xFFu);
-              const uint32_t c3 = ((uint32_t)point & 0xFFFFFFu) | (((uint32_t)j & 0xFFu) << 24);
-              NZr::gen(c0, c1, tree, c3, k0, k1, zc);
-              zblk = j;
-            }
-            const int slot = (int)(g % (uint32_t)kPer);
-            R v = zc[0];
+            const int k = q * DIM + c;
+            R v = zb[k];
 #pragma unroll
-            for (int m = 1; m < kPer; ++m) v = slot == m ? zc[m] : v;
+            for (int m = 1; m < kPer; ++m) v = o0 == m ? zb[k + m] : v;
             z[c] = v;
           }
+          gidx += DIM;
           const R sd = sigma * fsqrt(sn - s);
 #pragma unroll
           for (int k = 0; k < DIM; ++k) X[k] = X[k] + sd * z[k];
