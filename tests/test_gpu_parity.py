@@ -366,6 +366,58 @@ def test_c5_full_size_sampled_nodes(pdd, orc):
     assert int(g["censored"].sum()) == 0
 
 
+def test_c2_full_size_sampled_nodes(pdd, orc):
+    """C2 as timed (256 nodes x 1e6 paths, dt 1e-4, FP32, the problem-specialised
+    kernel): 3 sampled nodes recomputed by the oracle on the first 2000 paths
+    of the same streams, and every node against the exact solution."""
+    w = CF.c2()
+    log("C2 full size (256 x 1e6, specialised kernel)")
+    g = pdd.mc_interface(w.problem, w.nodes, w.paths, w.dt, w.seed, precision="fp32")
+    torch.cuda.synchronize()
+    gm, gs = g["mean"].cpu().numpy(), g["se"].cpu().numpy()
+    assert np.all(g["n"].cpu().numpy() == 1_000_000)
+    assert int(g["censored"].sum()) == 0
+    idx = np.array([0, 100, 255])
+    o = orc.walk(w.problem, w.nodes[idx], np.full(3, 2000), w.dt, w.seed, layout=orc.QUAD24, node_ids=idx)
+    assert np.all(np.abs(gm[idx] - o["mean"]) <= 4.0 * np.sqrt(gs[idx] ** 2 + o["se"] ** 2) + 1e-5)
+    # the exit-overshoot bias of Euler-Maruyama is about 0.58 sqrt(dt) |du/dn|
+    # <= 0.016 here (|grad u| = e^y <= e); standard errors are 1e-4 .. 5e-4
+    err = np.max(np.abs(gm - CF.c2_exact(w.nodes)))
+    log(f"C2 max error vs exact {err:.4f}")
+    assert err < 3e-2
+
+
+def test_c4_full_size_sampled_points(pdd, orc):
+    """C4 as timed (1024 points x 1e5 trees in R^3, FP32): 3 sampled points
+    against the FP64 oracle on independent streams."""
+    w = CF.c4()
+    log("C4 full size (1024 x 1e5 trees)")
+    g = pdd.branching_eval(w.problem, w.points, w.trees, w.seed, precision="fp32")
+    torch.cuda.synchronize()
+    idx = np.array([0, 511, 1023])
+    o = orc.branching(w.problem, w.points[idx], 20000, w.seed + 1)
+    gm, gs = g["mean"].cpu().numpy()[idx], g["se"].cpu().numpy()[idx]
+    assert np.all(np.abs(gm - o["mean"]) <= 4.0 * np.sqrt(gs ** 2 + o["se"] ** 2) + 1e-5)
+    assert np.all(g["n"].cpu().numpy() == w.trees)
+
+
+def test_c6_full_size_sampled_points(pdd, orc):
+    """C6 as timed (1024 points x 1e5 trees, 11 output times, FP32): 3 sampled
+    points at every time against the FP64 oracle on independent streams, and
+    the t = 0 row equal to the initial data."""
+    w = CF.c6()
+    log("C6 full size (1024 x 1e5 trees, 11 times)")
+    g = pdd.branching_bvp(w.problem, w.boundary, w.points, w.trees, w.seed, precision="fp32")
+    torch.cuda.synchronize()
+    gm, gs = g["mean"].cpu().numpy(), g["se"].cpu().numpy()
+    assert gm.shape == (11, len(w.points))
+    idx = np.array([0, 500, 1023])
+    o = orc.branching_bvp(w.problem, w.boundary, w.points[idx], 20000, w.seed + 1)
+    assert np.all(np.abs(gm[:, idx] - o["mean"]) <= 4.0 * np.sqrt(gs[:, idx] ** 2 + o["se"] ** 2) + 1e-5)
+    psi0 = CF.travelling_wave(w.points[:, 0], 0.0)
+    assert np.allclose(gm[0], psi0, rtol=0, atol=1e-6)
+
+
 # ----------------------------------------------------------------------------- branching
 BR_CASES = {
     "c4": lambda: (CF.c4_problem("tanh"), np.array([[-1.0, 0.0, 0.5], [0.3, 1.0, -1.0], [1.9, -2.0, 0.0]])),
