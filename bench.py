@@ -560,7 +560,7 @@ def main():
                     help="only run C6 (branching with a boundary, 11 output times) twice (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library drives a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         import torch
