@@ -54,18 +54,18 @@ def log(msg):
 #   X += sigma sqrt(dt) z                                                3
 #   ball exit test: 3 sub, mul, 2 fma, compare                           7
 #   step count and cap                                                   2
-# forward: 120.  The adjoint adds Y dt, Z dt and 3 x 20 tangent FMAs
-# (F += m Y dt, S += m dt, B += m Z dt): 182.
+# forward: 120.  The adjoint adds the 3 x 20 tangent updates F/dt += m Y,
+# S/dt += m, B/dt += m Z (the factor dt is applied once per fold): 180.
 OPS_PER_PS_FWD = 120.0
-OPS_PER_PS_ADJ = 182.0
+OPS_PER_PS_ADJ = 180.0
 
 # HBM bytes per launch of the dominant kernel (C5 value+Jacobian walk),
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the 256 MiB copy
 # calibration (x 2.000 / x 1.000).  Valid only for the kernel sources they
 # were counted on: any change to them makes the bench report null.
 TRAFFIC_SOURCES = ['paper_1705_03666_amd/csrc/walk_kernels.hpp', 'paper_1705_03666_amd/csrc/pdd_device.hpp', 'paper_1705_03666_amd/csrc/pdd_internal.hpp', 'paper_1705_03666_amd/csrc/walk_adj_f32.hip']
-TRAFFIC_SHA256 = "180228a995beb3e9857b8c0a36fda1df6a39d2c4f1990b4dd789fa273b987614"
-TRAFFIC_BYTES = 36.88e6 + 95.35e6
+TRAFFIC_SHA256 = "5bc976e85da6d53bc22e46fafe4ca39c596be1c68e63763f6a700a5f78ae103d"
+TRAFFIC_BYTES = 38.76e6 + 95.99e6
 
 
 def traffic_bytes():

@@ -189,6 +189,11 @@ __device__ __forceinline__ R g_value_tp(const LinearParams& P, const R* xp) {
 // (summation by parts of -g Y_N S_j(N) - sum_n f_n Y_n dt S_j(n)).  F and B
 // need no per-path reset, so each lane keeps them as running sums over all
 // the paths it runs; only S is per path and travels with the exit record.
+// The lanes sum F/dt, S/dt and B/dt (dt is the same at every step), and the
+// factor dt is applied once, when the running sums are folded: the stepping
+// loop then adds m_j, m_j Y and m_j Z with no scalar-register operand, so
+// those updates can issue in the same cycle as another wavefront's
+// instruction that reads one.
 // At every record flush the running sums are reduced across the wavefront
 // into FP64 per-item accumulators (column ic lives in lane ic % 64, slot
 // ic / 64), so no FP32 sum spans more than about one path per lane.
@@ -299,7 +304,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
 
     // Folds CNT running sums v[] of every lane into accumulator columns
     // ic0.. through an LDS transpose: lane j then adds up column j in FP64.
-    auto fold = [&](R* v, const int cnt, const int ic0) {
+    auto fold = [&](R* v, const int cnt, const int ic0, const double scale) {
       constexpr int kS = kFoldMax | 1;
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -311,7 +316,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
 #pragma unroll 8
         for (int i = 0; i < kWave; ++i) s += (double)rec[i * kS + lane];
         const int ic = ic0 + lane;
-        acc[wid][ic >> 6][ic & (kWave - 1)] += s;
+        acc[wid][ic >> 6][ic & (kWave - 1)] += s * scale;
       }
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -409,10 +414,10 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
       }
       if constexpr (ADJ) {
         if constexpr (NP > 0) {
-          fold(Fr, NP, 0);
-          fold(Br, NP, NP);
+          fold(Fr, NP, 0, (double)dt);
+          fold(Br, NP, NP, (double)dt);
         }
-        if constexpr (NT > 0) fold(Gr, NT, 2 * NP);
+        if constexpr (NT > 0) fold(Gr, NT, 2 * NP, 1.0);
       }
     };
 
@@ -460,14 +465,13 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
             const R fv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_F>(P, P.f, X, mono);
             const R cv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_C>(P, P.c, X, mono);
             if constexpr (ADJ) {
-              const R Ydt = Y * dt;
 #pragma unroll
               for (int t = 0; t < NT; ++t)
-                if (t < P.f.n_terms) Fr[t] += TP::template term<R, DIM, FUN_F>(P, t, X) * Ydt;
+                if (t < P.f.n_terms) Fr[t] += TP::template term<R, DIM, FUN_F>(P, t, X) * Y;
               if constexpr (NM > 0) {
                 if (P.f.poly_deg >= 0) {
 #pragma unroll
-                  for (int m = 0; m < NM; ++m) Fr[NT + m] += mono[m] * Ydt;
+                  for (int m = 0; m < NM; ++m) Fr[NT + m] += mono[m] * Y;
                 }
               }
             }
@@ -475,11 +479,10 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
             // Y exp(0) leave the same bits as evaluating them
             if (P.has_f) Z = Z + fv * Y * dt;
             if constexpr (ADJ) {
-              const R Zdt = Z * dt;
 #pragma unroll
               for (int t = 0; t < NT; ++t) {
                 if (t < P.c.n_terms) {
-                  const R e = TP::template term<R, DIM, FUN_C>(P, t, X) * dt;
+                  const R e = TP::template term<R, DIM, FUN_C>(P, t, X);
                   S[t] += e;
                   Br[t] += e * Z;
                 }
@@ -488,8 +491,8 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
                 if (P.c.poly_deg >= 0) {
 #pragma unroll
                   for (int m = 0; m < NM; ++m) {
-                    S[NT + m] += mono[m] * dt;
-                    Br[NT + m] += mono[m] * Zdt;
+                    S[NT + m] += mono[m];
+                    Br[NT + m] += mono[m] * Z;
                   }
                 }
               }
