@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -57,24 +58,45 @@ std::string cache_dir() {
   return std::string(home) + "/.cache/pdd_jit";
 }
 
-bool read_file(const std::string& p, std::string* out) {
+// One cache entry is one file, written to a temporary name and renamed into
+// place, so a reader sees either a whole entry or none:
+//   "PDDJIT2\n", three little-endian uint64 lengths (key, symbol, code
+//   object), then the three byte strings.
+constexpr char kEntryMagic[8] = {'P', 'D', 'D', 'J', 'I', 'T', '2', '\n'};
+
+bool read_entry(const std::string& p, const std::string& key, std::string* sym, std::string* code) {
   std::ifstream f(p, std::ios::binary);
   if (!f) return false;
-  std::stringstream s;
-  s << f.rdbuf();
-  *out = s.str();
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string d = ss.str();
+  const size_t head = sizeof kEntryMagic + 3 * sizeof(uint64_t);
+  if (d.size() < head || d.compare(0, sizeof kEntryMagic, kEntryMagic, sizeof kEntryMagic) != 0) return false;
+  uint64_t n[3];
+  std::memcpy(n, d.data() + sizeof kEntryMagic, sizeof n);
+  if (n[0] > d.size() || n[1] > d.size() || n[2] > d.size() || head + n[0] + n[1] + n[2] != d.size()) return false;
+  if (n[1] == 0 || n[2] == 0 || d.compare(head, n[0], key) != 0) return false;
+  sym->assign(d, head + n[0], n[1]);
+  code->assign(d, head + n[0] + n[1], n[2]);
   return true;
 }
 
-void write_file_atomic(const std::string& p, const std::string& data) {
+void write_entry(const std::string& p, const std::string& key, const std::string& sym, const std::string& code) {
   const std::string tmp = p + ".tmp" + std::to_string((long)getpid());
   {
     std::ofstream f(tmp, std::ios::binary);
     if (!f) return;
-    f.write(data.data(), (std::streamsize)data.size());
-    if (!f) return;
+    const uint64_t n[3] = {key.size(), sym.size(), code.size()};
+    f.write(kEntryMagic, sizeof kEntryMagic);
+    f.write(reinterpret_cast<const char*>(n), sizeof n);
+    f << key << sym << code;
+    if (!f) {
+      f.close();
+      std::remove(tmp.c_str());
+      return;
+    }
   }
-  std::rename(tmp.c_str(), p.c_str());
+  if (std::rename(tmp.c_str(), p.c_str()) != 0) std::remove(tmp.c_str());
 }
 
 void make_dirs(const std::string& d) {
@@ -205,32 +227,30 @@ bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc,
     *fn = it->second;
     return true;
   }
-  // disk cache: <hash>.co (code object), <hash>.key (full key, checked), <hash>.sym
+  // disk cache: <hash>.pddjit holds the full key (compared on read), the
+  // lowered kernel name and the code object
   const std::string dir = cache_dir();
   char hx[32];
   std::snprintf(hx, sizeof hx, "%016llx", (unsigned long long)fnv1a(key));
-  const std::string stem = dir.empty() ? "" : dir + "/" + hx;
-  std::string code, lowered, stored_key;
-  bool have = false;
-  if (!stem.empty() && read_file(stem + ".key", &stored_key) && stored_key == key &&
-      read_file(stem + ".co", &code) && read_file(stem + ".sym", &lowered) && !code.empty() && !lowered.empty())
-    have = true;
+  const std::string path = dir.empty() ? "" : dir + "/" + hx + ".pddjit";
+  std::string code, lowered;
+  const bool have = !path.empty() && read_entry(path, key, &lowered, &code);
   if (!have) {
     if (!compile(src, name, arch, &code, &lowered, err)) return false;
-    if (!stem.empty()) {
+    if (!path.empty()) {
       make_dirs(dir);
-      write_file_atomic(stem + ".co", code);
-      write_file_atomic(stem + ".sym", lowered);
-      write_file_atomic(stem + ".key", key);
+      write_entry(path, key, lowered, code);
     }
   }
   hipModule_t mod;
   hipError_t e = hipModuleLoadData(&mod, code.data());
   if (e != hipSuccess && have) {
-    // a stale or damaged cache entry: compile afresh
+    // an entry that does not load (written by another runtime version, or
+    // damaged in place): compile afresh and replace it
     (void)hipGetLastError();
     if (!compile(src, name, arch, &code, &lowered, err)) return false;
     e = hipModuleLoadData(&mod, code.data());
+    if (e == hipSuccess) write_entry(path, key, lowered, code);
   }
   if (e != hipSuccess) {
     *err = std::string("hipModuleLoadData: ") + hipGetErrorString(e);
