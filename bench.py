@@ -370,12 +370,10 @@ def other_workloads(pdd, dev):
     def run_c3():
         return [pdd.mc_interface(P, nd, pa, dt, sd, precision="fp32") for P, nd, pa, dt, sd in subs]
 
-    from oracle import fun_eval  # exact u = g for the harmonic data of C3 (reference values only)
-
     def err_se(rs_):
         z = []
         for p, r in zip(parts, rs_):
-            exact = np.array([fun_eval(p.problem.g, p.problem.ndim, x) for x in p.nodes])
+            exact = CF.c3_exact(p)
             z.append(np.abs(r["mean"].cpu().numpy() - exact) / r["se"].cpu().numpy())
         z = np.concatenate(z)
         return float(z.max()), float(np.sqrt(np.mean(z ** 2)))
@@ -486,6 +484,50 @@ def other_workloads(pdd, dev):
     return res
 
 
+def run_only(name, scale):
+    """One workload of the other_workloads section, called twice (the first
+    call of C2 also compiles its specialised kernel); for profiler runs."""
+    import torch
+    import paper_1705_03666_amd as pdd
+    from workloads import configs as CF
+    dev = "cuda"
+    if name in ("c3", "c3wos"):
+        subs = [(p.problem, torch.tensor(p.nodes, device=dev), p.paths, p.dt, p.seed) for p in CF.c3(scale=scale)]
+        if name == "c3":
+            call = lambda: [pdd.mc_interface(P, nd, pa, dt, sd, precision="fp32") for P, nd, pa, dt, sd in subs]
+        else:
+            call = lambda: [pdd.wos_interface(P, nd, pa, 1e-4, sd, precision="fp32") for P, nd, pa, dt, sd in subs]
+        work = lambda rs: sum(float(r["steps"].sum().item()) for r in rs)
+        unit = "path_steps" if name == "c3" else "jumps"
+    elif name == "c2":
+        w = CF.c2(scale=scale)
+        nd = torch.tensor(w.nodes, device=dev)
+        call = lambda: pdd.mc_interface(w.problem, nd, w.paths, w.dt, w.seed, precision="fp32")
+        work = lambda r: float(r["steps"].sum().item())
+        unit = "path_steps"
+    elif name in ("c4", "c7"):
+        w = CF.c4(scale=scale) if name == "c4" else CF.c7(scale=scale)
+        pt = torch.tensor(w.points, device=dev)
+        call = lambda: pdd.branching_eval(w.problem, pt, w.trees, w.seed, precision="fp32")
+        work = lambda r: float(r["steps"].sum().item())
+        unit = "segments"
+    else:
+        w = CF.c6(scale=scale)
+        pt = torch.tensor(w.points, device=dev)
+        call = lambda: pdd.branching_bvp(w.problem, w.boundary, pt, w.trees, w.seed, precision="fp32")
+        work = lambda r: float(r["steps"][0].sum().item())
+        unit = "particle_substeps"
+    for i in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = call()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        n = work(r)
+        print(json.dumps({"workload": name.upper(), "call": i + 1, unit: n, "seconds": el,
+                          unit + "_per_s": n / el}), flush=True)
+
+
 def cpu_baseline(w, seconds, pdd, coefs, dev):
     """The FP64 oracle (forward + adjoint) on a bounded sample of the same
     workload, timed on the host's cores; the GPU FP32 path is then run on the
@@ -558,6 +600,9 @@ def main():
                     help="only run C2 at full size twice (the first call compiles its kernel; for profiler runs)")
     ap.add_argument("--c6-only", action="store_true",
                     help="only run C6 (branching with a boundary, 11 output times) twice (for profiler runs)")
+    ap.add_argument("--only", default="", choices=["", "c2", "c3", "c3wos", "c4", "c6", "c7"],
+                    help="only run this workload at full size (times --scale) twice, one JSON line per call "
+                         "(for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library drives a single MI355X (use --gpus 1)", file=sys.stderr)
@@ -571,37 +616,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}), flush=True)
         return
-    if args.c6_only:
-        import torch
-        import paper_1705_03666_amd as pdd
-        from workloads import configs as CF
-        c6 = CF.c6(scale=args.scale)
-        p6 = torch.tensor(c6.points, device="cuda")
-        for i in range(2):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = pdd.branching_bvp(c6.problem, c6.boundary, p6, c6.trees, c6.seed, precision="fp32")
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            sub = float(r["steps"][0].sum().item())
-            print(json.dumps({"workload": "C6", "call": i + 1, "trees": len(c6.points) * c6.trees,
-                              "particle_substeps": sub, "seconds": el, "substeps_per_s": sub / el}), flush=True)
-        return
     if args.c2_only:
-        import torch
-        import paper_1705_03666_amd as pdd
-        from workloads import configs as CF
-        c2 = CF.c2()
-        n2 = torch.tensor(c2.nodes, device="cuda")
-        for i in range(2):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = pdd.mc_interface(c2.problem, n2, c2.paths, c2.dt, c2.seed, precision="fp32")
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            ps = float(r["steps"].sum().item())
-            print(json.dumps({"workload": "C2", "call": i + 1, "path_steps": ps, "seconds": el,
-                              "path_steps_per_s": ps / el}), flush=True)
+        args.only = "c2"
+    if args.c6_only:
+        args.only = "c6"
+    if args.only:
+        run_only(args.only, args.scale)
         return
     out = run(args)
     print(json.dumps(out), flush=True)

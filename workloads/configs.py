@@ -234,6 +234,14 @@ def eval_dense_poly(ndim: int, degree: int, coef: np.ndarray, x: np.ndarray) -> 
     return vals @ coef
 
 
+def c3_exact(w: LinearWorkload) -> np.ndarray:
+    """Exact solution at the nodes of one C3 layout: u = g (harmonic data,
+    b = c = f = 0), g being a dense polynomial with no terms."""
+    g = w.problem.g
+    assert g.n_terms == 0 and g.poly_degree >= 0
+    return eval_dense_poly(w.problem.ndim, g.poly_degree, np.asarray(g.poly), w.nodes)
+
+
 # --------------------------------------------------------------------------- C4
 def c4_problem(psi: str = "tanh", sigma: float = 1.0) -> BranchingProblem:
     if psi == "tanh":
