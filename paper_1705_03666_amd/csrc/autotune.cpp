@@ -30,16 +30,26 @@ Tuning choose_tuning(int dim, bool fp32, bool adjoint, const pdd_options& o, int
   return t;
 }
 
-Tuning choose_branch_tuning(int dim, bool fp32, const pdd_options& o, int n_cus) {
+Tuning choose_branch_tuning(int dim, bool fp32, const pdd_options& o, int n_cus, int64_t total_trees) {
   (void)dim;
-  (void)fp32;
-  (void)n_cus;
   Tuning t;
-  t.chunk_paths = 2048;
-  t.blocks_per_cu = 2;
+  // measured on MI355X for C4 / C7 (k_branch) and C6 (k_branch_bvp), 1024
+  // points x 1e5 trees: three blocks per CU (the FP32 kernels' register and
+  // LDS budgets allow three) and items of 16384 trees, so a wavefront merges
+  // its Welford triple into an item slot rarely; 2 blocks and 2048-tree
+  // items took 1.8x (C4) and 1.04x (C6) as long
+  t.chunk_paths = 16384;
+  t.blocks_per_cu = fp32 ? 3 : 2;
   t.refill_groups = 1;
-  if (o.chunk_paths > 0) t.chunk_paths = o.chunk_paths;
   if (o.blocks_per_cu > 0) t.blocks_per_cu = o.blocks_per_cu;
+  if (o.chunk_paths > 0) {
+    t.chunk_paths = o.chunk_paths;
+  } else {
+    // smaller calls: halve the item size (down to 1024 trees) until every
+    // resident wavefront gets at least one item
+    const int64_t waves = (int64_t)t.blocks_per_cu * std::max(1, n_cus) * 4;
+    while (t.chunk_paths > 1024 && total_trees / t.chunk_paths < waves) t.chunk_paths /= 2;
+  }
   t.chunk_paths = std::max(1, t.chunk_paths);
   return t;
 }

@@ -1009,7 +1009,7 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   Tables T;
   BranchParams& bp = pl.bp;
   fill_branch_params(B, seed, T, bp);
-  const Tuning tune = choose_branch_tuning(B.dim, fp32, o, device_cus());
+  const Tuning tune = choose_branch_tuning(B.dim, fp32, o, device_cus(), n_points * trees);
   Items items = make_items(n_points, nullptr, trees, tune.chunk_paths, {});
   const int n_items = (int)items.q.size();
   const int max_blocks = tune.blocks_per_cu * device_cus();
@@ -1158,10 +1158,7 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   bb.g = T.add(Bd.g, B.dim, 0, true);
   bp.n_fac = (int)T.fac.size();
 
-  Tuning tune = choose_branch_tuning(B.dim, fp32, o, device_cus());
-  // the FP32 kernel fits three blocks per CU (registers and LDS): measured
-  // 30% faster than two on C6, no gain beyond
-  if (o.blocks_per_cu <= 0 && fp32) tune.blocks_per_cu = 3;
+  const Tuning tune = choose_branch_tuning(B.dim, fp32, o, device_cus(), n_points * trees);
   Items items = make_items(n_points, nullptr, trees, tune.chunk_paths, {});
   const int n_items = (int)items.q.size();
   const int max_blocks = tune.blocks_per_cu * device_cus();

@@ -18,6 +18,6 @@ struct Tuning {
 // total_paths: paths of the whole call (sizes the default work item so that
 // small calls still give every resident wavefront several items).
 Tuning choose_tuning(int dim, bool fp32, bool adjoint, const pdd_options& o, int n_cus, int64_t total_paths);
-Tuning choose_branch_tuning(int dim, bool fp32, const pdd_options& o, int n_cus);
+Tuning choose_branch_tuning(int dim, bool fp32, const pdd_options& o, int n_cus, int64_t total_trees);
 
 }  // namespace pdd
