@@ -34,12 +34,13 @@ Tuning choose_branch_tuning(int dim, bool fp32, const pdd_options& o, int n_cus,
   (void)dim;
   Tuning t;
   // measured on MI355X for C4 / C7 (k_branch) and C6 (k_branch_bvp), 1024
-  // points x 1e5 trees: three blocks per CU (the FP32 kernels' register and
-  // LDS budgets allow three) and items of 16384 trees, so a wavefront merges
-  // its Welford triple into an item slot rarely; 2 blocks and 2048-tree
-  // items took 1.8x (C4) and 1.04x (C6) as long
+  // points x 1e5 trees: four blocks per CU (the FP32 kernels are built for
+  // four waves per SIMD: at most 128 VGPRs and 37 KB of LDS per block) and
+  // items of 16384 trees, so a wavefront merges its Welford triple into an
+  // item slot rarely; 2 blocks and 2048-tree items took 2.0x (C4) and 1.2x
+  // (C6) as long
   t.chunk_paths = 16384;
-  t.blocks_per_cu = fp32 ? 3 : 2;
+  t.blocks_per_cu = fp32 ? 4 : 2;
   t.refill_groups = 1;
   if (o.blocks_per_cu > 0) t.blocks_per_cu = o.blocks_per_cu;
   if (o.chunk_paths > 0) {

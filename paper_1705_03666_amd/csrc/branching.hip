@@ -22,9 +22,16 @@
 
 namespace pdd {
 
-// LDS stack depth per lane (entries of 24 B in FP32, 40 B in FP64).
+// LDS stack depth per lane (entries of 24 B in FP32, 40 B in FP64); deeper
+// entries go to the per-lane spill area in global memory.  Six FP32 entries
+// keep a 256-thread block at 37 KB of LDS, so four blocks fit a CU (eight
+// entries allowed three: measured 13% slower on C6, 6-12% on C4 / C7).
 template <typename R>
-constexpr int lds_depth() { return sizeof(R) == 4 ? 8 : 4; }
+constexpr int lds_depth() { return sizeof(R) == 4 ? 6 : 4; }
+
+// FP32 kernels are built for four waves per SIMD (at most 128 VGPRs).
+template <typename R>
+constexpr int branch_min_waves() { return sizeof(R) == 4 ? 4 : 1; }
 
 template <typename R>
 struct BrScalars;
@@ -99,7 +106,7 @@ struct StackEntry {
 };
 
 template <typename R, int DIM, int LAYOUT>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, (branch_min_waves<R>()))
 k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, uint32_t* __restrict__ qhead,
          ItemStat* __restrict__ istat, double* __restrict__ dump_val, int64_t* __restrict__ dump_segs,
          int64_t trees, StackEntry<R>* __restrict__ spill, int64_t spill_entries) {
@@ -388,7 +395,7 @@ __device__ __forceinline__ R bvp_g(const BranchParams& P, const BranchBoundary& 
 enum : int { EV_OUT = 1, EV_STOP = 2, EV_DEATH = 4, EV_END = 8 };
 
 template <typename R, int DIM, int LAYOUT>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, (branch_min_waves<R>()))
 k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __restrict__ items, int n_items,
              uint32_t* __restrict__ qhead, ItemStat* __restrict__ istat, double* __restrict__ dump_val,
              int64_t* __restrict__ dump_segs, int64_t trees, StackEntry<R>* __restrict__ spill,
