@@ -151,8 +151,9 @@ std::map<std::string, hipFunction_t> g_spec;   // (device, key) -> loaded kernel
 }  // namespace
 
 std::string spec_terms_source(const LinearParams& P, const std::vector<DevFactor>& fac) {
-  std::ostringstream term, sum;
+  std::ostringstream term, sum, load;
   bool first = true;
+  int nst = 0;   // state slots: the term coefficients of b, c and f
   for (int w = 0; w < 6; ++w) {
     const DevFun& F = fun_at(P, w);
     if (F.n_terms <= 0) continue;
@@ -170,7 +171,15 @@ std::string spec_terms_source(const LinearParams& P, const std::vector<DevFactor
              << ", " << b << ");";
       }
       term << "\n      }\n";
-      sum << "      s += c[" << (F.coef_off + t) << "] * term<R, DIM, W>(P, " << t << ", x);\n";
+      if (w == 5) {
+        // g is evaluated once per exit: its coefficients stay in the table
+        sum << "      s += c[" << (F.coef_off + t) << "] * term<R, DIM, W>(P, " << t << ", x);\n";
+      } else {
+        load << "    st.c[" << nst << "] = c[" << (F.coef_off + t) << "];\n"
+             << "    asm volatile(\"\" : \"+v\"(st.c[" << nst << "]));\n";
+        sum << "      s += st.c[" << nst << "] * term<R, DIM, W>(P, " << t << ", x);\n";
+        ++nst;
+      }
     }
     term << "    }\n";
     sum << "    }\n";
@@ -178,6 +187,20 @@ std::string spec_terms_source(const LinearParams& P, const std::vector<DevFactor
   std::ostringstream o;
   o << "namespace pdd_spec {\n"
        "struct SpecTerms {\n"
+       "  template <typename R>\n"
+       "  struct State {\n"
+       "    R c["
+    << (nst > 0 ? nst : 1)
+    << "];\n"
+       "  };\n"
+       "  template <typename R>\n"
+       "  __device__ static __forceinline__ State<R> load(const pdd::LinearParams& P) {\n"
+       "    State<R> st;\n"
+       "    const R PDD_CONST_AS* c = pdd::coef_table<R>(P);\n"
+       "    (void)c;\n"
+    << load.str()
+    << "    return st;\n"
+       "  }\n"
        "  template <typename R, int DIM, int W>\n"
        "  __device__ static __forceinline__ R term(const pdd::LinearParams& P, int t, const R* x) {\n"
        "    (void)P;\n"
@@ -186,9 +209,10 @@ std::string spec_terms_source(const LinearParams& P, const std::vector<DevFactor
     << "    return v;\n"
        "  }\n"
        "  template <typename R, int DIM, int W>\n"
-       "  __device__ static __forceinline__ R sum(const pdd::LinearParams& P, const R* x) {\n"
+       "  __device__ static __forceinline__ R sum(const pdd::LinearParams& P, const State<R>& st, const R* x) {\n"
        "    const R PDD_CONST_AS* c = pdd::coef_table<R>(P);\n"
        "    (void)c;\n"
+       "    (void)st;\n"
        "    R s = (R)0;\n"
     << sum.str()
     << "    return s;\n"

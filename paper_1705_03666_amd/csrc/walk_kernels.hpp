@@ -132,15 +132,24 @@ __device__ __forceinline__ const DevFun& fun_of(const LinearParams& P) {
 
 // Generic-term evaluation policies of k_walk.  TableTerms interprets the
 // staged factor records at run time (any problem).  A problem-specialised
-// policy, generated as source and compiled at run time, has the same two
-// members with the factor structure (functions, coordinates, scales, shifts,
-// powers) written in as constants and the coefficients still read from the
-// table; it evaluates the same products in the same order.
-//   sum<R, DIM, W>(P, x)      sum over the terms t of function W of coef_t term_t(x)
+// policy, generated as source and compiled at run time, has the same members
+// with the factor structure (functions, coordinates, scales, shifts, powers)
+// written in as constants; it evaluates the same products in the same order.
+//   State<R>                  per-thread data loaded once per launch
+//   load<R>(P)                builds it (the specialised policy copies the
+//                             term coefficients of b, c and f into VGPRs, so
+//                             the per-step products read no scalar register)
+//   sum<R, DIM, W>(P, st, x)  sum over the terms t of function W of coef_t term_t(x)
 //   term<R, DIM, W>(P, t, x)  term_t(x) without its coefficient
 struct TableTerms {
+  template <typename R>
+  struct State {};
+  template <typename R>
+  __device__ static __forceinline__ State<R> load(const LinearParams&) {
+    return State<R>{};
+  }
   template <typename R, int DIM, int W>
-  __device__ static __forceinline__ R sum(const LinearParams& P, const R* x) {
+  __device__ static __forceinline__ R sum(const LinearParams& P, const State<R>&, const R* x) {
     return terms_sum<R, DIM>(P.fac, P.cd, P.cf, fun_of<W>(P), x);
   }
   template <typename R, int DIM, int W>
@@ -151,10 +160,11 @@ struct TableTerms {
 
 // b_k, c or f at X: generic terms (only when TERMS) plus the dense polynomial.
 template <typename R, int DIM, int DFC, bool TERMS, class TP, int W>
-__device__ __forceinline__ R bcf_value(const LinearParams& P, const DevFun& F, const R* X, const R* mono) {
+__device__ __forceinline__ R bcf_value(const LinearParams& P, const typename TP::template State<R>& st,
+                                       const DevFun& F, const R* X, const R* mono) {
   R v = (R)0;
   if constexpr (TERMS) {
-    if (F.n_terms > 0) v = TP::template sum<R, DIM, W>(P, X);
+    if (F.n_terms > 0) v = TP::template sum<R, DIM, W>(P, st, X);
   }
   if constexpr (DFC >= 0) {
     if (F.poly_deg >= 0) v += poly_dot<R, GradedLex<DIM, DFC>::N>(coef_table<R>(P) + F.poly_off, mono);
@@ -164,9 +174,10 @@ __device__ __forceinline__ R bcf_value(const LinearParams& P, const DevFun& F, c
 
 // g at the projected exit point: generic terms plus the nested polynomial.
 template <typename R, int DIM, class TP>
-__device__ __forceinline__ R g_value_tp(const LinearParams& P, const R* xp) {
+__device__ __forceinline__ R g_value_tp(const LinearParams& P, const typename TP::template State<R>& st,
+                                        const R* xp) {
   R v = (R)0;
-  if (P.g.n_terms > 0) v = TP::template sum<R, DIM, FUN_G>(P, xp);
+  if (P.g.n_terms > 0) v = TP::template sum<R, DIM, FUN_G>(P, st, xp);
   if (P.g.poly_deg >= 0) v += poly_nested<R, DIM>(P.cd, P.cf, P.g.poly_deg, P.g.poly_off, xp);
   return v;
 }
@@ -247,6 +258,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   const Dom<R> Dt = make_test_dom<R>(P);    // exit test
   const R dt = dt_of<R>(P);
   const R sdt = sdt_of<R>(P);
+  const typename TP::template State<R> tst = TP::template load<R>(P);
   const uint32_t max_steps = (uint32_t)P.max_steps;
   const uint32_t k0 = P.key0, k1 = P.key1;
   const int ngm = (ADJ && P.g.poly_deg >= 0) ? P.g.n_mono : 0;
@@ -338,7 +350,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           const R y = rec[DIM * kWave + lane], z = rec[(DIM + 1) * kWave + lane];
           const uint32_t pr = rec_i[wid][0][lane], nr = rec_i[wid][1][lane];
           project<R, DIM>(D, xe, xr);
-          const R gv = g_value_tp<R, DIM, TP>(P, xr);
+          const R gv = g_value_tp<R, DIM, TP>(P, tst, xr);
           const R phi = gv * y + z;
           const double ph = (double)phi;
           wn += 1.0;
@@ -462,8 +474,8 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           if (alive && n < max_steps) {
             R mono[NM > 0 ? NM : 1];
             if constexpr (DFC >= 0) monomials<R, DIM, DFC>(X, mono);
-            const R fv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_F>(P, P.f, X, mono);
-            const R cv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_C>(P, P.c, X, mono);
+            const R fv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_F>(P, tst, P.f, X, mono);
+            const R cv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_C>(P, tst, P.c, X, mono);
             if constexpr (ADJ) {
 #pragma unroll
               for (int t = 0; t < NT; ++t)
@@ -501,12 +513,12 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
             if (P.has_b) {
               R bv[DIM];
               if constexpr (TERMS) {
-                bv[0] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B0>(P, P.b[0], X, mono);
-                if constexpr (DIM >= 2) bv[1] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B1>(P, P.b[1], X, mono);
-                if constexpr (DIM >= 3) bv[2] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B2>(P, P.b[2], X, mono);
+                bv[0] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B0>(P, tst, P.b[0], X, mono);
+                if constexpr (DIM >= 2) bv[1] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B1>(P, tst, P.b[1], X, mono);
+                if constexpr (DIM >= 3) bv[2] = bcf_value<R, DIM, DFC, TERMS, TP, FUN_B2>(P, tst, P.b[2], X, mono);
               } else {
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) bv[k] = bcf_value<R, DIM, DFC, false, TP, FUN_B0>(P, P.b[k], X, mono);
+                for (int k = 0; k < DIM; ++k) bv[k] = bcf_value<R, DIM, DFC, false, TP, FUN_B0>(P, tst, P.b[k], X, mono);
               }
 #pragma unroll
               for (int k = 0; k < DIM; ++k) X[k] = X[k] + bv[k] * dt + sdt * z[s * DIM + k];
