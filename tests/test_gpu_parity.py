@@ -387,6 +387,22 @@ def test_c2_full_size_sampled_nodes(pdd, orc):
     assert err < 3e-2
 
 
+def test_c3_full_size_sampled_nodes(pdd, orc):
+    """C3 as timed (4096 nodes over 8 layouts, budgets 1e3..1e5, dt 1e-3,
+    FP32, one call per layout): in every layout 2 sampled nodes recomputed by
+    the oracle on the first 2000 paths of the same streams."""
+    for w in CF.c3():
+        log(f"C3 full size: {w.name}, {len(w.nodes)} nodes")
+        g = pdd.mc_interface(w.problem, w.nodes, w.paths, w.dt, w.seed, precision="fp32")
+        torch.cuda.synchronize()
+        assert np.all(g["n"].cpu().numpy() == w.paths)
+        assert int(g["censored"].sum()) == 0
+        idx = np.array([0, len(w.nodes) - 1])
+        o = orc.walk(w.problem, w.nodes[idx], np.full(2, 2000), w.dt, w.seed, layout=orc.QUAD24, node_ids=idx)
+        gm, gs = g["mean"].cpu().numpy()[idx], g["se"].cpu().numpy()[idx]
+        assert np.all(np.abs(gm - o["mean"]) <= 4.0 * np.sqrt(gs ** 2 + o["se"] ** 2) + 1e-5), w.name
+
+
 def test_c4_full_size_sampled_points(pdd, orc):
     """C4 as timed (1024 points x 1e5 trees in R^3, FP32): 3 sampled points
     against the FP64 oracle on independent streams."""
