@@ -64,8 +64,8 @@ OPS_PER_PS_ADJ = 180.0
 # calibration (x 2.000 / x 1.000).  Valid only for the kernel sources they
 # were counted on: any change to them makes the bench report null.
 TRAFFIC_SOURCES = ['paper_1705_03666_amd/csrc/walk_kernels.hpp', 'paper_1705_03666_amd/csrc/pdd_device.hpp', 'paper_1705_03666_amd/csrc/pdd_internal.hpp', 'paper_1705_03666_amd/csrc/walk_adj_f32.hip']
-TRAFFIC_SHA256 = "425f360d28bf6393bff99dcc486e00d73901f0c4b57f7bf4652ae5270043459e"
-TRAFFIC_BYTES = 38.82e6 + 96.26e6
+TRAFFIC_SHA256 = "9b3486d56c070276749b6615cd34f8150bf1b065080348471e01c4036c78c0b1"
+TRAFFIC_BYTES = 59.22e6 + 119.75e6
 
 
 def traffic_bytes():

@@ -119,6 +119,18 @@ __device__ __forceinline__ R poly_dot(const R PDD_CONST_AS* c, const R* mono) {
   return s;
 }
 
+// The same with the coefficients in LDS: every lane reads the same address
+// (a broadcast, four coefficients per read), and the products then take
+// only VGPR operands, so they can share an issue slot with another
+// wavefront's instruction that reads a scalar register.
+template <typename R, int NM>
+__device__ __forceinline__ R poly_dot_lds(const __attribute__((address_space(3))) R* c, const R* mono) {
+  R s = c[0];
+#pragma unroll
+  for (int m = 1; m < NM; ++m) s += c[m] * mono[m];
+  return s;
+}
+
 // The six coefficient functions of a linear problem, as template arguments.
 enum : int { FUN_B0 = 0, FUN_B1 = 1, FUN_B2 = 2, FUN_C = 3, FUN_F = 4, FUN_G = 5 };
 
@@ -252,7 +264,30 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   __shared__ double acc[ADJ ? kWaves : 1][kSlots][kWave];
   // g-polynomial monomial k (nested order): its three power-table rows
   __shared__ uint32_t gmono[ADJ ? kGMono : 1];
+  // The adjoint keeps the statistics of the current item per wavefront in
+  // LDS (FP64 Welford triple (n, mean, M2), step and censoring counts),
+  // merged at every flush, so no lane holds FP64 or 64-bit accumulators
+  // through its register-bound stepping loop; the forward kernels, whose
+  // steps are short, keep them per lane (cheaper flushes).
+  constexpr bool kWaveStats = ADJ;
+  __shared__ double wstat[kWaveStats ? kWaves : 1][3];
+  __shared__ int64_t wcount[kWaveStats ? kWaves : 1][2];
   R* const rec = &area[wid][0];
+  // FP32 adjoint without generic terms: the dense coefficients of c and f are
+  // copied into LDS once per block and read from there at every step (the
+  // table-read form makes 40 of the step's FMAs read SGPRs)
+  constexpr bool kLdsPoly = ADJ && sizeof(R) == 4 && !TERMS && !WOS && DFC >= 0;
+  constexpr int kNMc = GradedLex<DIM, (DFC >= 0 ? DFC : 0)>::N;
+  constexpr int kNMp = ((kNMc + 3) / 4) * 4;      // 16-byte aligned rows
+  __shared__ __attribute__((aligned(16))) R lpoly[kLdsPoly ? 2 * kNMp : 4];   // row 0: c, row 1: f
+  if constexpr (kLdsPoly) {
+    for (int i = (int)threadIdx.x; i < 2 * kNMp; i += kBlock) {
+      const DevFun& F = i < kNMp ? P.c : P.f;
+      const int m = i % kNMp;
+      lpoly[i] = (F.poly_deg >= 0 && m < kNMc) ? P.cf[F.poly_off + m] : (R)0;
+    }
+    __syncthreads();
+  }
 
   const Dom<R> D = make_dom<R>(P);          // projection of exit points
   const Dom<R> Dt = make_test_dom<R>(P);    // exit test
@@ -300,8 +335,17 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
     R Y = (R)1, Z = (R)0;
     uint32_t n = 0;
 
-    double wn = 0.0, wmean = 0.0, wm2 = 0.0;
+    double wn = 0.0, wmean = 0.0, wm2 = 0.0;   // per lane (forward kernels)
     int64_t lsteps = 0, lcens = 0;
+    if constexpr (kWaveStats) {
+      if (lane == 0) {
+        wstat[wid][0] = 0.0;
+        wstat[wid][1] = 0.0;
+        wstat[wid][2] = 0.0;
+        wcount[wid][0] = 0;
+        wcount[wid][1] = 0;
+      }
+    }
     int nrec = 0;
 
     R S[NP > 0 ? NP : 1], Fr[NP > 0 ? NP : 1], Br[NP > 0 ? NP : 1], Gr[NT > 0 ? NT : 1];
@@ -343,6 +387,8 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
         __builtin_amdgcn_wave_barrier();
         R xr[3] = {(R)0, (R)0, (R)0};
         R yr = (R)0;
+        uint32_t rsteps = 0, rcens = 0;
+        double rph = 0.0;
         if (lane < nrec) {
           R xe[DIM];
 #pragma unroll
@@ -353,12 +399,18 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           const R gv = g_value_tp<R, DIM, TP>(P, tst, xr);
           const R phi = gv * y + z;
           const double ph = (double)phi;
-          wn += 1.0;
-          const double d1 = ph - wmean;
-          wmean += d1 / wn;
-          wm2 += d1 * (ph - wmean);
-          lsteps += (int64_t)(nr & 0x7FFFFFFFu);
-          lcens += (int64_t)(nr >> 31);
+          if constexpr (kWaveStats) {
+            rph = ph;
+            rsteps = nr & 0x7FFFFFFFu;
+            rcens = nr >> 31;
+          } else {
+            wn += 1.0;
+            const double d1 = ph - wmean;
+            wmean += d1 / wn;
+            wm2 += d1 * (ph - wmean);
+            lsteps += (int64_t)(nr & 0x7FFFFFFFu);
+            lcens += (int64_t)(nr >> 31);
+          }
           if (dump_phi != nullptr) {
             const int64_t o = dump_off[node] + (int64_t)pr;
             dump_phi[o] = ph;
@@ -371,6 +423,24 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
             for (int t = 0; t < NT; ++t)
               if (t < P.g.n_terms) Gr[t] += y * TP::template term<R, DIM, FUN_G>(P, t, xr);
             yr = y;
+          }
+        }
+        if constexpr (kWaveStats) {
+          // the records' values, step and censoring counts into the
+          // wavefront's item totals: a butterfly Welford merge over the
+          // record lanes, then one Chan merge into the running triple
+          double bn = lane < nrec ? 1.0 : 0.0, bm = rph, bq = 0.0;
+          wave_welford(bn, bm, bq);
+          const int64_t fs = wave_sum((int64_t)rsteps);
+          const int64_t fc = (int64_t)__popcll(ballot(rcens != 0));
+          if (lane == 0) {
+            double an = wstat[wid][0], am = wstat[wid][1], aq = wstat[wid][2];
+            chan_merge(an, am, aq, bn, bm, bq);
+            wstat[wid][0] = an;
+            wstat[wid][1] = am;
+            wstat[wid][2] = aq;
+            wcount[wid][0] += fs;
+            wcount[wid][1] += fc;
           }
         }
         if constexpr (ADJ) {
@@ -474,8 +544,15 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
           if (alive && n < max_steps) {
             R mono[NM > 0 ? NM : 1];
             if constexpr (DFC >= 0) monomials<R, DIM, DFC>(X, mono);
-            const R fv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_F>(P, tst, P.f, X, mono);
-            const R cv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_C>(P, tst, P.c, X, mono);
+            R fv, cv;
+            if constexpr (kLdsPoly) {
+              const __attribute__((address_space(3))) R* lp = (const __attribute__((address_space(3))) R*)lpoly;
+              fv = P.f.poly_deg >= 0 ? poly_dot_lds<R, NM>(lp + kNMp, mono) : (R)0;
+              cv = P.c.poly_deg >= 0 ? poly_dot_lds<R, NM>(lp, mono) : (R)0;
+            } else {
+              fv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_F>(P, tst, P.f, X, mono);
+              cv = bcf_value<R, DIM, DFC, TERMS, TP, FUN_C>(P, tst, P.c, X, mono);
+            }
             if constexpr (ADJ) {
 #pragma unroll
               for (int t = 0; t < NT; ++t)
@@ -584,9 +661,17 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
 
     // ---- item results
     flush();
-    wave_welford(wn, wmean, wm2);
-    lsteps = wave_sum(lsteps);
-    lcens = wave_sum(lcens);
+    if constexpr (kWaveStats) {
+      wn = wstat[wid][0];
+      wmean = wstat[wid][1];
+      wm2 = wstat[wid][2];
+      lsteps = wcount[wid][0];
+      lcens = wcount[wid][1];
+    } else {
+      wave_welford(wn, wmean, wm2);
+      lsteps = wave_sum(lsteps);
+      lcens = wave_sum(lcens);
+    }
     if (lane == 0 && istat != nullptr) {
       ItemStat st;
       st.mean = wmean;
