@@ -1,0 +1,41 @@
+"""Host-side checks of bench.py: the single-GPU contract and the bookkeeping
+behind its roofline object (no GPU needed)."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+    assert p.stdout.strip() == ""
+
+
+def test_traffic_figure_matches_the_committed_kernel_sources():
+    """The HBM bytes reported as roofline.traffic were counted on the current
+    sources of the dominant kernel (a kernel change without re-counting makes
+    bench.py report null, and this test fail)."""
+    b = _bench()
+    t = b.traffic_bytes()
+    assert t is not None
+    # at least the algorithmic bytes of a launch: 57344 items x (160 x 8 + 48) B
+    assert t >= 57344 * (160 * 8 + 48)
+
+
+def test_op_table_and_peak():
+    b = _bench()
+    assert b.OPS_PER_PS_FWD == 120.0 and b.OPS_PER_PS_ADJ == 180.0
+    # 256 CUs x 128 FP32 lanes x 2.4 GHz: half the published 157.3 TFLOP/s (FMA = 2 flops)
+    assert abs(b.PEAK_LANE_OPS * 2 - 157.3e12) / 157.3e12 < 1e-3
