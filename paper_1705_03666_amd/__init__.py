@@ -26,7 +26,7 @@ import torch
 
 from . import _abi as A
 
-__all__ = ["mc_interface", "mc_adjoint", "mc_value_jacobian", "branching_eval", "branching_bvp", "wos_interface",
+__all__ = ["mc_interface", "mc_interface_many", "mc_adjoint", "mc_value_jacobian", "branching_eval", "branching_bvp", "wos_interface",
            "item_count", "PDDInterface", "PddError",
            "release_workspace", "query_warnings", "library", "version", "param_layout", "jacobian_blocks"]
 
@@ -264,6 +264,40 @@ def wos_interface(problem, nodes, paths, eps: float, seed: int = 0, precision: s
         res["phi"], res["path_steps"] = dphi[:total], dst[:total]
     res["_keep"] = keep
     return res
+
+
+_STREAM_POOL: Dict[int, list] = {}
+
+
+def mc_interface_many(calls, max_streams: int = 8) -> list:
+    """Several independent mc_interface calls (for instance the subdomain
+    layouts of one batch, each with its own domain and data), issued on a pool
+    of HIP streams so that one launch's tail overlaps the next launch; the
+    current stream waits for all of them.  `calls` is a list of
+    (args, kwargs) for mc_interface.  Every call computes exactly what it
+    computes alone (same paths, same item order), so the results are
+    identical to issuing the calls one after the other."""
+    _need_gpu()
+    dev = torch.cuda.current_device()
+    pool = _STREAM_POOL.setdefault(dev, [])
+    n = max(1, min(int(max_streams), len(calls)))
+    while len(pool) < n:
+        pool.append(torch.cuda.Stream(device=dev))
+    cur = torch.cuda.current_stream()
+    out = []
+    for i, (args, kwargs) in enumerate(calls):
+        s = pool[i % n]
+        s.wait_stream(cur)
+        with torch.cuda.stream(s):
+            r = mc_interface(*args, **kwargs)
+        # results are read on the current stream: tell the caching allocator
+        for v in r.values():
+            if isinstance(v, torch.Tensor) and v.is_cuda:
+                v.record_stream(cur)
+        out.append(r)
+    for s in pool[:n]:
+        cur.wait_stream(s)
+    return out
 
 
 def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = "fp32",

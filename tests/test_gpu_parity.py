@@ -403,6 +403,20 @@ def test_c3_full_size_sampled_nodes(pdd, orc):
         assert np.all(np.abs(gm - o["mean"]) <= 4.0 * np.sqrt(gs ** 2 + o["se"] ** 2) + 1e-5), w.name
 
 
+def test_mc_interface_many_equals_serial_calls(pdd):
+    """Independent calls issued on a pool of streams compute exactly what
+    they compute one after the other (the C3 layouts at a small budget, with
+    per-path dumps), and their results are read correctly on the current stream."""
+    parts = CF.c3(scale=0.02)
+    calls = [((w.problem, w.nodes, w.paths, w.dt, w.seed), dict(precision="fp32", dump=True)) for w in parts]
+    ser = [pdd.mc_interface(*a, **k) for a, k in calls]
+    for max_streams in (8, 3):
+        many = pdd.mc_interface_many(calls, max_streams=max_streams)
+        for a, b in zip(ser, many):
+            for key in ("mean", "m2", "n", "steps", "censored", "phi", "path_steps"):
+                assert torch.equal(a[key], b[key]), (max_streams, key)
+
+
 def test_c4_full_size_sampled_points(pdd, orc):
     """C4 as timed (1024 points x 1e5 trees in R^3, FP32): 3 sampled points
     against the FP64 oracle on independent streams."""
