@@ -273,10 +273,10 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   __shared__ double wstat[kWaveStats ? kWaves : 1][3];
   __shared__ int64_t wcount[kWaveStats ? kWaves : 1][2];
   R* const rec = &area[wid][0];
-  // FP32 adjoint without generic terms: the dense coefficients of c and f are
+  // FP32 walks without generic terms: the dense coefficients of c and f are
   // copied into LDS once per block and read from there at every step (the
   // table-read form makes 40 of the step's FMAs read SGPRs)
-  constexpr bool kLdsPoly = ADJ && sizeof(R) == 4 && !TERMS && !WOS && DFC >= 0;
+  constexpr bool kLdsPoly = sizeof(R) == 4 && !TERMS && !WOS && DFC >= 0;
   constexpr int kNMc = GradedLex<DIM, (DFC >= 0 ? DFC : 0)>::N;
   constexpr int kNMp = ((kNMc + 3) / 4) * 4;      // 16-byte aligned rows
   __shared__ __attribute__((aligned(16))) R lpoly[kLdsPoly ? 2 * kNMp : 4];   // row 0: c, row 1: f
