@@ -291,8 +291,9 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
 
   const Dom<R> D = make_dom<R>(P);          // projection of exit points
   const Dom<R> Dt = make_test_dom<R>(P);    // exit test
-  const R dt = dt_of<R>(P);
-  const R sdt = sdt_of<R>(P);
+  R dt = dt_of<R>(P);
+  R sdt = sdt_of<R>(P);
+  if constexpr (sizeof(R) == 4 && TERMS && !ADJ) asm volatile("" : "+v"(dt), "+v"(sdt));
   const typename TP::template State<R> tst = TP::template load<R>(P);
   const uint32_t max_steps = (uint32_t)P.max_steps;
   const uint32_t k0 = P.key0, k1 = P.key1;
