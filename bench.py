@@ -64,8 +64,8 @@ OPS_PER_PS_ADJ = 180.0
 # calibration (x 2.000 / x 1.000).  Valid only for the kernel sources they
 # were counted on: any change to them makes the bench report null.
 TRAFFIC_SOURCES = ['paper_1705_03666_amd/csrc/walk_kernels.hpp', 'paper_1705_03666_amd/csrc/pdd_device.hpp', 'paper_1705_03666_amd/csrc/pdd_internal.hpp', 'paper_1705_03666_amd/csrc/walk_adj_f32.hip']
-TRAFFIC_SHA256 = "3ce0e4b1565c341fb06d6be86b58fa6a940e5e9d63d4e711f47b7c01d3446f00"
-TRAFFIC_BYTES = 59.55e6 + 119.96e6
+TRAFFIC_SHA256 = "282f8fa0c6b0a952ac712099d7ebaf3582d0b0426329efbdf012fa571ef19d2b"
+TRAFFIC_BYTES = 59.41e6 + 131.81e6
 
 
 def traffic_bytes():

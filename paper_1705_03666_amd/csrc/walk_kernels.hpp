@@ -293,7 +293,9 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
   const Dom<R> Dt = make_test_dom<R>(P);    // exit test
   R dt = dt_of<R>(P);
   R sdt = sdt_of<R>(P);
-  if constexpr (sizeof(R) == 4 && TERMS && !ADJ) asm volatile("" : "+v"(dt), "+v"(sdt));
+  // FP32: keep the step sizes in VGPRs, so the products that use them read no
+  // SGPR and can share an issue slot with another wavefront's instruction
+  if constexpr (sizeof(R) == 4) asm volatile("" : "+v"(dt), "+v"(sdt));
   const typename TP::template State<R> tst = TP::template load<R>(P);
   const uint32_t max_steps = (uint32_t)P.max_steps;
   const uint32_t k0 = P.key0, k1 = P.key1;
