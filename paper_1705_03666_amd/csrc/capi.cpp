@@ -38,6 +38,45 @@ pdd_status fail(pdd_status s, const std::string& msg) {
     if (e_ != hipSuccess) return fail(PDD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// ----------------------------------------------------------------------------- call arenas
+// Every call takes its device buffers (tables, work queue, per-item
+// statistics, branching stack) as one stream-ordered arena.  They come from a
+// memory pool of the library's own, one per device, that keeps the pages it
+// has mapped after a free (no release threshold): a repeated call maps no new
+// memory.  The process's default pool is left as it is.  The pool holds at
+// most the largest set of arenas in flight at once, until the process ends.
+hipError_t arena_alloc(void** p, size_t bytes, hipStream_t st) {
+  static std::mutex mu;
+  static std::vector<hipMemPool_t> pools;  // by device ordinal
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)pools.size() <= dev) pools.resize(dev + 1, nullptr);
+    if (pools[dev] == nullptr) {
+      hipMemPoolProps pr;
+      std::memset(&pr, 0, sizeof(pr));
+      pr.allocType = hipMemAllocationTypePinned;
+      pr.location.type = hipMemLocationTypeDevice;
+      pr.location.id = dev;
+      hipMemPool_t np = nullptr;
+      e = hipMemPoolCreate(&np, &pr);
+      if (e != hipSuccess) return e;
+      uint64_t keep = UINT64_MAX;
+      e = hipMemPoolSetAttribute(np, hipMemPoolAttrReleaseThreshold, &keep);
+      if (e != hipSuccess) {
+        (void)hipMemPoolDestroy(np);
+        return e;
+      }
+      pools[dev] = np;
+    }
+    pool = pools[dev];
+  }
+  return hipMallocFromPoolAsync(p, bytes, pool, st);
+}
+
 // ----------------------------------------------------------------------------- monomials
 int n_mono(int dim, int deg) {
   if (deg < 0) return 0;
@@ -741,7 +780,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     PDD_HIP(hipMalloc(&pl.arena, A.total));
     pl.owned = true;
   } else {
-    PDD_HIP(hipMallocAsync(&pl.arena, A.total, st));
+    PDD_HIP(arena_alloc(&pl.arena, A.total, st));
   }
   char* base = (char*)pl.arena;
   pl.d_jobs = (StageJob*)(base + o_jobs);
@@ -1029,7 +1068,7 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   const size_t o_first = A.add(sizeof(int64_t) * ((size_t)n_points + 1));
   const size_t o_spill =
       A.add(branch_stack_entry_bytes(fp32) * (size_t)std::max<int64_t>(1, spill_entries) * (size_t)grid * kBlock);
-  PDD_HIP(hipMallocAsync(&pl.arena, A.total, st));
+  PDD_HIP(arena_alloc(&pl.arena, A.total, st));
   char* base = (char*)pl.arena;
   pl.d_jobs = (StageJob*)(base + o_jobs);
   pl.n_jobs = (int)T.jobs.size();
@@ -1178,7 +1217,7 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   const size_t o_first = A.add(sizeof(int64_t) * ((size_t)n_points + 1));
   const size_t o_spill =
       A.add(branch_stack_entry_bytes(fp32) * (size_t)std::max<int64_t>(1, spill_entries) * (size_t)grid * kBlock);
-  PDD_HIP(hipMallocAsync(&pl.arena, A.total, st));
+  PDD_HIP(arena_alloc(&pl.arena, A.total, st));
   char* base = (char*)pl.arena;
   pl.d_jobs = (StageJob*)(base + o_jobs);
   pl.n_jobs = (int)T.jobs.size();
