@@ -934,7 +934,7 @@ namespace {
 
 // Assumption 3.2 with l0(s) = sum |alpha_k| s^k, l(s) = beta (l0(s psi_sup)/psi_sup - s):
 // admissible if l(1) <= 0, or l has a zero beyond 1, or int_1^inf ds / l(s) > T.
-bool admissible(const pdd_branching_problem& B, std::string* why) {
+bool admissible_scan(const pdd_branching_problem& B, std::string* why) {
   const double ps = B.psi_sup;
   auto l = [&](double s) {
     double l0 = 0.0, p = 1.0;
@@ -967,6 +967,35 @@ bool admissible(const pdd_branching_problem& B, std::string* why) {
   if (why) *why = "the branching representation may blow up before T (Assumption 3.2: l(1) > 0 and int 1/l = " +
                   std::to_string(integral) + " <= T)";
   return false;
+}
+
+// The scan above depends only on alpha, sup|psi|, beta and T; its verdict
+// (and message) is kept per problem, so repeated calls on one problem, the
+// usual case, skip the 2e5-point scan.  At most 256 problems are kept.
+bool admissible(const pdd_branching_problem& B, std::string* why) {
+  std::array<double, 8> key;
+  for (int k = 0; k < 5; ++k) key[k] = B.alpha[k];
+  key[5] = B.psi_sup;
+  key[6] = B.beta;
+  key[7] = B.T;
+  std::string k_bytes(reinterpret_cast<const char*>(key.data()), sizeof(key));
+  static std::mutex mu;
+  static std::unordered_map<std::string, std::pair<bool, std::string>> seen;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = seen.find(k_bytes);
+    if (it != seen.end()) {
+      if (why) *why = it->second.second;
+      return it->second.first;
+    }
+  }
+  std::string msg;
+  const bool ok = admissible_scan(B, &msg);
+  std::lock_guard<std::mutex> lock(mu);
+  if (seen.size() >= 256) seen.clear();
+  seen.emplace(std::move(k_bytes), std::make_pair(ok, msg));
+  if (why) *why = msg;
+  return ok;
 }
 
 // Branching problem checks shared by pdd_branching_eval and pdd_branching_bvp.
