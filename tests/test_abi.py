@@ -153,6 +153,35 @@ def test_branching_admissibility_is_checked_on_the_host(abi):
     assert st == abi.PDD_ERR_INVALID_ARG
 
 
+def test_branching_admissibility_verdict_is_kept_per_problem(abi):
+    """The Assumption 3.2 verdict is kept per (alpha, sup|psi|, beta, T):
+    repeated calls on one problem get the same verdict and message, and a
+    change of T alone is checked again (blow-up time ln 2 for this problem)."""
+    lib = abi.load()
+    b = abi.pdd_branching_problem()
+    b.dim, b.max_segments = 1, 127
+    b.sigma, b.beta = 1.0, 1.0
+    b.alpha[2] = 1.0
+    b.q[2] = 1.0
+    b.psi_sup = 2.0
+    b.psi.poly_degree = 0
+    b.psi.poly = 1
+    o = _opts(abi)
+    msgs = []
+    for T, want in ((1.0, abi.PDD_ERR_NOT_ADMISSIBLE), (0.5, abi.PDD_ERR_INVALID_ARG),
+                    (1.0, abi.PDD_ERR_NOT_ADMISSIBLE), (0.69, abi.PDD_ERR_INVALID_ARG),
+                    (0.70, abi.PDD_ERR_NOT_ADMISSIBLE), (1.0, abi.PDD_ERR_NOT_ADMISSIBLE)):
+        b.T = T
+        assert lib.pdd_branching_eval(C.byref(b), None, 1, 10, 0, C.byref(o), None, None) == want, T
+        if want == abi.PDD_ERR_NOT_ADMISSIBLE:
+            msgs.append((T, lib.pdd_last_error().decode()))
+    by_t = {}
+    for T, m in msgs:
+        assert "Assumption 3.2" in m
+        by_t.setdefault(T, set()).add(m)
+    assert all(len(v) == 1 for v in by_t.values())
+
+
 def test_branching_bvp_arguments_are_checked_on_the_host(abi):
     """pdd_branching_bvp: output times, dt, the per-particle Gaussian-block
     limit, the domain, the time coordinate of g and admissibility over
