@@ -25,10 +25,12 @@ import numpy as np
 import torch
 
 from . import _abi as A
+from . import nonlinear  # noqa: F401  (host-side driver of Sec. 3.3)
 
 __all__ = ["mc_interface", "mc_interface_many", "mc_adjoint", "mc_value_jacobian", "branching_eval", "branching_bvp", "wos_interface",
            "item_count", "PDDInterface", "PddError",
-           "release_workspace", "query_warnings", "library", "version", "param_layout", "jacobian_blocks"]
+           "release_workspace", "query_warnings", "library", "version", "param_layout", "jacobian_blocks",
+           "nonlinear"]
 
 
 class PddError(RuntimeError):

@@ -1,7 +1,10 @@
 """The polynomial-approximation driver for marked branching (Sec. 3.3):
 the fit against the coefficients the paper prints, the mapping to the
 branching form, the variance of the marks, and the whole rescaled
-construction against a PDE solve (on the oracle, no GPU)."""
+construction against a PDE solve (on the oracle, no GPU).  Every expected
+value here is computed without the driver: the reference quartic comes from
+numpy's own polynomial fit (`workloads.configs.cva_reference_quartic`), the
+branching coefficients and marks from their definitions."""
 import math
 import os
 
@@ -10,6 +13,7 @@ import pytest
 from scipy import integrate
 
 from paper_1705_03666_amd import nonlinear as NL
+from workloads import configs as CF
 from workloads.problem import BranchingProblem, const_fun, factor, make_fun
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -83,16 +87,48 @@ def _mol(rhs_u, psi, T, L=10.0, n=1601, sigma=1.0):
     return x, sol.y[:, -1]
 
 
+def _independent_marked_form(a, beta):
+    """alpha and q from their definitions: sum_i a_i u^i = beta (sum_i alpha_i u^i
+    - u) gives alpha_i = a_i / beta plus 1 at i = 1; q_i = |alpha_i| / sum |alpha|."""
+    alpha = np.zeros(5)
+    alpha[:len(a)] = np.asarray(a) / beta
+    alpha[1] += 1.0
+    return alpha, np.abs(alpha) / np.abs(alpha).sum()
+
+
+@pytest.mark.parametrize("c,psi_sup", [(1.0, 2.0), (0.7, 1.0), (2.5, 3.0)])
+def test_driver_alpha_and_q_match_an_independent_fit(c, psi_sup):
+    """The driver's branching coefficients and marks for f(u) = c (max(u, 0) - u)
+    rescaled by psi_sup equal those derived from numpy's fit of the same
+    rescaled nonlinearity (a wrong rescaling, an alpha_1 without its +1 or
+    unnormalised marks fail)."""
+    f = lambda u: c * (np.maximum(u, 0.0) - u)
+    psi = make_fun([(psi_sup, [factor("tanh", 0)])])
+    prob, scale = NL.rescaled_problem(1, 1.0, f, psi, psi_sup, 0.3, beta=c)
+    assert scale == psi_sup
+    a = CF.cva_reference_quartic(f, psi_sup)
+    alpha, q = _independent_marked_form(a, c)
+    assert np.allclose(prob.alpha, alpha, rtol=0, atol=1e-12), (prob.alpha, alpha)
+    assert np.allclose(prob.q, q, rtol=0, atol=1e-12), (prob.q, q)
+    assert np.allclose(prob.psi.coef, np.asarray(psi.coef) / psi_sup, rtol=1e-15)
+    # the reference fit itself against the printed quartic (c = 1 is max(v, 0) - v)
+    if c == 1.0:
+        printed = _printed_cva()
+        assert np.all(np.abs(alpha - printed) < 5e-5), alpha
+
+
 def test_rescaled_cva_problem_matches_a_pde_solve(orc):
     """u_t = 0.5 u_xx + c (max(u, 0) - u), psi = 2 tanh(x): the driver divides by
     psi_sup = 2, fits the rescaled nonlinearity, and the oracle estimate times 2
-    matches a method-of-lines solve of the PDE with that polynomial nonlinearity
-    (the approximation of max(u, 0) itself is a modelling choice of Sec. 3.3)."""
+    matches a method-of-lines solve of the PDE whose polynomial nonlinearity
+    comes from the independent fit (the approximation of max(u, 0) itself is a
+    modelling choice of Sec. 3.3)."""
     c, T, s = 1.0, 0.5, 2.0
     psi = make_fun([(2.0, [factor("tanh", 0)])])
-    prob, scale = NL.rescaled_problem(1, 1.0, lambda u: c * (np.maximum(u, 0.0) - u), psi, s, T, beta=c)
+    f = lambda u: c * (np.maximum(u, 0.0) - u)
+    prob, scale = NL.rescaled_problem(1, 1.0, f, psi, s, T, beta=c)
     assert scale == s
-    a = NL.fit_polynomial(lambda v: c * (np.maximum(s * v, 0.0) - s * v) / s)
+    a = CF.cva_reference_quartic(f, s)
     x, u = _mol(lambda u: s * sum(a[i] * (u / s) ** i for i in range(len(a))), lambda x: 2.0 * np.tanh(x), T)
     pts = np.array([[-1.0], [-0.2], [0.4], [1.5]])
     ref = np.interp(pts[:, 0], x, u)

@@ -315,6 +315,42 @@ def test_walk_degenerate_cases(orc):
     assert r["censored"][2] == 5 and r["steps"][2] == 15
 
 
+def test_censored_path_value_at_the_nearest_boundary_point(orc):
+    """A path still inside D when max_steps is reached (R12) takes
+    phi = g(P X) Y + Z, P the nearest boundary point: for a box the nearest
+    face (only that coordinate moves), for a ball the radial point.  With
+    sigma = 1e-12 a path does not move measurably in 3 steps, so P X is the
+    hand-computed point below, and with constant c, f the left-point sums are
+    Y = exp(-3 c dt), Z = f dt (1 + exp(-c dt) + exp(-2 c dt)).  Leaving an
+    interior point unprojected, picking the wrong face or scaling the wrong
+    way misses by more than 1 in every case."""
+    dt, c, f = 0.1, 0.5, 2.0
+    Y = math.exp(-3 * c * dt)
+    Z = f * dt * (1.0 + math.exp(-c * dt) + math.exp(-2 * c * dt))
+    cases = [
+        # (domain, g as a graded-lex linear polynomial, node, nearest boundary point)
+        (box((0.0,), (1.0,)), [3.0, 7.0], (0.3,), (0.0,)),
+        (box((0.0,), (1.0,)), [3.0, 7.0], (0.8,), (1.0,)),
+        (box((0, 0), (1, 1)), [0.0, 10.0, 100.0], (0.2, 0.5), (0.0, 0.5)),
+        (box((0, 0), (1, 1)), [0.0, 10.0, 100.0], (0.5, 0.9), (0.5, 1.0)),
+        (box((0, 0), (1, 1)), [0.0, 10.0, 100.0], (0.93, 0.4), (1.0, 0.4)),
+        (box((0, 0), (1, 1)), [0.0, 10.0, 100.0], (0.5, 0.03), (0.5, 0.0)),
+        (box((-1, 0, 0), (2, 1, 3)), [0.0, 1.0, 10.0, 100.0], (0.5, 0.5, 0.1), (0.5, 0.5, 0.0)),
+        (box((-1, 0, 0), (2, 1, 3)), [0.0, 1.0, 10.0, 100.0], (1.7, 0.5, 1.5), (2.0, 0.5, 1.5)),
+        (ball(2, 2.0, (1.0, -1.0)), [0.0, 10.0, 100.0], (1.3, -0.6), (2.2, 0.6)),
+        (ball(3), [0.0, 1.0, 10.0, 100.0], (0.1, 0.2, -0.2), (1 / 3, 2 / 3, -2 / 3)),
+    ]
+    for dom, gpoly, node, proj in cases:
+        d = dom.ndim
+        g = make_fun([], poly_degree=1, poly=gpoly)
+        prob = LinearProblem(dom, 1e-12, [zero_fun()] * d, const_fun(c), const_fun(f), g)
+        r = orc.walk(prob, np.array([node]), np.array([6]), dt, 2, max_steps=3, dump=True)
+        g_at = gpoly[0] + sum(gpoly[1 + k] * proj[k] for k in range(d))
+        want = g_at * Y + Z
+        assert r["censored"][0] == 6 and r["steps"][0] == 18, (node, r["censored"], r["steps"])
+        assert np.allclose(r["phi"], want, rtol=0, atol=1e-8), (node, r["phi"][0], want)
+
+
 def test_welford_matches_two_pass(orc):
     w = CF.c1(scale=0.05)
     r = orc.walk(w.problem, w.nodes, w.paths, w.dt, 0, dump=True)

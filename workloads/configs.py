@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass
-from typing import Dict, List, Optional
+from typing import Callable, Dict, List, Optional
 
 import numpy as np
 
@@ -342,9 +342,18 @@ def c6(scale: float = 1.0, seed: int = 0, n_points: int = 1024, dt: float = 1e-3
 # --------------------------------------------------------------------------- C7
 @dataclass
 class CvaWorkload:
+    """Inputs of the CVA construction of Sec. 3.3: u_t = 0.5 sigma^2 u_xx + f(u),
+    u(., 0) = psi with |psi| <= psi_sup, at horizon T, branching rate beta.
+    The branching problem itself (rescaling by psi_sup, polynomial fit of the
+    rescaled nonlinearity, marks) is built by the library's host-side driver;
+    this record holds only what goes into it."""
     name: str
-    problem: BranchingProblem
-    scale: float
+    sigma: float
+    nonlinearity: Callable[[np.ndarray], np.ndarray]
+    psi: Fun
+    psi_sup: float
+    T: float
+    beta: float
     points: np.ndarray
     trees: int
     seed: int
@@ -359,33 +368,44 @@ def c7_nonlinearity(u):
 def c7(scale: float = 1.0, seed: int = 0, n_points: int = 1024) -> CvaWorkload:
     """The CVA construction of Sec. 3.3 in one dimension (the paper leaves the
     operator, payoff and horizon open; chosen here): u_t = 0.5 u_xx + f(u),
-    f = max(u, 0) - u, payoff psi = 2 tanh(x) (bounded, signed), T = 0.5.
-    u / 2 is the rescaled unknown, its nonlinearity is fitted by a quartic on
-    [-1, 1] (Sec. 3.3's least-squares fit), marks q ~ |alpha|; 1024 points
-    evenly spaced in [-3, 3], 1e5 trees each."""
-    from paper_1705_03666_amd.nonlinear import rescaled_problem
+    f = max(u, 0) - u, payoff psi = 2 tanh(x) (bounded, signed, psi_sup = 2),
+    T = 0.5, beta = 1; 1024 points evenly spaced in [-3, 3], 1e5 trees each."""
     psi = make_fun([(2.0, [factor("tanh", 0)])])
-    prob, s = rescaled_problem(1, 1.0, c7_nonlinearity, psi, 2.0, 0.5, beta=1.0)
     pts = np.linspace(-3.0, 3.0, n_points).reshape(-1, 1)
-    return CvaWorkload("C7 CVA marked branching", prob, s, pts, _budget(100_000, scale), seed)
+    return CvaWorkload("C7 CVA marked branching", 1.0, c7_nonlinearity, psi, 2.0, 0.5, 1.0, pts,
+                       _budget(100_000, scale), seed)
+
+
+def cva_reference_quartic(f: Callable[[np.ndarray], np.ndarray], psi_sup: float, n: int = 2001) -> np.ndarray:
+    """Coefficients (increasing powers) of the quartic that Sec. 3.3's
+    approximation step assigns to the rescaled nonlinearity
+    v -> f(psi_sup v) / psi_sup on [-1, 1]: discrete least squares on n equally
+    spaced points (the reading that reproduces every digit the paper prints for
+    max(v, 0)), computed with numpy's own polynomial fit.  Used only to build
+    reference solutions and expected values, independently of the library's
+    driver."""
+    from numpy.polynomial import polynomial as NP
+    v = np.linspace(-1.0, 1.0, n)
+    return NP.polyfit(v, np.asarray(f(psi_sup * v), dtype=np.float64) / psi_sup, 4)
 
 
 def c7_reference(xq, L: float = 12.0, n: int = 2401) -> np.ndarray:
     """Method-of-lines solution (second-order differences, stiff BDF) at T of
     the PDE the C7 estimator represents: u_t = 0.5 u_xx + s P(u / s), P the
-    fitted quartic of the rescaled nonlinearity, s = 2, u(., 0) = 2 tanh x."""
+    quartic of `cva_reference_quartic`, s = psi_sup = 2, u(., 0) = 2 tanh x."""
     from scipy import integrate
     from scipy.sparse import diags
-    from paper_1705_03666_amd.nonlinear import fit_polynomial
-    s, T = 2.0, 0.5
-    a = fit_polynomial(lambda v: c7_nonlinearity(s * v) / s)
+    w = c7(scale=1e-5, n_points=1)
+    s, T = w.psi_sup, w.T
+    a = cva_reference_quartic(w.nonlinearity, s)
     x = np.linspace(-L, L, n)
     h = x[1] - x[0]
 
     def rhs(t, u):
         du = np.zeros_like(u)
         v = u[1:-1] / s
-        du[1:-1] = 0.5 * (u[2:] - 2 * u[1:-1] + u[:-2]) / h ** 2 + s * sum(a[i] * v ** i for i in range(len(a)))
+        du[1:-1] = 0.5 * w.sigma ** 2 * (u[2:] - 2 * u[1:-1] + u[:-2]) / h ** 2 + s * sum(
+            a[i] * v ** i for i in range(len(a)))
         return du
 
     sol = integrate.solve_ivp(rhs, (0, T), 2.0 * np.tanh(x), method="BDF", rtol=1e-10, atol=1e-12,
