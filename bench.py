@@ -187,14 +187,14 @@ def run(args):
 
     def step():
         # forward + adjoint in one pass: values and per-node Jacobian, then
-        # the loss gradient J^T w with w = dL/du = 2 (u - d).  The library
-        # launches on torch's current stream, so these events bracket the
-        # value+Jacobian graph (walk kernel + its small reductions).
+        # the misfit loss sum (u - d)^2 and its gradient J^T 2 (u - d), both in
+        # the library.  It launches on torch's current stream, so these events
+        # bracket the value+Jacobian graph (walk kernel + its small reductions).
         ev_vj[0].record()
         r = pdd.mc_value_jacobian(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_a)
         ev_vj[1].record()
-        grad = (2.0 * (r["mean"] - d)) @ r["jac"]
-        return r, grad
+        m = pdd.misfit_gradient(r, d)
+        return r, m["grad"]
 
     def step_recompute():
         r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_f)
@@ -321,7 +321,8 @@ def run(args):
                    "nodes": n, "paths_per_node": int(paths[0]), "dt": w.dt, "seed": w.seed,
                    "schedule": "persistent+hipGraph", "accumulation": "f64",
                    "tuned_forward": sched_f, "tuned_adjoint": sched_a},
-        "step": "one value+Jacobian pass (pdd_mc_value_jacobian) + J^T w",
+        "step": "one value+Jacobian pass (pdd_mc_value_jacobian) + misfit loss and gradient J^T w "
+                "(pdd_misfit_gradient)",
         "forward_path_steps_per_s": fwd_ps_s,
         "adjoint_path_steps_per_s": adj_ps_s,
         "forward_plus_recomputing_adjoint_path_steps_per_s": ps / (fwd_s + adj_s),
@@ -590,6 +591,24 @@ def cpu_baseline(w, seconds, pdd, coefs, dev):
     return base, err
 
 
+def reap_children(timeout: float = 10.0) -> int:
+    """Waits for (then ends) every child process this run started, so none
+    outlives it; returns how many were still there.  The only children the
+    bench itself starts are short host commands run to completion (uname for
+    the CPU name, amd-smi when sysfs has no clock table)."""
+    try:
+        import psutil
+    except ImportError:
+        return -1
+    kids = psutil.Process().children(recursive=True)
+    if kids:
+        _, alive = psutil.wait_procs(kids, timeout=timeout)
+        for p in alive:
+            p.terminate()
+        psutil.wait_procs(alive, timeout=timeout)
+    return len(kids)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -637,6 +656,7 @@ def main():
         run_only(args.only, args.scale)
         return
     out = run(args)
+    out["child_processes_at_exit"] = reap_children()
     print(json.dumps(out), flush=True)
 
 

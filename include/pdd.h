@@ -39,11 +39,25 @@
  *    "host" pointers host memory.  The caller owns every pointer; the library
  *    never frees caller memory and keeps no caller pointer after the call
  *    returns, except that device arrays must stay valid until the enqueued
- *    work finishes.  Scratch memory is allocated stream-ordered per call, or
- *    held by a cached launch plan until pdd_release_workspace().
- *  - Results are a pure function of (problem, nodes, budgets, dt, seed,
- *    precision, rng layout): independent of the schedule and bitwise
- *    reproducible run to run.
+ *    work finishes.
+ *  - Scratch memory.  A call's scratch (tables, work queue, per-item
+ *    partials, branching stacks) is taken stream-ordered from a memory pool
+ *    of the library's own, which keeps up to 2 GiB mapped between calls.  The
+ *    graph schedule (PDD_SCHED_AUTO / PDD_SCHED_PERSISTENT_GRAPH) instead
+ *    keeps a captured launch plan with its own scratch per (problem
+ *    structure, budgets, step, seed, options, outputs requested, stream); at
+ *    most 16 plans are cached, the least recently used one is dropped once
+ *    its last launch has finished.  A plan does not depend on the caller's
+ *    buffers (nodes, coefficient arrays, outputs, weights): they are handed
+ *    to every replay.  pdd_release_workspace() frees the plans and returns
+ *    the pool's memory.
+ *  - Per-path values and step counts are a pure function of (problem, node,
+ *    path index, dt, seed, precision, rng layout): independent of the
+ *    schedule, the work-item size and the device.  Node statistics merge
+ *    per-item partials in a fixed order, so they are bitwise reproducible for
+ *    a fixed schedule on a fixed device; across schedules or devices the item
+ *    boundaries move and the FP64 merges round differently (equal to about
+ *    1e-13 relative).
  *  - No exception or abort crosses the ABI.
  */
 #ifndef PDD_H
@@ -179,7 +193,9 @@ typedef struct {
   int32_t precision;      /* pdd_precision */
   int32_t rng_layout;     /* pdd_rng_layout; PDD_FP32_STEP requires QUAD24 */
   int64_t max_steps;      /* censoring cap per path; 0 = ceil(100/dt) */
-  double* dump_phi;       /* device, optional [sum(paths)]: per-path value, node-major */
+  double* dump_phi;       /* device, optional [sum(paths)]: per-path value, node-major (every linear
+                             entry point except the plain adjoint; a call with dumps is never captured
+                             into a cached graph) */
   int64_t* dump_steps;    /* device, optional [sum(paths)]: per-path step (segment) count */
   int32_t schedule;       /* pdd_schedule */
   int32_t chunk_paths;    /* paths per large work item (about the last eighth of each node's paths
@@ -325,6 +341,35 @@ pdd_status pdd_mc_value_jacobian(const pdd_linear_problem* problem, const double
  * -1 if the problem is malformed. */
 int64_t pdd_param_count(const pdd_linear_problem* problem);
 
+/* grad = J^T w: grad[k] = sum_i w_i jac[i][k] for a Jacobian from
+ * pdd_mc_value_jacobian, i.e. the gradient of sum_i w_i u_i with respect to the
+ * coefficients (the same quantity pdd_mc_adjoint accumulates, formed without
+ * re-simulating the paths).  Summed in a fixed order (bitwise reproducible).
+ *  jac_dev: device [n_nodes][jac_ld] FP64; w_dev: device [n_nodes];
+ *  grad_dev: device [n_params], overwritten.  n_params <= jac_ld.
+ * Errors: PDD_ERR_INVALID_ARG (sizes, non-device pointers), PDD_ERR_HIP. */
+pdd_status pdd_jacobian_apply(const double* jac_dev, int64_t n_nodes, int64_t jac_ld, int64_t n_params,
+                              const double* w_dev, double* grad_dev, void* hip_stream);
+
+/* Data-misfit loss of the interface values and its gradient (the loss the
+ * adjoint serves: a least-squares fit of the coefficients to data at the
+ * nodes): loss = sum_i (u_i - d_i)^2 with u_i = stats_dev[i].mean, and
+ * grad = J^T w with w_i = 2 (u_i - d_i), the exact gradient of the loss at
+ * the estimate with the same samples.
+ *  stats_dev: device [n_nodes] (from pdd_mc_value_jacobian); data_dev: device
+ *  [n_nodes]; jac_dev: device [n_nodes][jac_ld]; loss_dev: device, one double;
+ *  grad_dev: device [n_params]; both overwritten.
+ * Errors as pdd_jacobian_apply. */
+pdd_status pdd_misfit_gradient(const pdd_node_stat* stats_dev, const double* data_dev, int64_t n_nodes,
+                               const double* jac_dev, int64_t jac_ld, int64_t n_params, double* loss_dev,
+                               double* grad_dev, void* hip_stream);
+
+/* Sample variance and standard error of every node (the unbiased estimator:
+ * var = m2 / (n - 1), 0 for n < 2; se = sqrt(var / n), 0 for n = 0).
+ *  stats_dev: device [n_nodes]; var_dev, se_dev: device [n_nodes] or NULL. */
+pdd_status pdd_node_moments(const pdd_node_stat* stats_dev, int64_t n_nodes, double* var_dev, double* se_dev,
+                            void* hip_stream);
+
 /* Synchronizes hip_stream and reports (then clears) the censored-path and
  * redrawn-tree counters of the work enqueued since the last query:
  * PDD_WARN_CENSORED / PDD_WARN_REDRAWN if non-zero, else PDD_OK. */
@@ -336,8 +381,12 @@ pdd_status pdd_query_warnings(void* hip_stream, int64_t* censored_out, int64_t* 
  * and the device's compute units).  Negative pdd_status on invalid input. */
 int64_t pdd_item_count(int64_t n_nodes, const int64_t* paths_host, const pdd_options* options);
 
-/* Frees cached launch plans and their device memory (synchronizes the device). */
+/* Frees cached launch plans and their device memory, and returns the memory
+ * the library's pools keep (synchronizes the device). */
 pdd_status pdd_release_workspace(void);
+
+/* Number of cached graph launch plans (at most 16). */
+int64_t pdd_cached_plan_count(void);
 
 const char* pdd_status_string(pdd_status status);
 const char* pdd_last_error(void);

@@ -102,6 +102,8 @@ def lib():
                               C.c_int64, C.c_int, C.POINTER(OStat), dp, ip]
         L.orc_walk_adjoint.argtypes = [C.POINTER(OLinear), dp, C.c_int64, ip, C.c_double, C.c_uint64, C.c_int,
                                        C.c_int64, C.c_int, dp, dp, dp, dp, dp, dp, dp, C.POINTER(OStat)]
+        L.orc_walk_jacobian.argtypes = [C.POINTER(OLinear), dp, C.c_int64, ip, C.c_double, C.c_uint64, C.c_int,
+                                        C.c_int64, C.c_int, dp, dp, C.POINTER(OStat), ip]
         L.orc_branching_dfs.argtypes = [C.POINTER(OBranching), dp, C.c_int64, C.c_int64, C.c_uint64, C.c_int,
                                         C.c_int, C.POINTER(OStat), dp, ip, ip]
         L.orc_branching_alg31.argtypes = [C.POINTER(OBranching), dp, C.c_int64, C.c_int64, C.c_uint64, C.c_int,
@@ -315,6 +317,34 @@ def walk_adjoint(P: LinearProblem, nodes, paths, dt: float, seed: int, w, layout
            for k, v in grads.items()}
     res["stats"] = _stats(out[:n])
     return res
+
+
+def walk_jacobian(P: LinearProblem, nodes, paths, dt: float, seed: int, layout: int = PAIR52,
+                  max_steps: Optional[int] = None, n_threads: Optional[int] = None, node_ids=None,
+                  boundary_shift: float = 0.0) -> dict:
+    """Per-node Jacobian d mean_i / d theta (columns: g coef, g poly, f coef,
+    f poly, c coef, c poly) and the standard error of every entry, from the
+    spread of the per-path derivatives over the node's paths.  node_ids as in
+    walk()."""
+    keep = _Keep()
+    o = _olinear(P, keep, boundary_shift)
+    nodes = keep.arr(nodes, np.float64)
+    paths = keep.arr(paths, np.int64)
+    n = len(paths)
+    npar = sum(F.n_terms + F.n_mono(P.ndim) for F in (P.g, P.f, P.c))
+    mean = np.zeros((max(1, n), max(1, npar)))
+    m2 = np.zeros((max(1, n), max(1, npar)))
+    out = (OStat * max(1, n))()
+    rc = lib().orc_walk_jacobian(C.byref(o), _ptr(nodes, C.c_double), n, _ptr(paths, C.c_int64), dt, seed, layout,
+                                 default_max_steps(dt) if max_steps is None else max_steps,
+                                 default_threads() if n_threads is None else n_threads,
+                                 _ptr(mean, C.c_double), _ptr(m2, C.c_double), out,
+                                 _ptr(keep.arr(node_ids, np.int64), C.c_int64) if node_ids is not None else None)
+    if rc != 0:
+        raise ValueError("oracle rejected the Jacobian arguments")
+    N = paths[:, None].astype(np.float64)
+    var = np.where(N > 1, m2[:n, :npar] / np.maximum(N - 1, 1), 0.0)
+    return {"jac": mean[:n, :npar], "jac_se": np.sqrt(var / np.maximum(N, 1)), "stats": _stats(out[:n])}
 
 
 def _obranching(B: BranchingProblem, keep: _Keep) -> OBranching:

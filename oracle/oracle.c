@@ -375,6 +375,7 @@ typedef struct {
   double* grad_rows;   /* [n_nodes][n_grad] */
   int n_grad;
   const int64_t* node_ids; /* counter word 3 per node (NULL: the node's position) */
+  void* extra;             /* per-function outputs (orc_walk_jacobian) */
 } walk_ctx;
 
 static uint32_t node_id(const walk_ctx* C, int64_t i) { return (uint32_t)(C->node_ids ? C->node_ids[i] : i); }
@@ -561,6 +562,68 @@ int orc_walk_adjoint(const orc_linear* P, const double* nodes, int64_t n_nodes, 
     for (int k = 0; k < P->c.n_mono; ++k) if (dc_mono) dc_mono[k] += row[ng + nf + P->c.n_terms + k];
   }
   free(C.grad_rows);
+  return 0;
+}
+
+/* Per-node Jacobian with the spread of the per-path derivatives.  The
+ * derivative of one path value is the one the adjoint sums (exact derivative
+ * of the discrete estimator): G_k(X_tau) Y_N for a coefficient of g, F_j for
+ * one of f, -g(X_tau) Y_N S_j - A_j for one of c.  Each is pushed into its
+ * own Welford accumulator, in path order. */
+typedef struct {
+  double* mean;   /* [n_nodes][n_grad] */
+  double* m2;
+} jac_out;
+
+static void jacobian_node(void* vctx, int64_t i, int worker) {
+  (void)worker;
+  walk_ctx* C = (walk_ctx*)vctx;
+  const jac_out* J = (const jac_out*)C->extra;
+  const orc_linear* P = C->P;
+  int d = P->dom.dim;
+  int ng = fun_params(&P->g), nf = fun_params(&P->f), nc = fun_params(&P->c);
+  int np = ng + nf + nc;
+  double* mean = &J->mean[i * np];
+  double* m2 = &J->m2[i * np];
+  double* Fj = (double*)calloc((size_t)(nf + 2 * nc + np + 1), sizeof(double));
+  tangents tg;
+  tg.nf = nf; tg.nc = nc; tg.F = Fj; tg.S = Fj + nf; tg.A = Fj + nf + nc;
+  double* dphi = Fj + nf + 2 * nc;
+  orc_stat s = {0.0, 0.0, 0, 0, 0};
+  for (int k = 0; k < np; ++k) { mean[k] = 0.0; m2[k] = 0.0; }
+  for (int64_t p = 0; p < C->paths[i]; ++p) {
+    path_result R = walk_path(P, &C->nodes[i * d], C->key, C->layout, node_id(C, i), (uint32_t)p,
+                              C->dt, C->max_steps, &tg);
+    welford_push(&s, R.phi);
+    s.steps += R.steps;
+    s.censored += R.censored;
+    double gval = orc_fun_eval(&P->g, R.xexit);
+    for (int k = 0; k < ng; ++k) dphi[k] = param_basis(&P->g, k, R.xexit) * R.Y;
+    for (int j = 0; j < nf; ++j) dphi[ng + j] = tg.F[j];
+    for (int j = 0; j < nc; ++j) dphi[ng + nf + j] = -gval * R.Y * tg.S[j] - tg.A[j];
+    double cnt = (double)(p + 1);
+    for (int k = 0; k < np; ++k) {
+      double delta = dphi[k] - mean[k];
+      mean[k] += delta / cnt;
+      m2[k] += delta * (dphi[k] - mean[k]);
+    }
+  }
+  if (C->out) C->out[i] = s;
+  free(Fj);
+}
+
+int orc_walk_jacobian(const orc_linear* P, const double* nodes, int64_t n_nodes, const int64_t* paths,
+                      double dt, uint64_t seed, int layout, int64_t max_steps, int n_threads,
+                      double* jac_mean, double* jac_m2, orc_stat* out, const int64_t* node_ids) {
+  if (P->dom.kind == ORC_FREE || P->dom.dim < 1 || P->dom.dim > 3 || !(dt > 0.0)) return -1;
+  walk_ctx C;
+  memset(&C, 0, sizeof(C));
+  C.P = P; C.nodes = nodes; C.paths = paths; C.dt = dt; C.layout = layout;
+  C.max_steps = max_steps; C.out = out; C.node_ids = node_ids;
+  make_key(seed, C.key);
+  jac_out J = {jac_mean, jac_m2};
+  C.extra = &J;
+  run_pool(n_threads, n_nodes, jacobian_node, &C);
   return 0;
 }
 

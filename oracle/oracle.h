@@ -137,6 +137,16 @@ int orc_walk_adjoint(const orc_linear* P, const double* nodes, int64_t n_nodes, 
                      double* dg_coef, double* dg_mono, double* df_coef, double* df_mono,
                      double* dc_coef, double* dc_mono, orc_stat* out);
 
+/* per-node Jacobian of the sample mean with respect to the coefficient
+   arrays, with the spread of the per-path derivatives: for node i and
+   parameter k (columns [g coef | g mono | f coef | f mono | c coef | c mono]),
+   the Welford mean and sum of squared deviations over the node's paths of
+   d phi_p / d theta_k.  jac_mean and jac_m2 are [n_nodes][n_params]
+   (n_params = all coefficients of g, f and c); node_ids as for orc_walk. */
+int orc_walk_jacobian(const orc_linear* P, const double* nodes, int64_t n_nodes, const int64_t* paths,
+                      double dt, uint64_t seed, int layout, int64_t max_steps, int n_threads,
+                      double* jac_mean, double* jac_m2, orc_stat* out, const int64_t* node_ids);
+
 /* ---- branching (Sec. 3.1-3.2) ---- */
 int orc_branching_dfs(const orc_branching* B, const double* points, int64_t n_points,
                       int64_t trees, uint64_t seed, int layout, int n_threads,

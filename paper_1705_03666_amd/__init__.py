@@ -30,7 +30,7 @@ from . import nonlinear  # noqa: F401  (host-side driver of Sec. 3.3)
 __all__ = ["mc_interface", "mc_interface_many", "mc_adjoint", "mc_value_jacobian", "branching_eval", "branching_bvp", "wos_interface",
            "item_count", "PDDInterface", "PddError",
            "release_workspace", "query_warnings", "library", "version", "param_layout", "jacobian_blocks",
-           "nonlinear"]
+           "jacobian_apply", "misfit_gradient", "cached_plan_count", "nonlinear"]
 
 
 class PddError(RuntimeError):
@@ -169,13 +169,18 @@ def _linear(P, keep: _Keep, coefs: Optional[Dict[str, torch.Tensor]] = None) -> 
 
 
 def _stats(raw: torch.Tensor) -> Dict[str, torch.Tensor]:
-    ints = raw[:, 2:].contiguous().view(torch.int64)
-    n = ints[:, 0]
-    mean, m2 = raw[:, 0], raw[:, 1]
-    nf = n.to(torch.float64)
-    var = torch.where(n > 1, m2 / torch.clamp(nf - 1.0, min=1.0), torch.zeros_like(m2))
-    return {"mean": mean, "m2": m2, "n": n, "steps": ints[:, 1], "censored": ints[:, 2], "var": var,
-            "se": torch.sqrt(var / torch.clamp(nf, min=1.0))}
+    """Views of a pdd_node_stat array [n, 5] (FP64 words), plus the variance and
+    standard error computed by the library (pdd_node_moments)."""
+    raw = raw.contiguous()
+    n = raw.shape[0]
+    ints = raw[:, 2:].view(torch.int64)
+    var = torch.empty(max(n, 1), dtype=torch.float64, device=raw.device)
+    se = torch.empty(max(n, 1), dtype=torch.float64, device=raw.device)
+    if n:
+        _check(library().pdd_node_moments(raw.data_ptr(), n, var.data_ptr(), se.data_ptr(), _stream_handle()),
+               "pdd_node_moments")
+    return {"mean": raw[:, 0], "m2": raw[:, 1], "n": ints[:, 0], "steps": ints[:, 1], "censored": ints[:, 2],
+            "var": var[:n], "se": se[:n], "_raw": raw}
 
 
 def _nodes_tensor(nodes, ndim: int) -> torch.Tensor:
@@ -302,14 +307,24 @@ def mc_interface_many(calls, max_streams: int = 8) -> list:
     return out
 
 
+def _dumps(dump: bool, paths: np.ndarray):
+    if not dump:
+        return None, None
+    total = int(paths.sum())
+    return (torch.empty(max(total, 1), dtype=torch.float64, device="cuda"),
+            torch.empty(max(total, 1), dtype=torch.int64, device="cuda"))
+
+
 def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = "fp32",
                layout: Optional[str] = None, max_steps: int = 0, schedule: str = "auto", chunk_paths: int = 0,
                blocks_per_cu: int = 0, refill_groups: int = 0, coefs: Optional[Dict[str, torch.Tensor]] = None,
                with_stats: bool = False, boundary_correction: bool = False,
-               specialize: str = "auto") -> Dict[str, torch.Tensor]:
+               specialize: str = "auto", dump: bool = False) -> Dict[str, torch.Tensor]:
     """Gradient of sum_i w_i u_i with respect to the coefficient arrays of g, f
     and c (pdd_mc_adjoint).  Returns device tensors g_coef, g_poly, f_coef,
-    f_poly, c_coef, c_poly (and the per-node statistics with with_stats)."""
+    f_poly, c_coef, c_poly (and the per-node statistics with with_stats; with
+    dump=True the per-path values `phi` and step counts `path_steps` of the
+    adjoint kernel's own walk, node-major)."""
     _need_gpu()
     keep = _Keep()
     p = _linear(problem, keep, coefs)
@@ -336,7 +351,8 @@ def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = 
         grads[name + "_coef"] = grads[name + "_coef"][:T]
         grads[name + "_poly"] = grads[name + "_poly"][:M]
     raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda") if with_stats else None
-    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups,
+    dphi, dst = _dumps(dump, ph)
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups, dphi, dst,
                  boundary_correction=boundary_correction, specialize=specialize)
     st = library().pdd_mc_adjoint(C.byref(p), nt.data_ptr() if n else None, n,
                                   ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt), int(seed) & (2 ** 64 - 1),
@@ -345,6 +361,9 @@ def mc_adjoint(problem, nodes, paths, dt: float, seed: int, w, precision: str = 
     _check(st, "pdd_mc_adjoint")
     if with_stats:
         grads["stats"] = _stats(raw[:n])
+    if dump:
+        total = int(ph.sum())
+        grads["phi"], grads["path_steps"] = dphi[:total], dst[:total]
     grads["_keep"] = (keep, wt)
     return grads
 
@@ -365,10 +384,12 @@ def mc_value_jacobian(problem, nodes, paths, dt: float, seed: int = 0, precision
                       layout: Optional[str] = None, max_steps: int = 0, schedule: str = "auto", chunk_paths: int = 0,
                       blocks_per_cu: int = 0, refill_groups: int = 0,
                       coefs: Optional[Dict[str, torch.Tensor]] = None,
-                      boundary_correction: bool = False, specialize: str = "auto") -> Dict[str, torch.Tensor]:
+                      boundary_correction: bool = False, specialize: str = "auto",
+                      dump: bool = False) -> Dict[str, torch.Tensor]:
     """Per-node statistics and the Jacobian d mean_i / d coefficients in one
     pass (pdd_mc_value_jacobian).  Returns the statistics of mc_interface plus
-    `jac` [n, n_params] (column blocks in `param_layout(problem)` order)."""
+    `jac` [n, n_params] (column blocks in `param_layout(problem)` order); with
+    dump=True also the per-path values `phi` and step counts `path_steps`."""
     _need_gpu()
     keep = _Keep()
     p = _linear(problem, keep, coefs)
@@ -382,7 +403,8 @@ def mc_value_jacobian(problem, nodes, paths, dt: float, seed: int = 0, precision
         raise PddError("pdd_param_count rejected the problem")
     raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
     jac = torch.zeros((max(n, 1), max(npar, 1)), dtype=torch.float64, device="cuda")
-    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups,
+    dphi, dst = _dumps(dump, ph)
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups, dphi, dst,
                  boundary_correction=boundary_correction, specialize=specialize)
     st = library().pdd_mc_value_jacobian(C.byref(p), nt.data_ptr() if n else None, n,
                                          ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt),
@@ -391,8 +413,49 @@ def mc_value_jacobian(problem, nodes, paths, dt: float, seed: int = 0, precision
     _check(st, "pdd_mc_value_jacobian")
     res = _stats(raw[:n])
     res["jac"] = jac[:n, :npar]
+    res["jac_ld"] = max(npar, 1)
+    if dump:
+        total = int(ph.sum())
+        res["phi"], res["path_steps"] = dphi[:total], dst[:total]
     res["_keep"] = keep
     return res
+
+
+def jacobian_apply(jac: torch.Tensor, w) -> torch.Tensor:
+    """J^T w on the device (pdd_jacobian_apply): the gradient of sum_i w_i u_i
+    from a Jacobian of mc_value_jacobian, summed in a fixed order."""
+    _need_gpu()
+    if not (jac.is_cuda and jac.dtype == torch.float64 and jac.dim() == 2 and jac.stride(1) == 1):
+        raise ValueError("jac must be a float64 CUDA matrix with unit column stride")
+    n, npar = jac.shape
+    wt = _dev_f64(w).reshape(-1).contiguous()
+    if wt.numel() != n:
+        raise ValueError("w must have one entry per Jacobian row")
+    grad = torch.empty(max(npar, 1), dtype=torch.float64, device="cuda")
+    st = library().pdd_jacobian_apply(jac.data_ptr() if n else None, n, max(jac.stride(0), npar), npar,
+                                      wt.data_ptr() if n else None, grad.data_ptr(), _stream_handle())
+    _check(st, "pdd_jacobian_apply")
+    return grad[:npar]
+
+
+def misfit_gradient(result: Dict[str, torch.Tensor], data) -> Dict[str, torch.Tensor]:
+    """Least-squares misfit of the interface values to `data` and its gradient
+    with respect to the coefficients (pdd_misfit_gradient), from the result of
+    mc_value_jacobian: loss = sum_i (u_i - d_i)^2, grad = J^T 2 (u - d).
+    Returns {"loss": [1] tensor, "grad": [n_params] tensor}."""
+    _need_gpu()
+    raw, jac = result["_raw"], result["jac"]
+    n, npar = jac.shape
+    dt = _dev_f64(data).reshape(-1).contiguous()
+    if dt.numel() != n:
+        raise ValueError("data must have one entry per node")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty(max(npar, 1), dtype=torch.float64, device="cuda")
+    st = library().pdd_misfit_gradient(raw.data_ptr() if n else None, dt.data_ptr() if n else None, n,
+                                       jac.data_ptr() if n else None, int(result.get("jac_ld", npar)), npar,
+                                       loss.data_ptr(), grad.data_ptr(), _stream_handle())
+    _check(st, "pdd_misfit_gradient")
+    return {"loss": loss, "grad": grad[:npar], "_keep": dt}
 
 
 def jacobian_blocks(problem, jac: torch.Tensor) -> Dict[str, torch.Tensor]:
@@ -483,7 +546,7 @@ def branching_bvp(problem, boundary, points, trees: int, seed: int = 0, precisio
     st = library().pdd_branching_bvp(C.byref(b), C.byref(bd), pt.data_ptr() if n else None, n, int(trees),
                                      int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(), _stream_handle())
     _check(st, "pdd_branching_bvp")
-    res = {k: v.reshape(nt, n) for k, v in _stats(raw[:n * nt]).items()}
+    res = {k: (v if k == "_raw" else v.reshape(nt, n)) for k, v in _stats(raw[:n * nt]).items()}
     if dump:
         res["value"] = dv[:n * trees * nt].reshape(n, trees, nt)
         res["segments"] = ds[:n * trees].reshape(n, trees)
@@ -515,6 +578,11 @@ def query_warnings():
 
 def release_workspace():
     _check(library().pdd_release_workspace(), "pdd_release_workspace")
+
+
+def cached_plan_count() -> int:
+    """Graph launch plans the library currently caches (at most 16)."""
+    return int(library().pdd_cached_plan_count())
 
 
 _COEF_KEYS = ("g_coef", "g_poly", "f_coef", "f_poly", "c_coef", "c_poly")
@@ -559,7 +627,7 @@ class PDDInterface(torch.autograd.Function):
             if present:
                 coefs[k] = saved.pop(0)
         if ctx.jac is not None:
-            g = jacobian_blocks(ctx.problem, grad_u.detach().to(torch.float64) @ ctx.jac)
+            g = jacobian_blocks(ctx.problem, jacobian_apply(ctx.jac, grad_u.detach()))
         else:
             opts = {k: v for k, v in ctx.opts.items() if k not in ("dump",)}
             g = mc_adjoint(ctx.problem, ctx.nodes, ctx.paths, ctx.dt, ctx.seed, grad_u.detach(), coefs=coefs, **opts)

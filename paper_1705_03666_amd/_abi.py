@@ -17,8 +17,9 @@ PDD_SCHED_AUTO, PDD_SCHED_PERSISTENT, PDD_SCHED_PERSISTENT_GRAPH = 0, 1, 2
 
 EXPORTED = ["pdd_mc_interface", "pdd_wos_interface", "pdd_branching_eval", "pdd_branching_bvp", "pdd_mc_adjoint",
             "pdd_mc_value_jacobian", "pdd_item_count",
-            "pdd_param_count", "pdd_query_warnings", "pdd_release_workspace", "pdd_status_string", "pdd_last_error",
-            "pdd_version"]
+            "pdd_param_count", "pdd_jacobian_apply", "pdd_misfit_gradient", "pdd_node_moments",
+            "pdd_query_warnings", "pdd_release_workspace", "pdd_cached_plan_count", "pdd_status_string",
+            "pdd_last_error", "pdd_version"]
 
 
 class pdd_domain(C.Structure):
@@ -100,6 +101,16 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.pdd_item_count.restype = C.c_int64
     L.pdd_param_count.argtypes = [C.POINTER(pdd_linear_problem)]
     L.pdd_param_count.restype = C.c_int64
+    L.pdd_jacobian_apply.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
+    L.pdd_jacobian_apply.restype = C.c_int
+    L.pdd_misfit_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]
+    L.pdd_misfit_gradient.restype = C.c_int
+    L.pdd_node_moments.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.pdd_node_moments.restype = C.c_int
+    L.pdd_cached_plan_count.argtypes = []
+    L.pdd_cached_plan_count.restype = C.c_int64
     L.pdd_query_warnings.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.pdd_query_warnings.restype = C.c_int
     L.pdd_release_workspace.argtypes = []

@@ -41,21 +41,25 @@ pdd_status fail(pdd_status s, const std::string& msg) {
 // ----------------------------------------------------------------------------- call arenas
 // Every call takes its device buffers (tables, work queue, per-item
 // statistics, branching stack) as one stream-ordered arena.  They come from a
-// memory pool of the library's own, one per device, that keeps the pages it
-// has mapped after a free (no release threshold): a repeated call maps no new
-// memory.  The process's default pool is left as it is.  The pool holds at
-// most the largest set of arenas in flight at once, until the process ends.
+// memory pool of the library's own, one per device, that keeps up to
+// kPoolKeep bytes mapped after a free, so a repeated call maps no new memory
+// (the largest arena at the workloads here, the 1024-point branching spill
+// area, is about 0.8 GB); beyond that the pool returns memory at the next
+// synchronisation.  pdd_release_workspace() returns all of it.  The
+// process's default pool is left as it is.
+constexpr uint64_t kPoolKeep = 2ull << 30;
+std::mutex g_pool_mu;
+std::vector<hipMemPool_t> g_pools;  // by device ordinal
+
 hipError_t arena_alloc(void** p, size_t bytes, hipStream_t st) {
-  static std::mutex mu;
-  static std::vector<hipMemPool_t> pools;  // by device ordinal
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   hipMemPool_t pool = nullptr;
   {
-    std::lock_guard<std::mutex> lock(mu);
-    if ((int)pools.size() <= dev) pools.resize(dev + 1, nullptr);
-    if (pools[dev] == nullptr) {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if ((int)g_pools.size() <= dev) g_pools.resize(dev + 1, nullptr);
+    if (g_pools[dev] == nullptr) {
       hipMemPoolProps pr;
       std::memset(&pr, 0, sizeof(pr));
       pr.allocType = hipMemAllocationTypePinned;
@@ -64,17 +68,28 @@ hipError_t arena_alloc(void** p, size_t bytes, hipStream_t st) {
       hipMemPool_t np = nullptr;
       e = hipMemPoolCreate(&np, &pr);
       if (e != hipSuccess) return e;
-      uint64_t keep = UINT64_MAX;
+      uint64_t keep = kPoolKeep;
       e = hipMemPoolSetAttribute(np, hipMemPoolAttrReleaseThreshold, &keep);
       if (e != hipSuccess) {
         (void)hipMemPoolDestroy(np);
         return e;
       }
-      pools[dev] = np;
+      g_pools[dev] = np;
     }
-    pool = pools[dev];
+    pool = g_pools[dev];
   }
   return hipMallocFromPoolAsync(p, bytes, pool, st);
+}
+
+// Unmaps every page the library pools hold (call after a device synchronisation).
+hipError_t trim_pools() {
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  for (hipMemPool_t p : g_pools)
+    if (p != nullptr) {
+      hipError_t e = hipMemPoolTrimTo(p, 0);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
 }
 
 // ----------------------------------------------------------------------------- monomials
@@ -155,13 +170,26 @@ pdd_status check_device_ptr(const void* p, const char* name) {
 }
 
 // ----------------------------------------------------------------------------- tables
+// Where a staging job reads from: coefficient array `part` (0 = coef, 1 =
+// poly, 2 = none: zero padding, 3 = node coordinates) of function `fun`
+// (0..2 = b, 3 = c, 4 = f, 5 = g; -1 = not recorded).
+struct JobSource {
+  int fun, part;
+};
+
 struct Tables {
   std::vector<DevFactor> fac;
   std::vector<StageJob> jobs;
+  std::vector<JobSource> src;
   std::vector<int32_t> perm;
   int ncoef = 0;
 
-  DevFun add(const pdd_fun& F, int dim, int pad_deg, bool nested) {
+  void job(const StageJob& j, int fun, int part) {
+    jobs.push_back(j);
+    src.push_back(JobSource{fun, part});
+  }
+
+  DevFun add(const pdd_fun& F, int dim, int pad_deg, bool nested, int fun = -1) {
     DevFun d{};
     d.n_terms = F.n_terms;
     d.n_factors = F.n_terms > 0 ? F.n_factors : 0;
@@ -175,7 +203,7 @@ struct Tables {
     }
     d.coef_off = ncoef;
     if (F.n_terms > 0) {
-      jobs.push_back(StageJob{F.coef, ncoef, F.n_terms, -1, 0});
+      job(StageJob{F.coef, nullptr, ncoef, F.n_terms, -1, 0}, fun, 0);
       ncoef += F.n_terms;
     }
     d.poly_deg = -1;
@@ -187,15 +215,15 @@ struct Tables {
         auto p = nested_to_graded(dim, F.poly_degree);
         const int poff = (int)perm.size();
         perm.insert(perm.end(), p.begin(), p.end());
-        jobs.push_back(StageJob{F.poly, ncoef, own, poff, 0});
+        job(StageJob{F.poly, nullptr, ncoef, own, poff, 0}, fun, 1);
         d.poly_deg = F.poly_degree;
         d.n_mono = own;
         ncoef += own;
       } else {
         const int deg = std::max(pad_deg, F.poly_degree);
         const int tot = n_mono(dim, deg);
-        jobs.push_back(StageJob{F.poly, ncoef, own, -1, 0});
-        if (tot > own) jobs.push_back(StageJob{nullptr, ncoef + own, tot - own, -1, 0});
+        job(StageJob{F.poly, nullptr, ncoef, own, -1, 0}, fun, 1);
+        if (tot > own) job(StageJob{nullptr, nullptr, ncoef + own, tot - own, -1, 0}, fun, 2);
         d.poly_deg = deg;
         d.n_mono = tot;
         ncoef += tot;
@@ -250,12 +278,19 @@ pdd_status counters(unsigned long long** out) {
 // ----------------------------------------------------------------------------- plans
 // Everything a call enqueues, with its device buffers.  `enqueue` issues only
 // kernel launches (no memset, no copies), so it can be captured in a graph.
+// The caller's per-call pointers (node coordinates and coefficient arrays,
+// through the staging jobs; outputs and weights, through CallPtrs) are read
+// from the call block at the start of the arena, which is uploaded before
+// every launch: a graph plan is keyed on what shapes the launch, not on the
+// caller's buffers.
 struct Plan {
   int device = 0;
   void* arena = nullptr;
   bool owned = false;   // hipMalloc'd (graph plan) vs stream-ordered
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  hipEvent_t done = nullptr;   // recorded after every launch of a graph plan
+  uint64_t last_use = 0;
 
   LinearParams lp{};
   BranchParams bp{};
@@ -270,8 +305,12 @@ struct Plan {
   BranchLaunch bl{};
   std::vector<PlainLaunch> pl;
 
+  CallPtrs* d_call = nullptr;   // call block: CallPtrs, then the staging jobs
   StageJob* d_jobs = nullptr;
   int n_jobs = 0;
+  std::vector<StageJob> jobs_host;   // graph plans: the staging jobs as captured,
+  std::vector<JobSource> job_src;    // with where each one reads from
+  double* d_nodes = nullptr;         // staged node coordinates
   int32_t* d_perm = nullptr;
   double* d_cd = nullptr;
   float* d_cf = nullptr;
@@ -279,7 +318,7 @@ struct Plan {
   ItemStat* d_istat = nullptr;
   int64_t* d_first = nullptr;
   int64_t n_nodes = 0;
-  void* out = nullptr;
+  bool has_out = false;
   unsigned long long* ctr = nullptr;
 
   // adjoint reduction
@@ -288,13 +327,13 @@ struct Plan {
   int n_items = 0;
   int32_t* d_slot_node = nullptr;
   double* d_inv_n = nullptr;
-  const double* w = nullptr;
+  bool has_w = false;
   double* d_colsum = nullptr;
   int32_t* d_gmap = nullptr;
-  struct Scatter { int col, count; bool gmap; double* dst; };
+  struct Scatter { int col, count; bool gmap; int which; };
   std::vector<Scatter> scatters;
   // value+Jacobian mode
-  double* jac = nullptr;
+  bool has_jac = false;
   int64_t jac_ld = 0;
   int32_t* d_colmap = nullptr;
   int n_jcols = 0;
@@ -305,15 +344,14 @@ struct Plan {
     if (plain) {
       for (const auto& L : pl)
         if ((e = (L.adjoint ? launch_plain_adj(L, st) : launch_plain(L, st))) != hipSuccess) return e;
-      if (!adjoint) return launch_finalize_nodes(d_istat, d_first, n_nodes, out, ctr, st);
+      if (!adjoint) return launch_finalize_nodes(d_istat, d_first, n_nodes, d_call, 0, ctr, st);
     } else {
       if ((e = launch_fill_u32(d_qhead, 1, 0u, st)) != hipSuccess) return e;
       if (bvp) {
         if ((e = launch_branch_bvp(bvl, st)) != hipSuccess) return e;
         for (int k = 0; k < n_times; ++k)
-          if ((e = launch_finalize_nodes(d_istat + (size_t)k * n_items, d_first, n_nodes,
-                                         (pdd_node_stat*)out + (size_t)k * n_nodes, k == 0 ? ctr : nullptr,
-                                         st)) != hipSuccess)
+          if ((e = launch_finalize_nodes(d_istat + (size_t)k * n_items, d_first, n_nodes, d_call,
+                                         (int64_t)k * n_nodes, k == 0 ? ctr : nullptr, st)) != hipSuccess)
             return e;
         return hipSuccess;
       } else if (branch) {
@@ -322,32 +360,51 @@ struct Plan {
         if ((e = launch_walk(wl, st)) != hipSuccess) return e;
       }
     }
-    if (out != nullptr)
-      if ((e = launch_finalize_nodes(d_istat, d_first, n_nodes, out, ctr, st)) != hipSuccess) return e;
-    if (adjoint && w != nullptr) {
-      if ((e = launch_finalize_grad(d_igrad, grad_stride, grad_stride, n_items, d_slot_node, w, d_inv_n, d_colsum,
-                                    st)) != hipSuccess)
+    if (has_out)
+      if ((e = launch_finalize_nodes(d_istat, d_first, n_nodes, d_call, 0, ctr, st)) != hipSuccess) return e;
+    if (adjoint && has_w) {
+      if ((e = launch_finalize_grad(d_igrad, grad_stride, grad_stride, n_items, d_slot_node, d_call, d_inv_n,
+                                    d_colsum, st)) != hipSuccess)
         return e;
       for (const auto& s : scatters)
-        if ((e = launch_scatter_add(d_colsum + s.col, s.gmap ? d_gmap : nullptr, s.count, s.dst, st)) != hipSuccess)
+        if ((e = launch_scatter_add(d_colsum + s.col, s.gmap ? d_gmap : nullptr, s.count, d_call, s.which, st)) !=
+            hipSuccess)
           return e;
     }
-    if (adjoint && jac != nullptr && n_jcols > 0) {
-      if ((e = launch_node_jacobian(d_igrad, grad_stride, d_first, n_nodes, d_inv_n, d_colmap, n_jcols, jac, jac_ld,
-                                    st)) != hipSuccess)
+    if (adjoint && has_jac && n_jcols > 0) {
+      if ((e = launch_node_jacobian(d_igrad, grad_stride, d_first, n_nodes, d_inv_n, d_colmap, n_jcols, d_call,
+                                    jac_ld, st)) != hipSuccess)
         return e;
     }
     return hipSuccess;
   }
 
   ~Plan() {
+    if (done) {
+      (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
+    }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (owned && arena) (void)hipFree(arena);
   }
 };
 
+// Cached graph plans, least recently used first out.  A plan's arena stays
+// allocated while it is cached (at C5 about 80 MB), so the cache is bounded;
+// an evicted plan is destroyed after its last launch has finished.
+constexpr size_t kMaxPlans = 16;
 std::unordered_map<std::string, std::unique_ptr<Plan>> g_plans;
+uint64_t g_plan_clock = 0;
+
+void evict_plans_locked(size_t keep) {
+  while (g_plans.size() > keep) {
+    auto victim = g_plans.begin();
+    for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
+      if (it->second->last_use < victim->second->last_use) victim = it;
+    g_plans.erase(victim);
+  }
+}
 
 // Host-side staging buffer: copies are stream-ordered; the host vector is
 // pageable, which makes hipMemcpyAsync take its own copy before returning.
@@ -365,19 +422,34 @@ void put(std::vector<Upload>& ups, size_t off, const std::vector<T>& v) {
   ups.push_back(std::move(u));
 }
 
+// The call block: CallPtrs, then the staging jobs from the next 16-byte
+// boundary.  Written by a host-to-device copy before every launch.
+constexpr size_t kJobsOff = (sizeof(CallPtrs) + 15) & ~(size_t)15;
+
+size_t add_call_block(Arena& A, size_t n_jobs) {
+  return A.add(kJobsOff + sizeof(StageJob) * std::max<size_t>(1, n_jobs));
+}
+
+std::vector<char> call_block_image(const CallPtrs& cp, const std::vector<StageJob>& jobs) {
+  std::vector<char> b(kJobsOff + sizeof(StageJob) * jobs.size(), 0);
+  std::memcpy(b.data(), &cp, sizeof(cp));
+  if (!jobs.empty()) std::memcpy(b.data() + kJobsOff, jobs.data(), sizeof(StageJob) * jobs.size());
+  return b;
+}
+
 template <typename T>
 void key_add(std::string& k, const T& v) {
   k.append(reinterpret_cast<const char*>(&v), sizeof(T));
 }
 
+// The structure of a coefficient function (not where its coefficients live:
+// those are read through the staging jobs of the call block).
 void key_fun(std::string& k, const pdd_fun& F) {
   key_add(k, F.n_terms);
   key_add(k, F.n_factors);
   if (F.n_terms > 0 && F.n_factors > 0)
     k.append(reinterpret_cast<const char*>(F.factors), sizeof(pdd_factor) * (size_t)F.n_terms * F.n_factors);
-  key_add(k, F.coef);
   key_add(k, F.poly_degree);
-  key_add(k, F.poly);
 }
 
 // Estimated mean exit time (in steps) from a node; used only to order work
@@ -539,13 +611,33 @@ pdd_status validate_linear(const LinearPlanArgs& a) {
     if (a.jac && (s = check_device_ptr(a.jac, "jac_dev")) != PDD_OK) return s;
   }
   if (a.jac && a.jac_ld < param_count(P)) return fail(PDD_ERR_INVALID_ARG, "jac_ld is smaller than pdd_param_count");
-  if ((o.dump_phi || o.dump_steps) && a.adjoint)
-    return fail(PDD_ERR_UNSUPPORTED, "per-path dumps are not produced by the adjoint");
+  if ((o.dump_phi || o.dump_steps) && a.adjoint && o.precision == PDD_FP64_PLAIN)
+    return fail(PDD_ERR_UNSUPPORTED, "per-path dumps are not produced by the plain adjoint");
   if (o.dump_steps && !o.dump_phi) return fail(PDD_ERR_INVALID_ARG, "dump_steps needs dump_phi");
   if (a.adjoint) {
     if (a.grads == nullptr && a.jac == nullptr) return fail(PDD_ERR_INVALID_ARG, "grads_host is NULL");
   }
   return PDD_OK;
+}
+
+const double* job_source(const pdd_linear_problem& P, const double* nodes, JobSource js) {
+  if (js.part == 3) return nodes;
+  if (js.part == 2 || js.fun < 0) return nullptr;
+  const pdd_fun& F = js.fun < 3 ? P.b[js.fun] : (js.fun == 3 ? P.c : (js.fun == 4 ? P.f : P.g));
+  return js.part == 0 ? F.coef : F.poly;
+}
+
+CallPtrs call_ptrs(const LinearPlanArgs& a) {
+  CallPtrs c{};
+  c.out = a.out;
+  c.w = a.w;
+  c.jac = a.jac;
+  if (a.adjoint && a.grads != nullptr)
+    for (int k = 0; k < 3; ++k) {
+      c.grad[2 * k] = a.grads[k].dcoef;
+      c.grad[2 * k + 1] = a.grads[k].dpoly;
+    }
+  return c;
 }
 
 pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
@@ -560,35 +652,44 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   const bool graph = !plain && (o.schedule == PDD_SCHED_AUTO || o.schedule == PDD_SCHED_PERSISTENT_GRAPH) &&
                      o.dump_phi == nullptr && o.skip_items == nullptr && o.partials == nullptr;
 
-  // ---- plan cache lookup
+  // ---- plan cache lookup: the key holds what shapes the launch (problem
+  // structure, budgets, step, seed, options, which outputs are wanted, the
+  // stream), not the caller's buffers, which reach a replay through the call
+  // block
   std::string key;
   if (graph) {
     key_add(key, a.adjoint ? 2 : (a.wos ? 3 : 1));
     int dev = 0;
     PDD_HIP(hipGetDevice(&dev));
     key_add(key, dev);
+    key_add(key, st);
     key_add(key, P.domain);
     key_add(key, P.sigma);
     for (int k = 0; k < 3; ++k) key_fun(key, P.b[k]);
     key_fun(key, P.c);
     key_fun(key, P.f);
     key_fun(key, P.g);
-    key_add(key, a.nodes);
     key_add(key, a.n_nodes);
     key.append(reinterpret_cast<const char*>(a.paths), sizeof(int64_t) * (size_t)a.n_nodes);
     key_add(key, a.dt);
     key_add(key, a.seed);
     key_add(key, o);
-    key_add(key, a.out);
-    key_add(key, a.w);
-    key_add(key, a.jac);
+    const CallPtrs cp = call_ptrs(a);
+    uint32_t present = (cp.out ? 1u : 0u) | (cp.w ? 2u : 0u) | (cp.jac ? 4u : 0u);
+    for (int k = 0; k < 6; ++k) present |= cp.grad[k] ? (8u << k) : 0u;
+    key_add(key, present);
     key_add(key, a.jac_ld);
-    if (a.adjoint && a.grads)
-      for (int k = 0; k < 3; ++k) key_add(key, a.grads[k]);
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
-      PDD_HIP(hipGraphLaunch(it->second->exec, st));
+      Plan& hp = *it->second;
+      hp.last_use = ++g_plan_clock;
+      std::vector<StageJob> jobs = hp.jobs_host;
+      for (size_t j = 0; j < jobs.size(); ++j) jobs[j].src = job_source(P, a.nodes, hp.job_src[j]);
+      const std::vector<char> img = call_block_image(cp, jobs);
+      PDD_HIP(hipMemcpyAsync(hp.d_call, img.data(), img.size(), hipMemcpyHostToDevice, st));
+      PDD_HIP(hipGraphLaunch(hp.exec, st));
+      PDD_HIP(hipEventRecord(hp.done, st));
       return PDD_OK;
     }
   }
@@ -643,10 +744,10 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   lp.key1 = (uint32_t)(a.seed >> 32);
   pdd_fun zero{};
   zero.poly_degree = -1;
-  for (int k = 0; k < 3; ++k) lp.b[k] = T.add(k < dim ? P.b[k] : zero, dim, dfc, false);
-  lp.c = T.add(P.c, dim, dfc, false);
-  lp.f = T.add(P.f, dim, dfc, false);
-  lp.g = T.add(P.g, dim, 0, true);
+  for (int k = 0; k < 3; ++k) lp.b[k] = T.add(k < dim ? P.b[k] : zero, dim, dfc, false, k);
+  lp.c = T.add(P.c, dim, dfc, false, 3);
+  lp.f = T.add(P.f, dim, dfc, false, 4);
+  lp.g = T.add(P.g, dim, 0, true, 5);
   lp.n_fac = (int)T.fac.size();
   auto nonzero = [](const DevFun& F) { return F.n_terms > 0 || F.poly_deg >= 0; };
   lp.has_b = nonzero(lp.b[0]) || nonzero(lp.b[1]) || nonzero(lp.b[2]);
@@ -686,7 +787,8 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
 
   // ---- arena layout
   Arena A;
-  const size_t o_jobs = A.add(sizeof(StageJob) * std::max<size_t>(1, T.jobs.size()));
+  const size_t o_call = add_call_block(A, T.jobs.size() + 1);   // + the node-coordinate job
+  const size_t o_nodes = A.add(sizeof(double) * (size_t)a.n_nodes * (size_t)dim);
   const size_t o_perm = A.add(sizeof(int32_t) * std::max<size_t>(1, T.perm.size()));
   const size_t o_fac = A.add(sizeof(DevFactor) * std::max<size_t>(1, T.fac.size()));
   const size_t o_cd = A.add(sizeof(double) * std::max(1, T.ncoef));
@@ -783,8 +885,13 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     PDD_HIP(arena_alloc(&pl.arena, A.total, st));
   }
   char* base = (char*)pl.arena;
-  pl.d_jobs = (StageJob*)(base + o_jobs);
+  pl.d_call = (CallPtrs*)(base + o_call);
+  pl.d_jobs = (StageJob*)(base + o_call + kJobsOff);
+  pl.d_nodes = (double*)(base + o_nodes);
+  T.job(StageJob{a.nodes, pl.d_nodes, 0, (int32_t)(a.n_nodes * dim), -1, 0}, -1, 3);
   pl.n_jobs = (int)T.jobs.size();
+  pl.jobs_host = T.jobs;
+  pl.job_src = T.src;
   pl.d_perm = (int32_t*)(base + o_perm);
   DevFactor* d_fac = (DevFactor*)(base + o_fac);
   pl.d_cd = (double*)(base + o_cd);
@@ -793,14 +900,14 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   pl.d_istat = o.partials ? (ItemStat*)o.partials : (ItemStat*)(base + o_istat);
   pl.d_first = (int64_t*)(base + o_first);
   int64_t* d_doff = (int64_t*)(base + o_doff);
-  pl.out = a.out;
+  pl.has_out = a.out != nullptr;
   lp.fac = d_fac;
   lp.cd = pl.d_cd;
   lp.cf = pl.d_cf;
-  lp.nodes = a.nodes;
+  lp.nodes = pl.d_nodes;
 
   std::vector<Upload> ups;
-  put(ups, o_jobs, T.jobs);
+  put(ups, o_call, call_block_image(call_ptrs(a), T.jobs));
   put(ups, o_perm, T.perm);
   put(ups, o_fac, T.fac);
   put(ups, o_doff, doff);
@@ -821,11 +928,11 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     pl.d_inv_n = (double*)(base + o_invn);
     pl.d_colsum = (double*)(base + o_col);
     pl.d_gmap = (int32_t*)(base + o_gmap);
-    pl.w = a.w;
+    pl.has_w = a.w != nullptr;
     if (a.jac) {
       put(ups, o_colmap, colmap);
       pl.d_colmap = (int32_t*)(base + o_colmap);
-      pl.jac = a.jac;
+      pl.has_jac = true;
       pl.jac_ld = a.jac_ld;
       pl.n_jcols = (int)colmap.size();
     }
@@ -836,15 +943,15 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     const pdd_fun_grad& gf = a.grads[1];
     const pdd_fun_grad& gc = a.grads[2];
     int col = 0;
-    if (gg.dcoef && P.g.n_terms > 0) pl.scatters.push_back({col, P.g.n_terms, false, gg.dcoef});
+    if (gg.dcoef && P.g.n_terms > 0) pl.scatters.push_back({col, P.g.n_terms, false, 0});
     col += nt;
-    if (gg.dpoly && ngm > 0) pl.scatters.push_back({col, ngm, true, gg.dpoly});
+    if (gg.dpoly && ngm > 0) pl.scatters.push_back({col, ngm, true, 1});
     col += ngm;
-    if (gf.dcoef && P.f.n_terms > 0) pl.scatters.push_back({col, P.f.n_terms, false, gf.dcoef});
-    if (gf.dpoly && P.f.poly_degree >= 0) pl.scatters.push_back({col + nt, n_mono(dim, P.f.poly_degree), false, gf.dpoly});
+    if (gf.dcoef && P.f.n_terms > 0) pl.scatters.push_back({col, P.f.n_terms, false, 2});
+    if (gf.dpoly && P.f.poly_degree >= 0) pl.scatters.push_back({col + nt, n_mono(dim, P.f.poly_degree), false, 3});
     col += NP;
-    if (gc.dcoef && P.c.n_terms > 0) pl.scatters.push_back({col, P.c.n_terms, false, gc.dcoef});
-    if (gc.dpoly && P.c.poly_degree >= 0) pl.scatters.push_back({col + nt, n_mono(dim, P.c.poly_degree), false, gc.dpoly});
+    if (gc.dcoef && P.c.n_terms > 0) pl.scatters.push_back({col, P.c.n_terms, false, 4});
+    if (gc.dpoly && P.c.poly_degree >= 0) pl.scatters.push_back({col + nt, n_mono(dim, P.c.poly_degree), false, 5});
   }
   for (const auto& u : ups)
     if (!u.bytes.empty()) PDD_HIP(hipMemcpyAsync(base + u.off, u.bytes.data(), u.bytes.size(), hipMemcpyHostToDevice, st));
@@ -921,8 +1028,12 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     return fail(PDD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
   pl.graph = g;
   PDD_HIP(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
+  PDD_HIP(hipEventCreateWithFlags(&pl.done, hipEventDisableTiming));
   PDD_HIP(hipGraphLaunch(pl.exec, st));
+  PDD_HIP(hipEventRecord(pl.done, st));
   std::lock_guard<std::mutex> lk(g_mu);
+  pl.last_use = ++g_plan_clock;
+  evict_plans_locked(kMaxPlans - 1);
   g_plans[key] = std::move(plan);
   return PDD_OK;
 }
@@ -1086,7 +1197,7 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32));
 
   Arena A;
-  const size_t o_jobs = A.add(sizeof(StageJob) * std::max<size_t>(1, T.jobs.size()));
+  const size_t o_call = add_call_block(A, T.jobs.size());
   const size_t o_perm = A.add(sizeof(int32_t) * std::max<size_t>(1, T.perm.size()));
   const size_t o_fac = A.add(sizeof(DevFactor) * std::max<size_t>(1, T.fac.size()));
   const size_t o_cd = A.add(sizeof(double) * std::max(1, T.ncoef));
@@ -1099,7 +1210,8 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
       A.add(branch_stack_entry_bytes(fp32) * (size_t)std::max<int64_t>(1, spill_entries) * (size_t)grid * kBlock);
   PDD_HIP(arena_alloc(&pl.arena, A.total, st));
   char* base = (char*)pl.arena;
-  pl.d_jobs = (StageJob*)(base + o_jobs);
+  pl.d_call = (CallPtrs*)(base + o_call);
+  pl.d_jobs = (StageJob*)(base + o_call + kJobsOff);
   pl.n_jobs = (int)T.jobs.size();
   pl.d_perm = (int32_t*)(base + o_perm);
   pl.d_cd = (double*)(base + o_cd);
@@ -1108,13 +1220,15 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   pl.d_istat = (ItemStat*)(base + o_istat);
   pl.d_first = (int64_t*)(base + o_first);
   pl.n_nodes = n_points;
-  pl.out = out;
+  pl.has_out = true;
   bp.fac = (const DevFactor*)(base + o_fac);
   bp.cd = pl.d_cd;
   bp.cf = pl.d_cf;
   bp.points = points;
   std::vector<Upload> ups;
-  put(ups, o_jobs, T.jobs);
+  CallPtrs cpb{};
+  cpb.out = out;
+  put(ups, o_call, call_block_image(cpb, T.jobs));
   put(ups, o_perm, T.perm);
   put(ups, o_fac, T.fac);
   put(ups, o_first, items.first);
@@ -1235,7 +1349,7 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32));
 
   Arena A;
-  const size_t o_jobs = A.add(sizeof(StageJob) * std::max<size_t>(1, T.jobs.size()));
+  const size_t o_call = add_call_block(A, T.jobs.size());
   const size_t o_perm = A.add(sizeof(int32_t) * std::max<size_t>(1, T.perm.size()));
   const size_t o_fac = A.add(sizeof(DevFactor) * std::max<size_t>(1, T.fac.size()));
   const size_t o_cd = A.add(sizeof(double) * std::max(1, T.ncoef));
@@ -1248,7 +1362,8 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
       A.add(branch_stack_entry_bytes(fp32) * (size_t)std::max<int64_t>(1, spill_entries) * (size_t)grid * kBlock);
   PDD_HIP(arena_alloc(&pl.arena, A.total, st));
   char* base = (char*)pl.arena;
-  pl.d_jobs = (StageJob*)(base + o_jobs);
+  pl.d_call = (CallPtrs*)(base + o_call);
+  pl.d_jobs = (StageJob*)(base + o_call + kJobsOff);
   pl.n_jobs = (int)T.jobs.size();
   pl.d_perm = (int32_t*)(base + o_perm);
   pl.d_cd = (double*)(base + o_cd);
@@ -1258,13 +1373,15 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   pl.d_first = (int64_t*)(base + o_first);
   pl.n_nodes = n_points;
   pl.n_items = n_items;
-  pl.out = out;
+  pl.has_out = true;
   bp.fac = (const DevFactor*)(base + o_fac);
   bp.cd = pl.d_cd;
   bp.cf = pl.d_cf;
   bp.points = points;
   std::vector<Upload> ups;
-  put(ups, o_jobs, T.jobs);
+  CallPtrs cpb{};
+  cpb.out = out;
+  put(ups, o_call, call_block_image(cpb, T.jobs));
   put(ups, o_perm, T.perm);
   put(ups, o_fac, T.fac);
   put(ups, o_first, items.first);
@@ -1436,9 +1553,73 @@ int64_t pdd_item_count(int64_t n_nodes, const int64_t* paths_host, const pdd_opt
 
 pdd_status pdd_release_workspace(void) {
   PDD_HIP(hipDeviceSynchronize());
-  std::lock_guard<std::mutex> lk(g_mu);
-  g_plans.clear();
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans.clear();
+  }
+  PDD_HIP(trim_pools());
   return PDD_OK;
+}
+
+int64_t pdd_cached_plan_count(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return (int64_t)g_plans.size();
+}
+
+pdd_status pdd_jacobian_apply(const double* jac_dev, int64_t n_nodes, int64_t jac_ld, int64_t n_params,
+                              const double* w_dev, double* grad_dev, void* hip_stream) {
+  try {
+    if (n_nodes < 0 || n_params < 0 || jac_ld < n_params) return fail(PDD_ERR_INVALID_ARG, "bad Jacobian sizes");
+    if (n_params == 0) return PDD_OK;
+    pdd_status s;
+    if ((s = check_device_ptr(grad_dev, "grad_dev")) != PDD_OK) return s;
+    if (n_nodes > 0) {
+      if ((s = check_device_ptr(jac_dev, "jac_dev")) != PDD_OK) return s;
+      if ((s = check_device_ptr(w_dev, "w_dev")) != PDD_OK) return s;
+    }
+    PDD_HIP(launch_jacobian_apply(jac_dev, n_nodes, jac_ld, n_params, w_dev, nullptr, nullptr, grad_dev, nullptr,
+                                  (hipStream_t)hip_stream));
+    return PDD_OK;
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_misfit_gradient(const pdd_node_stat* stats_dev, const double* data_dev, int64_t n_nodes,
+                               const double* jac_dev, int64_t jac_ld, int64_t n_params, double* loss_dev,
+                               double* grad_dev, void* hip_stream) {
+  try {
+    if (n_nodes < 0 || n_params < 0 || jac_ld < n_params) return fail(PDD_ERR_INVALID_ARG, "bad Jacobian sizes");
+    pdd_status s;
+    if ((s = check_device_ptr(loss_dev, "loss_dev")) != PDD_OK) return s;
+    if (n_params > 0 && (s = check_device_ptr(grad_dev, "grad_dev")) != PDD_OK) return s;
+    if (n_nodes > 0) {
+      if ((s = check_device_ptr(stats_dev, "stats_dev")) != PDD_OK) return s;
+      if ((s = check_device_ptr(data_dev, "data_dev")) != PDD_OK) return s;
+      if (n_params > 0 && (s = check_device_ptr(jac_dev, "jac_dev")) != PDD_OK) return s;
+    }
+    PDD_HIP(launch_jacobian_apply(jac_dev, n_nodes, jac_ld, n_params, nullptr, stats_dev, data_dev,
+                                  n_params > 0 ? grad_dev : nullptr, loss_dev, (hipStream_t)hip_stream));
+    return PDD_OK;
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_node_moments(const pdd_node_stat* stats_dev, int64_t n_nodes, double* var_dev, double* se_dev,
+                            void* hip_stream) {
+  try {
+    if (n_nodes < 0) return fail(PDD_ERR_INVALID_ARG, "n_nodes < 0");
+    if (n_nodes == 0) return PDD_OK;
+    pdd_status s;
+    if ((s = check_device_ptr(stats_dev, "stats_dev")) != PDD_OK) return s;
+    if (var_dev && (s = check_device_ptr(var_dev, "var_dev")) != PDD_OK) return s;
+    if (se_dev && (s = check_device_ptr(se_dev, "se_dev")) != PDD_OK) return s;
+    PDD_HIP(launch_node_moments(stats_dev, n_nodes, var_dev, se_dev, (hipStream_t)hip_stream));
+    return PDD_OK;
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
 }
 
 const char* pdd_status_string(pdd_status status) {

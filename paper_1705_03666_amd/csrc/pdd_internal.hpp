@@ -107,10 +107,23 @@ struct ItemStat {
   int64_t n, steps, censored, redrawn;
 };
 
-// Copy job for the coefficient staging kernel: dst[dst_off + k] = src[perm ? perm[k] : k].
+// Copy job of the staging kernel.  With dst == nullptr it fills the staged
+// coefficient tables: cd[dst_off + k] = src[perm ? perm[k] : k] (and the FP32
+// shadow cf); otherwise it copies dst[k] = src[k] (node coordinates).
 struct StageJob {
   const double* src;
+  double* dst;
   int32_t dst_off, count, perm_off, pad;
+};
+
+// The caller's per-call buffers that the reduction kernels write or read.
+// They live in one small device block that is rewritten before every launch,
+// so a cached graph plan serves calls whose buffers differ.
+struct CallPtrs {
+  void* out;          // pdd_node_stat [n_nodes] (branching with a boundary: [n_times][n_nodes])
+  const double* w;    // adjoint weights [n_nodes]
+  double* jac;        // value+Jacobian output [n_nodes][jac_ld]
+  double* grad[6];    // gradient destinations: g coef, g poly, f coef, f poly, c coef, c poly
 };
 
 }  // namespace pdd

@@ -94,14 +94,20 @@ hipError_t launch_branch(const BranchLaunch& L, hipStream_t st);
 hipError_t launch_branch_bvp(const BranchBvpLaunch& L, hipStream_t st);
 size_t branch_stack_entry_bytes(bool fp32);
 int branch_lds_depth(bool fp32);
-hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, int64_t n_nodes, void* out,
-                                 unsigned long long* counters, hipStream_t st);
+hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, int64_t n_nodes, const CallPtrs* cp,
+                                 int64_t out_off, unsigned long long* counters, hipStream_t st);
 hipError_t launch_finalize_grad(const double* igrad, int stride, int n_cols, int n_items, const int32_t* slot_node,
-                                const double* w, const double* inv_n, double* colsum, hipStream_t st);
+                                const CallPtrs* cp, const double* inv_n, double* colsum, hipStream_t st);
 hipError_t launch_node_jacobian(const double* igrad, int stride, const int64_t* first, int64_t n_nodes,
-                                const double* inv_n, const int32_t* colmap, int n_cols, double* jac, int64_t jac_ld,
-                                hipStream_t st);
-hipError_t launch_scatter_add(const double* src, const int32_t* map, int count, double* dst, hipStream_t st);
+                                const double* inv_n, const int32_t* colmap, int n_cols, const CallPtrs* cp,
+                                int64_t jac_ld, hipStream_t st);
+hipError_t launch_scatter_add(const double* src, const int32_t* map, int count, const CallPtrs* cp, int which,
+                              hipStream_t st);
+// grad = J^T w, or with data != nullptr the misfit gradient (w_i = 2 (mean_i - data_i))
+// and loss = sum_i (mean_i - data_i)^2
+hipError_t launch_jacobian_apply(const double* jac, int64_t n_rows, int64_t ld, int64_t n_cols, const double* w,
+                                 const void* stats, const double* data, double* grad, double* loss, hipStream_t st);
+hipError_t launch_node_moments(const void* stats, int64_t n, double* var, double* se, hipStream_t st);
 hipError_t launch_stage(const StageJob* jobs, int n_jobs, const int32_t* perm, double* cd, float* cf,
                         hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t st);

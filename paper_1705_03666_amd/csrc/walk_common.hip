@@ -10,10 +10,11 @@ namespace pdd {
 // ---------------------------------------------------------------------------
 // Merge item partials into per-node statistics in item-slot order (fixed).
 __global__ void k_finalize_nodes(const ItemStat* __restrict__ istat, const int64_t* __restrict__ first,
-                                 int64_t n_nodes, pdd_node_stat_dev* __restrict__ out,
+                                 int64_t n_nodes, const CallPtrs* __restrict__ cp, int64_t out_off,
                                  unsigned long long* __restrict__ counters) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_nodes) return;
+  pdd_node_stat_dev* __restrict__ out = (pdd_node_stat_dev*)cp->out + out_off;
   double n = 0.0, m = 0.0, q = 0.0;
   int64_t st = 0, ce = 0, rd = 0;
   for (int64_t s = first[i]; s < first[i + 1]; ++s) {
@@ -35,9 +36,10 @@ __global__ void k_finalize_nodes(const ItemStat* __restrict__ istat, const int64
 // Adjoint reduction: grad[k] = sum over items s (in slot order) of
 // (w[node_s] / N[node_s]) * row_s[k]; one block per column, fixed tree order.
 __global__ void k_finalize_grad(const double* __restrict__ igrad, int stride, int n_items,
-                                const int32_t* __restrict__ slot_node, const double* __restrict__ w,
+                                const int32_t* __restrict__ slot_node, const CallPtrs* __restrict__ cp,
                                 const double* __restrict__ inv_n, double* __restrict__ colsum) {
   const int col = blockIdx.x;
+  const double* __restrict__ w = cp->w;
   __shared__ double part[kBlock];
   double acc = 0.0;
   for (int s = threadIdx.x; s < n_items; s += blockDim.x) {
@@ -57,8 +59,9 @@ __global__ void k_finalize_grad(const double* __restrict__ igrad, int stride, in
 // order) of row_s[colmap[c]].  One block per node.
 __global__ void k_node_jacobian(const double* __restrict__ igrad, int stride, const int64_t* __restrict__ first,
                                 const double* __restrict__ inv_n, const int32_t* __restrict__ colmap, int n_cols,
-                                double* __restrict__ jac, int64_t jac_ld) {
+                                const CallPtrs* __restrict__ cp, int64_t jac_ld) {
   const int64_t i = blockIdx.x;
+  double* __restrict__ jac = cp->jac;
   for (int c = threadIdx.x; c < n_cols; c += blockDim.x) {
     const int src = colmap[c];
     double acc = 0.0;
@@ -67,10 +70,12 @@ __global__ void k_node_jacobian(const double* __restrict__ igrad, int stride, co
   }
 }
 
-// dst[map[k]] += src[k] for the gradient columns of one coefficient array.
+// dst[map[k]] += src[k] for the gradient columns of one coefficient array
+// (dst = the caller's array number `which` of the call block).
 __global__ void k_scatter_add(const double* __restrict__ src, const int32_t* __restrict__ map, int count,
-                              double* __restrict__ dst) {
+                              const CallPtrs* __restrict__ cp, int which) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  double* __restrict__ dst = cp->grad[which];
   if (k < count) dst[map ? map[k] : k] += src[k];
 }
 
@@ -79,6 +84,10 @@ __global__ void k_stage(const StageJob* __restrict__ jobs, int n_jobs, const int
                         double* __restrict__ cd, float* __restrict__ cf) {
   for (int j = 0; j < n_jobs; ++j) {
     const StageJob J = jobs[j];
+    if (J.dst != nullptr) {
+      for (int k = threadIdx.x; k < J.count; k += blockDim.x) J.dst[k] = J.src[k];
+      continue;
+    }
     for (int k = threadIdx.x; k < J.count; k += blockDim.x) {
       const int src = J.perm_off >= 0 ? perm[J.perm_off + k] : k;
       const double v = J.src != nullptr ? J.src[src] : 0.0;
@@ -86,6 +95,65 @@ __global__ void k_stage(const StageJob* __restrict__ jobs, int n_jobs, const int
       cf[J.dst_off + k] = (float)v;
     }
   }
+}
+
+// grad[k] = sum_i w_i J[i][k] (with `data`: w_i = 2 (mean_i - data_i), and
+// loss = sum_i (mean_i - data_i)^2 into *loss).  A block owns 64 columns;
+// its 4 wavefronts take rows r = 4 t + wave (coalesced 64-column row
+// segments), each lane sums its column over those rows in row order, and the
+// four partial sums are added in wave order: a fixed order, so the result is
+// bitwise reproducible.
+__global__ void k_jacobian_apply(const double* __restrict__ jac, int64_t n_rows, int64_t ld, int64_t n_cols,
+                                 const double* __restrict__ w, const pdd_node_stat_dev* __restrict__ stats,
+                                 const double* __restrict__ data, double* __restrict__ grad,
+                                 double* __restrict__ loss) {
+  constexpr int kW = kBlock / kWave;
+  __shared__ double part[kW][kWave];
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int wv = (int)(threadIdx.x / kWave);
+  const int64_t col = (int64_t)blockIdx.x * kWave + lane;
+  double acc = 0.0, lacc = 0.0;
+  for (int64_t r = wv; r < n_rows; r += kW) {
+    double wi;
+    if (data != nullptr) {
+      const double e = stats[r].mean - data[r];
+      wi = 2.0 * e;
+      lacc += e * e;
+    } else {
+      wi = w[r];
+    }
+    if (col < n_cols) acc += wi * jac[(size_t)r * ld + col];
+  }
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0 && col < n_cols) {
+    double s = part[0][lane];
+#pragma unroll
+    for (int k = 1; k < kW; ++k) s += part[k][lane];
+    grad[col] = s;
+  }
+  if (loss != nullptr && blockIdx.x == 0) {
+    __syncthreads();
+    part[wv][lane] = lacc;   // every lane of a wave holds the same partial loss
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = part[0][0];
+#pragma unroll
+      for (int k = 1; k < kW; ++k) s += part[k][0];
+      *loss = s;
+    }
+  }
+}
+
+// var_i = m2_i / (n_i - 1) (0 for n_i < 2), se_i = sqrt(var_i / n_i).
+__global__ void k_node_moments(const pdd_node_stat_dev* __restrict__ stats, int64_t n, double* __restrict__ var,
+                               double* __restrict__ se) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const pdd_node_stat_dev s = stats[i];
+  const double v = s.n > 1 ? s.m2 / (double)(s.n - 1) : 0.0;
+  if (var != nullptr) var[i] = v;
+  if (se != nullptr) se[i] = s.n > 0 ? sqrt(v / (double)s.n) : 0.0;
 }
 
 __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
@@ -124,31 +192,48 @@ hipError_t launch_walk(const WalkLaunch& L, hipStream_t st) {
   return L.fp32 ? launch_walk_adj_f32(L, st) : launch_walk_adj_f64(L, st);
 }
 
-hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, int64_t n_nodes, void* out,
-                                 unsigned long long* counters, hipStream_t st) {
+hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, int64_t n_nodes, const CallPtrs* cp,
+                                 int64_t out_off, unsigned long long* counters, hipStream_t st) {
   const int64_t blocks = (n_nodes + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_finalize_nodes, dim3((unsigned)blocks), dim3(kBlock), 0, st, istat, first, n_nodes,
-                     (pdd_node_stat_dev*)out, counters);
+  hipLaunchKernelGGL(k_finalize_nodes, dim3((unsigned)blocks), dim3(kBlock), 0, st, istat, first, n_nodes, cp,
+                     out_off, counters);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize_grad(const double* igrad, int stride, int n_cols, int n_items, const int32_t* slot_node,
-                                const double* w, const double* inv_n, double* colsum, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_grad, dim3(n_cols), dim3(kBlock), 0, st, igrad, stride, n_items, slot_node, w,
+                                const CallPtrs* cp, const double* inv_n, double* colsum, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_grad, dim3(n_cols), dim3(kBlock), 0, st, igrad, stride, n_items, slot_node, cp,
                      inv_n, colsum);
   return hipGetLastError();
 }
 
 hipError_t launch_node_jacobian(const double* igrad, int stride, const int64_t* first, int64_t n_nodes,
-                                const double* inv_n, const int32_t* colmap, int n_cols, double* jac, int64_t jac_ld,
-                                hipStream_t st) {
+                                const double* inv_n, const int32_t* colmap, int n_cols, const CallPtrs* cp,
+                                int64_t jac_ld, hipStream_t st) {
   hipLaunchKernelGGL(k_node_jacobian, dim3((unsigned)n_nodes), dim3(kBlock), 0, st, igrad, stride, first, inv_n, colmap,
-                     n_cols, jac, jac_ld);
+                     n_cols, cp, jac_ld);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_add(const double* src, const int32_t* map, int count, double* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_scatter_add, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, map, count, dst);
+hipError_t launch_scatter_add(const double* src, const int32_t* map, int count, const CallPtrs* cp, int which,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_add, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, map, count, cp,
+                     which);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobian_apply(const double* jac, int64_t n_rows, int64_t ld, int64_t n_cols, const double* w,
+                                 const void* stats, const double* data, double* grad, double* loss, hipStream_t st) {
+  const int64_t blocks = (n_cols + kWave - 1) / kWave;
+  hipLaunchKernelGGL(k_jacobian_apply, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kBlock), 0, st, jac, n_rows,
+                     ld, n_cols, w, (const pdd_node_stat_dev*)stats, data, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_moments(const void* stats, int64_t n, double* var, double* se, hipStream_t st) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_node_moments, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kBlock), 0, st,
+                     (const pdd_node_stat_dev*)stats, n, var, se);
   return hipGetLastError();
 }
 

@@ -656,3 +656,57 @@ def test_adjoint_analytic_solid_harmonic_gradient(orc):
     # allow 4 SE of a bounded variable plus the sqrt(dt) exit bias
     tol = 4.0 * 1.3 / math.sqrt(n) + 0.03
     assert np.max(np.abs(grad_theta - exact)) < tol
+
+
+def test_walk_jacobian_columns_are_walks_of_the_basis_functions(orc):
+    """With c = 0 the derivative of one path value with respect to a
+    coefficient of g is that basis function at the exit point, and with
+    respect to one of f the path's integral of that basis function: each
+    Jacobian column is the plain walk of the problem whose g (or f) is that
+    basis function alone.  Its mean and standard error must equal that walk's
+    (whose Welford statistics are pinned to a two-pass computation)."""
+    P = _small_adjoint_problem(2)
+    P.c = zero_fun()
+    P.g = make_fun([(0.8, [factor("sin", 2)])], poly_degree=2, poly=np.arange(10) * 0.1 - 0.3)
+    P.f = make_fun([(0.5, [factor("cos", 1)])], poly_degree=1, poly=np.array([0.2, -0.1, 0.4, 0.3]))
+    nodes = CF.c5_nodes(3)
+    paths = np.array([300, 150, 211], np.int64)
+    dt, seed = 1e-2, 13
+    ids = np.array([7, 40, 2])
+    J = orc.walk_jacobian(P, nodes, paths, dt, seed, node_ids=ids)
+    one = lambda n, k: np.eye(n)[k]
+    col = 0
+    cases = []
+    for k in range(P.g.n_terms):
+        cases.append(("g", P.g.with_coef(coef=one(P.g.n_terms, k), poly=np.zeros(len(P.g.poly)))))
+    for m in range(len(P.g.poly)):
+        cases.append(("g", P.g.with_coef(coef=np.zeros(P.g.n_terms), poly=one(len(P.g.poly), m))))
+    for k in range(P.f.n_terms):
+        cases.append(("f", P.f.with_coef(coef=one(P.f.n_terms, k), poly=np.zeros(len(P.f.poly)))))
+    for m in range(len(P.f.poly)):
+        cases.append(("f", P.f.with_coef(coef=np.zeros(P.f.n_terms), poly=one(len(P.f.poly), m))))
+    assert J["jac"].shape == (3, len(cases) + len(P.c.poly) + P.c.n_terms)
+    for name, F in cases:
+        Pk = LinearProblem(P.domain, P.sigma, P.b, zero_fun(), F if name == "f" else zero_fun(),
+                           F if name == "g" else zero_fun())
+        r = orc.walk(Pk, nodes, paths, dt, seed, node_ids=ids)
+        assert np.allclose(J["jac"][:, col], r["mean"], rtol=1e-12, atol=1e-14), (name, col)
+        assert np.allclose(J["jac_se"][:, col], r["se"], rtol=1e-9, atol=1e-14), (name, col)
+        col += 1
+    assert np.array_equal(J["stats"]["steps"], orc.walk(P, nodes, paths, dt, seed, node_ids=ids)["steps"])
+
+
+def test_walk_jacobian_weighted_rows_equal_the_adjoint(orc):
+    """sum_i w_i J[i] is the gradient of sum_i w_i u_i, which the adjoint
+    computes (pinned above by finite differences with common random
+    numbers); with terms and polynomials in g, f and c."""
+    P = _small_adjoint_problem(3)
+    nodes = CF.c5_nodes(4)
+    paths = np.array([120, 90, 150, 60], np.int64)
+    dt, seed = 1e-2, 4
+    w = np.array([0.5, -1.5, 2.0, 0.7])
+    J = orc.walk_jacobian(P, nodes, paths, dt, seed)
+    adj = orc.walk_adjoint(P, nodes, paths, dt, seed, w)
+    want = np.concatenate([adj[k] for k in ("g_coef", "g_poly", "f_coef", "f_poly", "c_coef", "c_poly")])
+    got = w @ J["jac"]
+    assert np.allclose(got, want, rtol=1e-11, atol=1e-13 * np.abs(want).max())
