@@ -266,6 +266,26 @@ pdd_status pdd_mc_interface(const pdd_linear_problem* problem, const double* nod
                             const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
                             pdd_node_stat* out_dev, void* hip_stream);
 
+/* pdd_mc_interface for callers that cannot allocate device memory (code
+ * running under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same walk, statistics and outputs, but every scratch
+ * buffer of the call (staged tables, node copy, work queue, per-item
+ * partials) is carved out of one fixed area of 16 MiB that the library holds
+ * on each device it runs on until the process ends; the call maps no memory,
+ * calls no hipMalloc / hipFree / pool allocation and compiles nothing at run
+ * time (problems with generic terms in b, c or f run on the table-driven
+ * kernel, which computes the same values).  The schedule option is taken as
+ * PDD_SCHED_PERSISTENT (no cached graph).  A call whose scratch does not fit
+ * returns PDD_ERR_UNSUPPORTED before enqueuing anything, with the sizes in
+ * pdd_last_error() (4096 nodes x 1e5 paths in FP32 take about 4 MB).
+ * Every call on one device shares that device's area, whose contents are the
+ * last call's: calls that overlap on one GPU (two streams, two threads) race
+ * and must be serialised by the caller.  Arguments and errors otherwise as
+ * pdd_mc_interface. */
+pdd_status pdd_mc_interface_noalloc(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                                    const int64_t* paths_host, double dt, uint64_t seed,
+                                    const pdd_options* options, pdd_node_stat* out_dev, void* hip_stream);
+
 /* Walk on Spheres for Laplace's equation with Dirichlet data, the method
  * Sec. 2.1 recommends for that case: b, c and f must be identically zero
  * (no terms, no polynomial; else PDD_ERR_UNSUPPORTED); sigma does not

@@ -27,7 +27,7 @@ import torch
 from . import _abi as A
 from . import nonlinear  # noqa: F401  (host-side driver of Sec. 3.3)
 
-__all__ = ["mc_interface", "mc_interface_many", "mc_adjoint", "mc_value_jacobian", "branching_eval", "branching_bvp", "wos_interface",
+__all__ = ["mc_interface", "mc_interface_noalloc", "mc_interface_many", "mc_adjoint", "mc_value_jacobian", "branching_eval", "branching_bvp", "wos_interface",
            "item_count", "PDDInterface", "PddError",
            "release_workspace", "query_warnings", "library", "version", "param_layout", "jacobian_blocks",
            "jacobian_apply", "misfit_gradient", "cached_plan_count", "nonlinear"]
@@ -235,6 +235,40 @@ def mc_interface(problem, nodes, paths, dt: float, seed: int = 0, precision: str
     if dump:
         total = int(ph.sum())
         res["phi"], res["path_steps"] = dphi[:total], dst[:total]
+    res["_keep"] = keep
+    return res
+
+
+def mc_interface_noalloc(problem, nodes, paths, dt: float, seed: int = 0, precision: str = "fp32",
+                         layout: Optional[str] = None, max_steps: int = 0, chunk_paths: int = 0,
+                         blocks_per_cu: int = 0, refill_groups: int = 0,
+                         coefs: Optional[Dict[str, torch.Tensor]] = None, boundary_correction: bool = False,
+                         out: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+    """mc_interface through pdd_mc_interface_noalloc: the library maps no device
+    memory for the call (its scratch is a fixed per-device area).  `out`, if
+    given, is the caller's float64 CUDA tensor [n, 5] that receives the
+    pdd_node_stat records (so that a caller who cannot allocate passes its own)."""
+    _need_gpu()
+    keep = _Keep()
+    p = _linear(problem, keep, coefs)
+    nt = _nodes_tensor(nodes, problem.domain.ndim)
+    n = nt.shape[0]
+    ph = np.ascontiguousarray(np.asarray(paths, dtype=np.int64).reshape(-1))
+    if ph.shape[0] != n:
+        raise ValueError("paths must have one entry per node")
+    if out is None:
+        out = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
+    elif not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.dim() == 2
+              and out.shape[1] == 5 and out.shape[0] >= n):
+        raise ValueError("out must be a contiguous float64 CUDA tensor [>= n, 5]")
+    o = _options(precision, layout, max_steps, "persistent", chunk_paths, blocks_per_cu, refill_groups,
+                 boundary_correction=boundary_correction, specialize="off")
+    st = library().pdd_mc_interface_noalloc(C.byref(p), nt.data_ptr() if n else None, n,
+                                            ph.ctypes.data_as(C.POINTER(C.c_int64)), float(dt),
+                                            int(seed) & (2 ** 64 - 1), C.byref(o), out.data_ptr(),
+                                            _stream_handle())
+    _check(st, "pdd_mc_interface_noalloc")
+    res = _stats(out[:n])
     res["_keep"] = keep
     return res
 

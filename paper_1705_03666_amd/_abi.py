@@ -15,7 +15,7 @@ PDD_FP64_PLAIN, PDD_FP64, PDD_FP32_STEP = 0, 1, 2
 PDD_RNG_PAIR52, PDD_RNG_QUAD24 = 0, 1
 PDD_SCHED_AUTO, PDD_SCHED_PERSISTENT, PDD_SCHED_PERSISTENT_GRAPH = 0, 1, 2
 
-EXPORTED = ["pdd_mc_interface", "pdd_wos_interface", "pdd_branching_eval", "pdd_branching_bvp", "pdd_mc_adjoint",
+EXPORTED = ["pdd_mc_interface", "pdd_mc_interface_noalloc", "pdd_wos_interface", "pdd_branching_eval", "pdd_branching_bvp", "pdd_mc_adjoint",
             "pdd_mc_value_jacobian", "pdd_item_count",
             "pdd_param_count", "pdd_jacobian_apply", "pdd_misfit_gradient", "pdd_node_moments",
             "pdd_query_warnings", "pdd_release_workspace", "pdd_cached_plan_count", "pdd_status_string",
@@ -80,6 +80,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.pdd_mc_interface.argtypes = [C.POINTER(pdd_linear_problem), C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                    C.c_double, C.c_uint64, C.POINTER(pdd_options), C.c_void_p, C.c_void_p]
     L.pdd_mc_interface.restype = C.c_int
+    L.pdd_mc_interface_noalloc.argtypes = L.pdd_mc_interface.argtypes
+    L.pdd_mc_interface_noalloc.restype = C.c_int
     L.pdd_wos_interface.argtypes = L.pdd_mc_interface.argtypes
     L.pdd_wos_interface.restype = C.c_int
     L.pdd_branching_eval.argtypes = [C.POINTER(pdd_branching_problem), C.c_void_p, C.c_int64, C.c_int64, C.c_uint64,

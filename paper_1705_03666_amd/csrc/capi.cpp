@@ -19,6 +19,7 @@
 #include "pdd_internal.hpp"
 #include "pdd_kernels.hpp"
 #include "pdd_spec.hpp"
+#include "pdd_fixed.hpp"
 #include "pdd_tuning.hpp"
 
 using namespace pdd;
@@ -258,20 +259,15 @@ int device_cus() {
   return cus[dev];
 }
 
-// per-device warning counters (censored paths, redrawn trees)
+// per-device warning counters (censored paths, redrawn trees): a device
+// array of the library (zero when the library is loaded), never allocated
 std::mutex g_mu;
-unsigned long long* g_counters[64] = {nullptr};
 
 pdd_status counters(unsigned long long** out) {
   int dev = 0;
   PDD_HIP(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64) return fail(PDD_ERR_UNSUPPORTED, "device index above 63");
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (g_counters[dev] == nullptr) {
-    PDD_HIP(hipMalloc((void**)&g_counters[dev], 2 * sizeof(unsigned long long)));
-    PDD_HIP(hipMemset(g_counters[dev], 0, 2 * sizeof(unsigned long long)));
-  }
-  *out = g_counters[dev];
+  if (dev < 0 || dev >= kMaxDevices) return fail(PDD_ERR_UNSUPPORTED, "device index above 63");
+  PDD_HIP(fixed_symbols(nullptr, out));
   return PDD_OK;
 }
 
@@ -540,6 +536,8 @@ struct LinearPlanArgs {
   double* jac;          // value+Jacobian mode: [n_nodes][jac_ld]
   int64_t jac_ld;
   bool wos = false;     // walk on spheres; dt holds eps
+  void* fixed = nullptr;     // caller-provided scratch area: no allocation, no graph, no
+  size_t fixed_bytes = 0;    // runtime-compiled kernel
 };
 
 int64_t param_count(const pdd_linear_problem& P) {
@@ -650,7 +648,8 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   const bool plain = o.precision == PDD_FP64_PLAIN;
   const bool fp32 = o.precision == PDD_FP32_STEP;
   const bool graph = !plain && (o.schedule == PDD_SCHED_AUTO || o.schedule == PDD_SCHED_PERSISTENT_GRAPH) &&
-                     o.dump_phi == nullptr && o.skip_items == nullptr && o.partials == nullptr;
+                     o.dump_phi == nullptr && o.skip_items == nullptr && o.partials == nullptr &&
+                     a.fixed == nullptr;
 
   // ---- plan cache lookup: the key holds what shapes the launch (problem
   // structure, budgets, step, seed, options, which outputs are wanted, the
@@ -862,7 +861,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
 
   // ---- problem-specialised kernel for per-step generic terms
   hipFunction_t spec = nullptr;
-  if (!plain && bcf_terms && !a.wos && o.specialize >= 0) {
+  if (!plain && bcf_terms && !a.wos && o.specialize >= 0 && a.fixed == nullptr) {
     const std::string src = spec_terms_source(lp, T.fac);
     std::string why = "a scale or shift is not finite";
     if (src.empty() ||
@@ -878,7 +877,13 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   }
 
   // ---- allocate
-  if (graph) {
+  if (a.fixed != nullptr) {
+    if (A.total > a.fixed_bytes)
+      return fail(PDD_ERR_UNSUPPORTED, "this call needs " + std::to_string(A.total) +
+                                           " bytes of scratch; the fixed scratch area holds " +
+                                           std::to_string(a.fixed_bytes));
+    pl.arena = a.fixed;
+  } else if (graph) {
     PDD_HIP(hipMalloc(&pl.arena, A.total));
     pl.owned = true;
   } else {
@@ -1003,10 +1008,10 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   if (!graph) {
     hipError_t e = pl.enqueue(st);
     if (e != hipSuccess) {
-      (void)hipFreeAsync(pl.arena, st);
+      if (a.fixed == nullptr) (void)hipFreeAsync(pl.arena, st);
       return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     }
-    PDD_HIP(hipFreeAsync(pl.arena, st));
+    if (a.fixed == nullptr) PDD_HIP(hipFreeAsync(pl.arena, st));
     return PDD_OK;
   }
   // graph: uploads are ordered before capture on the caller's stream; the
@@ -1039,6 +1044,30 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
 }
 
 }  // namespace
+
+namespace pdd {
+
+pdd_status set_error(pdd_status s, const std::string& msg) { return fail(s, msg); }
+
+pdd_status run_linear_fixed(const pdd_linear_problem* problem, const double* nodes_dev, int64_t n_nodes,
+                            const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
+                            pdd_node_stat* out_dev, void* area, size_t bytes, void* hip_stream) {
+  try {
+    if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
+    if (area == nullptr || bytes == 0) return fail(PDD_ERR_INVALID_ARG, "no scratch area");
+    LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, false, nullptr, nullptr,
+                     nullptr, 0};
+    a.fixed = area;
+    a.fixed_bytes = bytes;
+    return run_linear(a, (hipStream_t)hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+}  // namespace pdd
 
 // ============================================================================= branching
 namespace {
