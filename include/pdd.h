@@ -182,6 +182,23 @@ typedef enum {
   PDD_SCHED_PERSISTENT_GRAPH = 2  /* persistent kernel captured once into a hipGraph and replayed */
 } pdd_schedule;
 
+/* The persistent kernels, as keys of the schedule table. */
+typedef enum {
+  PDD_KERNEL_WALK = 0,          /* pdd_mc_interface (batched forward walk) */
+  PDD_KERNEL_WALK_ADJOINT = 1,  /* pdd_mc_adjoint, pdd_mc_value_jacobian */
+  PDD_KERNEL_WOS = 2,           /* pdd_wos_interface */
+  PDD_KERNEL_WALK_BATCH = 3,    /* pdd_mc_interface_batch (dim 0: any mix of dimensions) */
+  PDD_KERNEL_WOS_BATCH = 4,     /* pdd_wos_interface_batch */
+  PDD_KERNEL_BRANCH = 5,        /* pdd_branching_eval */
+  PDD_KERNEL_BRANCH_BVP = 6     /* pdd_branching_bvp */
+} pdd_kernel;
+
+/* A launch schedule: paths (trees) per large work item, persistent blocks
+ * per compute unit, step groups between lane refills (walks only). */
+typedef struct {
+  int32_t chunk_paths, blocks_per_cu, refill_groups, pad;
+} pdd_launch_schedule;
+
 /* Partial statistics of one work item (48 bytes): the Welford triple of its
  * paths, their total steps, censored paths and redrawn trees. */
 typedef struct {
@@ -200,9 +217,9 @@ typedef struct {
   int32_t schedule;       /* pdd_schedule */
   int32_t chunk_paths;    /* paths per large work item (about the last eighth of each node's paths
                              goes into items of chunk_paths/8, at least 256, queued last);
-                             0 = autotuned/default */
-  int32_t blocks_per_cu;  /* persistent grid size per compute unit; 0 = autotuned/default */
-  int32_t refill_groups;  /* step groups between lane refills; 0 = autotuned/default (3) */
+                             0 = the schedule table (tuned entry, else default) */
+  int32_t blocks_per_cu;  /* persistent grid size per compute unit; 0 = the schedule table */
+  int32_t refill_groups;  /* step groups between lane refills; 0 = the schedule table */
   int32_t boundary_correction; /* linear walks: 0 = plain exit test (X outside D after a step);
                                   1 = boundary-corrected test of Gobet and Menozzi (Sec. 2.1 points to
                                   their schemes): the path stops once X leaves D shrunk by
@@ -301,6 +318,36 @@ pdd_status pdd_wos_interface(const pdd_linear_problem* problem, const double* no
                              const int64_t* paths_host, double eps, uint64_t seed, const pdd_options* options,
                              pdd_node_stat* out_dev, void* hip_stream);
 
+/* Interface values of a heterogeneous batch of linear problems in one
+ * persistent launch: the nodes of every subdomain of a PDD partition (or of
+ * several partitions), whose domains, dimensions, operators and boundary data
+ * differ, share one work queue and one grid (the loops over interface nodes
+ * and samples of Algorithm 3.1).
+ *  problems: host [n_problems], 1 <= n_problems <= 64; each as for
+ *    pdd_mc_interface except that b, c, f are dense polynomials only (no
+ *    generic terms: PDD_ERR_UNSUPPORTED); g may have terms.  Dimensions 1..3
+ *    may be mixed.
+ *  node_problem_host: host [n_nodes], the problem of every node.
+ *  nodes_dev: device [n_nodes][3] FP64; a node uses the first dim
+ *    coordinates of its row (the rest are ignored).
+ *  paths_host, dt, seed, out_dev: as pdd_mc_interface; options as
+ *    pdd_mc_interface except PDD_FP64_PLAIN, skip_items and partials
+ *    (PDD_ERR_UNSUPPORTED).
+ * Node i draws its Gaussians with node index i (its row in this batch), so
+ * its paths are those pdd_mc_interface computes for a node of index i with
+ * the same problem. */
+pdd_status pdd_mc_interface_batch(const pdd_linear_problem* problems, int32_t n_problems,
+                                  const int32_t* node_problem_host, const double* nodes_dev, int64_t n_nodes,
+                                  const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
+                                  pdd_node_stat* out_dev, void* hip_stream);
+
+/* Walk on Spheres over a heterogeneous batch (b, c, f zero in every problem;
+ * eps as pdd_wos_interface; everything else as pdd_mc_interface_batch). */
+pdd_status pdd_wos_interface_batch(const pdd_linear_problem* problems, int32_t n_problems,
+                                   const int32_t* node_problem_host, const double* nodes_dev, int64_t n_nodes,
+                                   const int64_t* paths_host, double eps, uint64_t seed, const pdd_options* options,
+                                   pdd_node_stat* out_dev, void* hip_stream);
+
 /* Branching estimator (Sec. 3.1-3.2) at points_dev [n_points][dim] (device,
  * FP64), trees_per_point trees each (< 2^32).  out_dev: device [n_points];
  * steps = segments simulated, censored = trees that failed 16 draws (value 0).
@@ -395,11 +442,34 @@ pdd_status pdd_node_moments(const pdd_node_stat* stats_dev, int64_t n_nodes, dou
  * PDD_WARN_CENSORED / PDD_WARN_REDRAWN if non-zero, else PDD_OK. */
 pdd_status pdd_query_warnings(void* hip_stream, int64_t* censored_out, int64_t* redrawn_out);
 
-/* Number of work items (partials slots) pdd_mc_interface / pdd_wos_interface
- * cut these budgets into with these options on the current device (the item
- * size depends on the schedule options, the precision, the total path count
- * and the device's compute units).  Negative pdd_status on invalid input. */
-int64_t pdd_item_count(int64_t n_nodes, const int64_t* paths_host, const pdd_options* options);
+/* Number of work items (partials slots) a call of `kernel` (PDD_KERNEL_WALK,
+ * PDD_KERNEL_WOS, PDD_KERNEL_WALK_BATCH or PDD_KERNEL_WOS_BATCH) in dimension
+ * `dim` (0 for the batch entry points) cuts these budgets into with these
+ * options on the current device (the item size depends on the schedule
+ * options, the schedule table, the precision, the total path count and the
+ * device's compute units).  Negative pdd_status on invalid input. */
+int64_t pdd_item_count(int32_t kernel, int32_t dim, int64_t n_nodes, const int64_t* paths_host,
+                       const pdd_options* options);
+
+/* Schedule table of the current device (see the options chunk_paths,
+ * blocks_per_cu, refill_groups: a call takes each knob from its options when
+ * non-zero, else from the table entry of (kernel, dim, precision), else from
+ * the built-in default).  Entries are kept per device kind (architecture and
+ * compute-unit count); the library reads $PDD_SCHEDULE_FILE (default
+ * ~/.cache/pdd/schedules.txt) on its first call.  precision: PDD_FP64 or
+ * PDD_FP32_STEP; dim: 1..3, or 0 for the batch kernels.
+ *  pdd_set_schedule: sets (s != NULL) or removes (s == NULL) an entry of this
+ *    process's table; 1 <= chunk_paths <= 2^30, 1 <= blocks_per_cu,
+ *    refill_groups <= 64, else PDD_ERR_INVALID_ARG.
+ *  pdd_get_schedule: the entry a call would start from (tuned, or the
+ *    default), *tuned = 1 if it is a table entry.
+ *  pdd_save_schedules / pdd_load_schedules: write the table to / merge a file
+ *    into it (path NULL = the default file); PDD_ERR_INVALID_ARG if the file
+ *    cannot be written / read. */
+pdd_status pdd_set_schedule(int32_t kernel, int32_t dim, int32_t precision, const pdd_launch_schedule* s);
+pdd_status pdd_get_schedule(int32_t kernel, int32_t dim, int32_t precision, pdd_launch_schedule* out, int32_t* tuned);
+pdd_status pdd_save_schedules(const char* path);
+pdd_status pdd_load_schedules(const char* path);
 
 /* Frees cached launch plans and their device memory, and returns the memory
  * the library's pools keep (synchronizes the device). */

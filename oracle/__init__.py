@@ -99,7 +99,7 @@ def lib():
         L.orc_walk.argtypes = [C.POINTER(OLinear), dp, C.c_int64, ip, C.c_double, C.c_uint64, C.c_int,
                                C.c_int64, C.c_int, C.POINTER(OStat), dp, ip, ip]
         L.orc_wos.argtypes = [C.POINTER(OLinear), dp, C.c_int64, ip, C.c_double, C.c_uint64, C.c_int,
-                              C.c_int64, C.c_int, C.POINTER(OStat), dp, ip]
+                              C.c_int64, C.c_int, C.POINTER(OStat), dp, ip, ip]
         L.orc_walk_adjoint.argtypes = [C.POINTER(OLinear), dp, C.c_int64, ip, C.c_double, C.c_uint64, C.c_int,
                                        C.c_int64, C.c_int, dp, dp, dp, dp, dp, dp, dp, C.POINTER(OStat)]
         L.orc_walk_jacobian.argtypes = [C.POINTER(OLinear), dp, C.c_int64, ip, C.c_double, C.c_uint64, C.c_int,
@@ -266,9 +266,10 @@ def walk(P: LinearProblem, nodes, paths, dt: float, seed: int, layout: int = PAI
 
 
 def wos(P: LinearProblem, nodes, paths, eps: float, seed: int, layout: int = PAIR52,
-        max_steps: int = 100000, n_threads: Optional[int] = None, dump: bool = False) -> dict:
+        max_steps: int = 100000, n_threads: Optional[int] = None, dump: bool = False, node_ids=None) -> dict:
     """Walk on Spheres for Laplace's equation (b = c = f = 0): per-node mean /
-    variance of g at the projected eps-shell exit point; steps = jumps."""
+    variance of g at the projected eps-shell exit point; steps = jumps.
+    node_ids as in walk()."""
     keep = _Keep()
     o = _olinear(P, keep)
     nodes = keep.arr(nodes, np.float64)
@@ -280,7 +281,8 @@ def wos(P: LinearProblem, nodes, paths, eps: float, seed: int, layout: int = PAI
     st = np.zeros(total if dump else 1, np.int64)
     rc = lib().orc_wos(C.byref(o), _ptr(nodes, C.c_double), n, _ptr(paths, C.c_int64), eps, seed, layout,
                        max_steps, default_threads() if n_threads is None else n_threads, out,
-                       _ptr(phi, C.c_double) if dump else None, _ptr(st, C.c_int64) if dump else None)
+                       _ptr(phi, C.c_double) if dump else None, _ptr(st, C.c_int64) if dump else None,
+                       _ptr(keep.arr(node_ids, np.int64), C.c_int64) if node_ids is not None else None)
     if rc != 0:
         raise ValueError("oracle rejected the walk-on-spheres arguments")
     res = _stats(out[:n])

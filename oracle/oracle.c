@@ -485,7 +485,7 @@ static void wos_node(void* vctx, int64_t i, int worker) {
 
 int orc_wos(const orc_linear* P, const double* nodes, int64_t n_nodes, const int64_t* paths,
             double eps, uint64_t seed, int layout, int64_t max_steps, int n_threads,
-            orc_stat* out, double* dump_phi, int64_t* dump_steps) {
+            orc_stat* out, double* dump_phi, int64_t* dump_steps, const int64_t* node_ids) {
   if ((P->dom.kind != ORC_BOX && P->dom.kind != ORC_BALL) || P->dom.dim < 1 || P->dom.dim > 3 || !(eps > 0.0))
     return -1;
   for (int k = 0; k < P->dom.dim; ++k)
@@ -495,6 +495,7 @@ int orc_wos(const orc_linear* P, const double* nodes, int64_t n_nodes, const int
   memset(&C, 0, sizeof(C));
   C.P = P; C.nodes = nodes; C.paths = paths; C.dt = eps; C.layout = layout;
   C.max_steps = max_steps; C.out = out; C.dump_phi = dump_phi; C.dump_steps = dump_steps;
+  C.node_ids = node_ids;
   make_key(seed, C.key);
   int64_t* off = prefix_offsets(paths, n_nodes);
   C.offsets = off;

@@ -124,10 +124,11 @@ int orc_walk(const orc_linear* P, const double* nodes, int64_t n_nodes, const in
    path (same counters as orc_walk); it stops at the first r < eps (before
    jumping) with phi = g(P(X)); steps = number of jumps.  A path reaching
    max_steps jumps is censored with phi = g(P(X)).  A node outside D gives
-   phi = g(P(node)), 0 jumps.  Returns -1 if b, c or f is not zero. */
+   phi = g(P(node)), 0 jumps.  node_ids as for orc_walk.  Returns -1 if b, c or
+   f is not zero. */
 int orc_wos(const orc_linear* P, const double* nodes, int64_t n_nodes, const int64_t* paths,
             double eps, uint64_t seed, int layout, int64_t max_steps, int n_threads,
-            orc_stat* out, double* dump_phi, int64_t* dump_steps);
+            orc_stat* out, double* dump_phi, int64_t* dump_steps, const int64_t* node_ids);
 
 /* gradient of sum_i w_i * mean_i with respect to the coefficient arrays
    (accumulated into caller-zeroed arrays; NULL pointers are skipped) */

@@ -27,8 +27,9 @@ import torch
 from . import _abi as A
 from . import nonlinear  # noqa: F401  (host-side driver of Sec. 3.3)
 
-__all__ = ["mc_interface", "mc_interface_noalloc", "mc_interface_many", "mc_adjoint", "mc_value_jacobian", "branching_eval", "branching_bvp", "wos_interface",
-           "item_count", "PDDInterface", "PddError",
+__all__ = ["mc_interface", "mc_interface_noalloc", "mc_interface_batch", "wos_interface_batch", "mc_interface_many", "mc_adjoint", "mc_value_jacobian", "branching_eval", "branching_bvp", "wos_interface",
+           "item_count", "set_schedule", "get_schedule", "save_schedules", "load_schedules",
+           "PDDInterface", "PddError",
            "release_workspace", "query_warnings", "library", "version", "param_layout", "jacobian_blocks",
            "jacobian_apply", "misfit_gradient", "cached_plan_count", "nonlinear"]
 
@@ -271,6 +272,62 @@ def mc_interface_noalloc(problem, nodes, paths, dt: float, seed: int = 0, precis
     res = _stats(out[:n])
     res["_keep"] = keep
     return res
+
+
+def _batch(entry: str, problems, node_problem, nodes, paths, step: float, seed: int, precision: str,
+           layout: Optional[str], max_steps: int, dump: bool, schedule: str, chunk_paths: int, blocks_per_cu: int,
+           refill_groups: int, boundary_correction: bool) -> Dict[str, torch.Tensor]:
+    _need_gpu()
+    keep = _Keep()
+    n_probs = len(problems)
+    arr = (A.pdd_linear_problem * max(1, n_probs))()
+    for k, P in enumerate(problems):
+        arr[k] = _linear(P, keep)
+    keep.append(arr)
+    nt = _dev_f64(nodes)
+    if nt.dim() != 2 or nt.shape[1] != 3:
+        raise ValueError("nodes must have shape (n, 3) (rows padded to three coordinates)")
+    n = nt.shape[0]
+    ph = np.ascontiguousarray(np.asarray(paths, dtype=np.int64).reshape(-1))
+    npb = np.ascontiguousarray(np.asarray(node_problem, dtype=np.int32).reshape(-1))
+    if ph.shape[0] != n or npb.shape[0] != n:
+        raise ValueError("paths and node_problem must have one entry per node")
+    raw = torch.empty((max(n, 1), 5), dtype=torch.float64, device="cuda")
+    dphi, dst = _dumps(dump, ph)
+    o = _options(precision, layout, max_steps, schedule, chunk_paths, blocks_per_cu, refill_groups, dphi, dst,
+                 boundary_correction)
+    st = getattr(library(), entry)(arr, n_probs, npb.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   nt.data_ptr() if n else None, n, ph.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   float(step), int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(),
+                                   _stream_handle())
+    _check(st, entry)
+    res = _stats(raw[:n])
+    if dump:
+        total = int(ph.sum())
+        res["phi"], res["path_steps"] = dphi[:total], dst[:total]
+    res["_keep"] = (keep, nt)
+    return res
+
+
+def mc_interface_batch(problems, node_problem, nodes, paths, dt: float, seed: int = 0, precision: str = "fp32",
+                       layout: Optional[str] = None, max_steps: int = 0, dump: bool = False, schedule: str = "auto",
+                       chunk_paths: int = 0, blocks_per_cu: int = 0, refill_groups: int = 0,
+                       boundary_correction: bool = False) -> Dict[str, torch.Tensor]:
+    """Interface values of a heterogeneous batch of linear problems in one
+    persistent launch (pdd_mc_interface_batch): node i belongs to
+    problems[node_problem[i]] and sits at nodes[i, :dim] (nodes is (n, 3)).
+    Outputs as mc_interface."""
+    return _batch("pdd_mc_interface_batch", problems, node_problem, nodes, paths, dt, seed, precision, layout,
+                  max_steps, dump, schedule, chunk_paths, blocks_per_cu, refill_groups, boundary_correction)
+
+
+def wos_interface_batch(problems, node_problem, nodes, paths, eps: float, seed: int = 0, precision: str = "fp32",
+                        layout: Optional[str] = None, max_steps: int = 0, dump: bool = False, schedule: str = "auto",
+                        chunk_paths: int = 0, blocks_per_cu: int = 0,
+                        refill_groups: int = 0) -> Dict[str, torch.Tensor]:
+    """Walk on Spheres over a heterogeneous batch (pdd_wos_interface_batch)."""
+    return _batch("pdd_wos_interface_batch", problems, node_problem, nodes, paths, eps, seed, precision, layout,
+                  max_steps, dump, schedule, chunk_paths, blocks_per_cu, refill_groups, False)
 
 
 def wos_interface(problem, nodes, paths, eps: float, seed: int = 0, precision: str = "fp32",
@@ -588,16 +645,61 @@ def branching_bvp(problem, boundary, points, trees: int, seed: int = 0, precisio
     return res
 
 
-def item_count(paths, precision: str = "fp32", layout: Optional[str] = None, schedule: str = "auto",
-               chunk_paths: int = 0, blocks_per_cu: int = 0, refill_groups: int = 0) -> int:
-    """Work items (partials slots) mc_interface cuts these budgets into with
-    these schedule options on the current device (pdd_item_count)."""
+_KERNELS = {"walk": A.PDD_KERNEL_WALK, "walk_adjoint": A.PDD_KERNEL_WALK_ADJOINT, "wos": A.PDD_KERNEL_WOS,
+            "walk_batch": A.PDD_KERNEL_WALK_BATCH, "wos_batch": A.PDD_KERNEL_WOS_BATCH,
+            "branch": A.PDD_KERNEL_BRANCH, "branch_bvp": A.PDD_KERNEL_BRANCH_BVP}
+
+
+def item_count(paths, dim: int, kernel: str = "walk", precision: str = "fp32", layout: Optional[str] = None,
+               schedule: str = "auto", chunk_paths: int = 0, blocks_per_cu: int = 0, refill_groups: int = 0) -> int:
+    """Work items (partials slots) a forward call of `kernel` ("walk", "wos",
+    "walk_batch", "wos_batch") in dimension `dim` (0 for the batch kernels)
+    cuts these budgets into with these schedule options on the current device
+    (pdd_item_count)."""
     ph = np.ascontiguousarray(np.asarray(paths, dtype=np.int64).reshape(-1))
     o = _options(precision, layout, 0, schedule, chunk_paths, blocks_per_cu, refill_groups)
-    n = int(library().pdd_item_count(ph.shape[0], ph.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(o)))
+    n = int(library().pdd_item_count(_KERNELS[kernel], int(dim), ph.shape[0],
+                                     ph.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(o)))
     if n < 0:
         _check(n, "pdd_item_count")
     return n
+
+
+def _prec_key(precision: str) -> int:
+    if precision not in ("fp32", "fp64"):
+        raise ValueError("schedules are kept for precision 'fp32' or 'fp64'")
+    return A.PDD_FP32_STEP if precision == "fp32" else A.PDD_FP64
+
+
+def set_schedule(kernel: str, dim: int, precision: str, chunk_paths: Optional[int] = None,
+                 blocks_per_cu: Optional[int] = None, refill_groups: Optional[int] = None):
+    """Sets the current device's schedule-table entry (kernel, dim, precision)
+    (pdd_set_schedule); with every knob None, removes it."""
+    if chunk_paths is None and blocks_per_cu is None and refill_groups is None:
+        st = library().pdd_set_schedule(_KERNELS[kernel], int(dim), _prec_key(precision), None)
+    else:
+        s = A.pdd_launch_schedule(int(chunk_paths), int(blocks_per_cu), int(refill_groups), 0)
+        st = library().pdd_set_schedule(_KERNELS[kernel], int(dim), _prec_key(precision), C.byref(s))
+    _check(st, "pdd_set_schedule")
+
+
+def get_schedule(kernel: str, dim: int, precision: str) -> dict:
+    """The schedule a call would start from (pdd_get_schedule): the table's
+    tuned entry or the built-in default, with `tuned` telling which."""
+    s = A.pdd_launch_schedule()
+    t = C.c_int32(0)
+    _check(library().pdd_get_schedule(_KERNELS[kernel], int(dim), _prec_key(precision), C.byref(s), C.byref(t)),
+           "pdd_get_schedule")
+    return {"chunk_paths": s.chunk_paths, "blocks_per_cu": s.blocks_per_cu, "refill_groups": s.refill_groups,
+            "tuned": bool(t.value)}
+
+
+def save_schedules(path: Optional[str] = None):
+    _check(library().pdd_save_schedules(path.encode() if path else None), "pdd_save_schedules")
+
+
+def load_schedules(path: Optional[str] = None):
+    _check(library().pdd_load_schedules(path.encode() if path else None), "pdd_load_schedules")
 
 
 def query_warnings():

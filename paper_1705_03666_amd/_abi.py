@@ -14,9 +14,13 @@ PDD_DOM_BOX, PDD_DOM_BALL, PDD_DOM_FREE = 0, 1, 2
 PDD_FP64_PLAIN, PDD_FP64, PDD_FP32_STEP = 0, 1, 2
 PDD_RNG_PAIR52, PDD_RNG_QUAD24 = 0, 1
 PDD_SCHED_AUTO, PDD_SCHED_PERSISTENT, PDD_SCHED_PERSISTENT_GRAPH = 0, 1, 2
+(PDD_KERNEL_WALK, PDD_KERNEL_WALK_ADJOINT, PDD_KERNEL_WOS, PDD_KERNEL_WALK_BATCH, PDD_KERNEL_WOS_BATCH,
+ PDD_KERNEL_BRANCH, PDD_KERNEL_BRANCH_BVP) = range(7)
 
-EXPORTED = ["pdd_mc_interface", "pdd_mc_interface_noalloc", "pdd_wos_interface", "pdd_branching_eval", "pdd_branching_bvp", "pdd_mc_adjoint",
-            "pdd_mc_value_jacobian", "pdd_item_count",
+EXPORTED = ["pdd_mc_interface", "pdd_mc_interface_noalloc", "pdd_mc_interface_batch", "pdd_wos_interface_batch",
+            "pdd_wos_interface", "pdd_branching_eval", "pdd_branching_bvp", "pdd_mc_adjoint",
+            "pdd_mc_value_jacobian", "pdd_item_count", "pdd_set_schedule", "pdd_get_schedule",
+            "pdd_save_schedules", "pdd_load_schedules",
             "pdd_param_count", "pdd_jacobian_apply", "pdd_misfit_gradient", "pdd_node_moments",
             "pdd_query_warnings", "pdd_release_workspace", "pdd_cached_plan_count", "pdd_status_string",
             "pdd_last_error", "pdd_version"]
@@ -71,6 +75,11 @@ class pdd_node_stat(C.Structure):
                 ("censored", C.c_int64)]
 
 
+class pdd_launch_schedule(C.Structure):
+    _fields_ = [("chunk_paths", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill_groups", C.c_int32),
+                ("pad", C.c_int32)]
+
+
 class pdd_fun_grad(C.Structure):
     _fields_ = [("dcoef", C.c_void_p), ("dpoly", C.c_void_p)]
 
@@ -82,6 +91,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.pdd_mc_interface.restype = C.c_int
     L.pdd_mc_interface_noalloc.argtypes = L.pdd_mc_interface.argtypes
     L.pdd_mc_interface_noalloc.restype = C.c_int
+    L.pdd_mc_interface_batch.argtypes = [C.POINTER(pdd_linear_problem), C.c_int32, C.POINTER(C.c_int32), C.c_void_p,
+                                         C.c_int64, C.POINTER(C.c_int64), C.c_double, C.c_uint64,
+                                         C.POINTER(pdd_options), C.c_void_p, C.c_void_p]
+    L.pdd_mc_interface_batch.restype = C.c_int
+    L.pdd_wos_interface_batch.argtypes = L.pdd_mc_interface_batch.argtypes
+    L.pdd_wos_interface_batch.restype = C.c_int
     L.pdd_wos_interface.argtypes = L.pdd_mc_interface.argtypes
     L.pdd_wos_interface.restype = C.c_int
     L.pdd_branching_eval.argtypes = [C.POINTER(pdd_branching_problem), C.c_void_p, C.c_int64, C.c_int64, C.c_uint64,
@@ -99,8 +114,17 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                         C.POINTER(C.c_int64), C.c_double, C.c_uint64, C.POINTER(pdd_options),
                                         C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
     L.pdd_mc_value_jacobian.restype = C.c_int
-    L.pdd_item_count.argtypes = [C.c_int64, C.POINTER(C.c_int64), C.POINTER(pdd_options)]
+    L.pdd_item_count.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int64), C.POINTER(pdd_options)]
     L.pdd_item_count.restype = C.c_int64
+    L.pdd_set_schedule.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(pdd_launch_schedule)]
+    L.pdd_set_schedule.restype = C.c_int
+    L.pdd_get_schedule.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(pdd_launch_schedule),
+                                   C.POINTER(C.c_int32)]
+    L.pdd_get_schedule.restype = C.c_int
+    L.pdd_save_schedules.argtypes = [C.c_char_p]
+    L.pdd_save_schedules.restype = C.c_int
+    L.pdd_load_schedules.argtypes = [C.c_char_p]
+    L.pdd_load_schedules.restype = C.c_int
     L.pdd_param_count.argtypes = [C.POINTER(pdd_linear_problem)]
     L.pdd_param_count.restype = C.c_int64
     L.pdd_jacobian_apply.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,

@@ -176,6 +176,7 @@ pdd_status check_device_ptr(const void* p, const char* name) {
 // (0..2 = b, 3 = c, 4 = f, 5 = g; -1 = not recorded).
 struct JobSource {
   int fun, part;
+  int prob;   // problem index within a batch call (0 otherwise)
 };
 
 struct Tables {
@@ -184,10 +185,11 @@ struct Tables {
   std::vector<JobSource> src;
   std::vector<int32_t> perm;
   int ncoef = 0;
+  int cur_prob = 0;   // problem the next functions belong to (batch calls)
 
   void job(const StageJob& j, int fun, int part) {
     jobs.push_back(j);
-    src.push_back(JobSource{fun, part});
+    src.push_back(JobSource{fun, part, cur_prob});
   }
 
   DevFun add(const pdd_fun& F, int dim, int pad_deg, bool nested, int fun = -1) {
@@ -300,6 +302,8 @@ struct Plan {
   WalkLaunch wl{};
   BranchLaunch bl{};
   std::vector<PlainLaunch> pl;
+  bool batch = false;        // heterogeneous batch of linear problems
+  WalkBatchLaunch wbl{};
 
   CallPtrs* d_call = nullptr;   // call block: CallPtrs, then the staging jobs
   StageJob* d_jobs = nullptr;
@@ -352,6 +356,8 @@ struct Plan {
         return hipSuccess;
       } else if (branch) {
         if ((e = launch_branch(bl, st)) != hipSuccess) return e;
+      } else if (batch) {
+        if ((e = launch_walk_batch(wbl, st)) != hipSuccess) return e;
       } else {
         if ((e = launch_walk(wl, st)) != hipSuccess) return e;
       }
@@ -390,6 +396,7 @@ struct Plan {
 // allocated while it is cached (at C5 about 80 MB), so the cache is bounded;
 // an evicted plan is destroyed after its last launch has finished.
 constexpr size_t kMaxPlans = 16;
+constexpr int kMaxBatchProblems = 64;
 std::unordered_map<std::string, std::unique_ptr<Plan>> g_plans;
 uint64_t g_plan_clock = 0;
 
@@ -618,6 +625,92 @@ pdd_status validate_linear(const LinearPlanArgs& a) {
   return PDD_OK;
 }
 
+// The device record of one linear problem (domain, exit-test domain, step,
+// sigma sqrt(dt), censoring cap, seed, where its functions' data sit in the
+// staged tables T); b, c, f polynomials are padded to degree dfc.
+void fill_linear_params(const pdd_linear_problem& P, double dt, const pdd_options& o, bool wos, uint64_t seed,
+                        int dfc, Tables& T, LinearParams& lp) {
+  const int dim = P.domain.dim;
+  lp.dim = dim;
+  lp.dom_kind = P.domain.kind;
+  lp.layout = o.rng_layout;
+  for (int k = 0; k < 3; ++k) {
+    lp.lo[k] = P.domain.lo[k]; lp.hi[k] = P.domain.hi[k]; lp.ctr[k] = P.domain.center[k];
+    lp.lof[k] = (float)lp.lo[k]; lp.hif[k] = (float)lp.hi[k]; lp.ctrf[k] = (float)lp.ctr[k];
+  }
+  lp.rad = P.domain.radius;
+  lp.rad2 = P.domain.radius * P.domain.radius;
+  lp.radf = (float)lp.rad;
+  lp.rad2f = (float)lp.rad2;
+  // exit-test domain: D, or D shrunk by c0 sigma sqrt(dt) (Gobet-Menozzi shift;
+  // c0 = -zeta(1/2)/sqrt(2 pi), zeta(1/2) = -1.4603545088095868...)
+  {
+    const double delta = o.boundary_correction ? (1.4603545088095868 / std::sqrt(2.0 * M_PI)) * P.sigma * std::sqrt(dt)
+                                               : 0.0;
+    double trad = P.domain.radius - delta;
+    if (trad < 0.0) trad = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      lp.tlo[k] = P.domain.lo[k] + delta;
+      lp.thi[k] = P.domain.hi[k] - delta;
+      lp.tlof[k] = (float)lp.tlo[k];
+      lp.thif[k] = (float)lp.thi[k];
+    }
+    lp.trad2 = trad * trad;
+    lp.trad2f = (float)lp.trad2;
+  }
+  lp.dt = dt;
+  lp.sdt = P.sigma * std::sqrt(dt);
+  lp.dtf = (float)lp.dt;
+  lp.sdtf = (float)lp.sdt;
+  lp.max_steps = o.max_steps > 0 ? o.max_steps : (wos ? (int64_t)100000 : (int64_t)std::ceil(100.0 / dt));
+  if (lp.max_steps > 0x7FFFFFFF) lp.max_steps = 0x7FFFFFFF;
+  lp.key0 = (uint32_t)seed;
+  lp.key1 = (uint32_t)(seed >> 32);
+  pdd_fun zero{};
+  zero.poly_degree = -1;
+  for (int k = 0; k < 3; ++k) lp.b[k] = T.add(k < dim ? P.b[k] : zero, dim, dfc, false, k);
+  lp.c = T.add(P.c, dim, dfc, false, 3);
+  lp.f = T.add(P.f, dim, dfc, false, 4);
+  lp.g = T.add(P.g, dim, 0, true, 5);
+  lp.n_fac = (int)T.fac.size();
+  auto nonzero = [](const DevFun& F) { return F.n_terms > 0 || F.poly_deg >= 0; };
+  lp.has_b = nonzero(lp.b[0]) || nonzero(lp.b[1]) || nonzero(lp.b[2]);
+  lp.has_c = nonzero(lp.c);
+  lp.has_f = nonzero(lp.f);
+}
+
+// Captures a plan's launches into a graph (the uploads were ordered before
+// on the caller's stream; the capture runs on a private stream that first
+// waits for them), launches it once and caches it under `key`.
+pdd_status capture_plan(std::unique_ptr<Plan> plan, const std::string& key, hipStream_t st) {
+  Plan& pl = *plan;
+  hipStream_t cap;
+  PDD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipEvent_t ready;
+  PDD_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  PDD_HIP(hipEventRecord(ready, st));
+  PDD_HIP(hipStreamWaitEvent(cap, ready, 0));
+  PDD_HIP(hipStreamSynchronize(cap));
+  PDD_HIP(hipEventDestroy(ready));
+  PDD_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = pl.enqueue(cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cap, &g);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(PDD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  pl.graph = g;
+  PDD_HIP(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
+  PDD_HIP(hipEventCreateWithFlags(&pl.done, hipEventDisableTiming));
+  PDD_HIP(hipGraphLaunch(pl.exec, st));
+  PDD_HIP(hipEventRecord(pl.done, st));
+  std::lock_guard<std::mutex> lk(g_mu);
+  pl.last_use = ++g_plan_clock;
+  evict_plans_locked(kMaxPlans - 1);
+  g_plans[key] = std::move(plan);
+  return PDD_OK;
+}
+
 const double* job_source(const pdd_linear_problem& P, const double* nodes, JobSource js) {
   if (js.part == 3) return nodes;
   if (js.part == 2 || js.fun < 0) return nullptr;
@@ -706,57 +799,13 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   const int dfc = any_poly ? kMaxPolyBCF : -1;
   Tables T;
   LinearParams& lp = pl.lp;
-  lp.dim = dim;
-  lp.dom_kind = P.domain.kind;
-  lp.layout = o.rng_layout;
-  for (int k = 0; k < 3; ++k) {
-    lp.lo[k] = P.domain.lo[k]; lp.hi[k] = P.domain.hi[k]; lp.ctr[k] = P.domain.center[k];
-    lp.lof[k] = (float)lp.lo[k]; lp.hif[k] = (float)lp.hi[k]; lp.ctrf[k] = (float)lp.ctr[k];
-  }
-  lp.rad = P.domain.radius;
-  lp.rad2 = P.domain.radius * P.domain.radius;
-  lp.radf = (float)lp.rad;
-  lp.rad2f = (float)lp.rad2;
-  // exit-test domain: D, or D shrunk by c0 sigma sqrt(dt) (Gobet-Menozzi shift;
-  // c0 = -zeta(1/2)/sqrt(2 pi), zeta(1/2) = -1.4603545088095868...)
-  {
-    const double delta = o.boundary_correction ? (1.4603545088095868 / std::sqrt(2.0 * M_PI)) * P.sigma * std::sqrt(a.dt)
-                                               : 0.0;
-    double trad = P.domain.radius - delta;
-    if (trad < 0.0) trad = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      lp.tlo[k] = P.domain.lo[k] + delta;
-      lp.thi[k] = P.domain.hi[k] - delta;
-      lp.tlof[k] = (float)lp.tlo[k];
-      lp.thif[k] = (float)lp.thi[k];
-    }
-    lp.trad2 = trad * trad;
-    lp.trad2f = (float)lp.trad2;
-  }
-  lp.dt = a.dt;
-  lp.sdt = P.sigma * std::sqrt(a.dt);
-  lp.dtf = (float)lp.dt;
-  lp.sdtf = (float)lp.sdt;
-  lp.max_steps = o.max_steps > 0 ? o.max_steps : (a.wos ? (int64_t)100000 : (int64_t)std::ceil(100.0 / a.dt));
-  if (lp.max_steps > 0x7FFFFFFF) lp.max_steps = 0x7FFFFFFF;
-  lp.key0 = (uint32_t)a.seed;
-  lp.key1 = (uint32_t)(a.seed >> 32);
-  pdd_fun zero{};
-  zero.poly_degree = -1;
-  for (int k = 0; k < 3; ++k) lp.b[k] = T.add(k < dim ? P.b[k] : zero, dim, dfc, false, k);
-  lp.c = T.add(P.c, dim, dfc, false, 3);
-  lp.f = T.add(P.f, dim, dfc, false, 4);
-  lp.g = T.add(P.g, dim, 0, true, 5);
-  lp.n_fac = (int)T.fac.size();
-  auto nonzero = [](const DevFun& F) { return F.n_terms > 0 || F.poly_deg >= 0; };
-  lp.has_b = nonzero(lp.b[0]) || nonzero(lp.b[1]) || nonzero(lp.b[2]);
-  lp.has_c = nonzero(lp.c);
-  lp.has_f = nonzero(lp.f);
+  fill_linear_params(P, a.dt, o, a.wos, a.seed, dfc, T, lp);
 
   // ---- work items
   int64_t total_paths = 0;
   for (int64_t i = 0; i < a.n_nodes; ++i) total_paths += a.paths[i];
-  const Tuning tune = choose_tuning(dim, fp32, a.adjoint, o, device_cus(), total_paths);
+  const int kernel = a.adjoint ? PDD_KERNEL_WALK_ADJOINT : (a.wos ? PDD_KERNEL_WOS : PDD_KERNEL_WALK);
+  const Tuning tune = choose_schedule(kernel, dim, fp32 ? PDD_FP32_STEP : PDD_FP64, o, device_cus(), total_paths);
   std::vector<double> cost((size_t)a.n_nodes);
   for (int64_t i = 0; i < a.n_nodes; ++i) cost[(size_t)i] = 0.0;
   std::vector<double> hnodes((size_t)a.n_nodes * dim);
@@ -1014,33 +1063,223 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     if (a.fixed == nullptr) PDD_HIP(hipFreeAsync(pl.arena, st));
     return PDD_OK;
   }
-  // graph: uploads are ordered before capture on the caller's stream; the
-  // capture runs on a private stream that first waits for them
-  hipStream_t cap;
-  PDD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-  hipEvent_t ready;
-  PDD_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-  PDD_HIP(hipEventRecord(ready, st));
-  PDD_HIP(hipStreamWaitEvent(cap, ready, 0));
-  PDD_HIP(hipStreamSynchronize(cap));
-  PDD_HIP(hipEventDestroy(ready));
-  PDD_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  hipError_t e = pl.enqueue(cap);
-  hipGraph_t g = nullptr;
-  hipError_t e2 = hipStreamEndCapture(cap, &g);
-  (void)hipStreamDestroy(cap);
-  if (e != hipSuccess || e2 != hipSuccess)
-    return fail(PDD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
-  pl.graph = g;
-  PDD_HIP(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
-  PDD_HIP(hipEventCreateWithFlags(&pl.done, hipEventDisableTiming));
-  PDD_HIP(hipGraphLaunch(pl.exec, st));
-  PDD_HIP(hipEventRecord(pl.done, st));
-  std::lock_guard<std::mutex> lk(g_mu);
-  pl.last_use = ++g_plan_clock;
-  evict_plans_locked(kMaxPlans - 1);
-  g_plans[key] = std::move(plan);
-  return PDD_OK;
+  return capture_plan(std::move(plan), key, st);
+}
+
+// ---------------------------------------------------------------------------- batch of problems
+struct BatchArgs {
+  const pdd_linear_problem* probs;
+  int32_t n_probs;
+  const int32_t* node_prob;   // host [n_nodes]
+  const double* nodes;        // device [n_nodes][3]
+  int64_t n_nodes;
+  const int64_t* paths;
+  double dt;                  // Euler step, or the walk-on-spheres shell width
+  uint64_t seed;
+  pdd_options opt;
+  pdd_node_stat* out;
+  bool wos;
+};
+
+pdd_status run_linear_batch(const BatchArgs& a, hipStream_t st) {
+  if (a.probs == nullptr) return fail(PDD_ERR_INVALID_ARG, "problems is NULL");
+  if (a.n_probs < 1 || a.n_probs > kMaxBatchProblems)
+    return fail(PDD_ERR_INVALID_ARG, "n_problems must be 1.." + std::to_string(kMaxBatchProblems));
+  const pdd_options& o = a.opt;
+  pdd_status s;
+  for (int k = 0; k < a.n_probs; ++k) {
+    LinearPlanArgs v{&a.probs[k], nullptr, 0, nullptr, a.dt, a.seed, o, a.out, false, nullptr, nullptr, nullptr, 0};
+    v.wos = a.wos;
+    if ((s = validate_linear(v)) != PDD_OK) return fail(s, "problem " + std::to_string(k) + ": " + pdd_last_error());
+    const pdd_linear_problem& P = a.probs[k];
+    bool terms = P.c.n_terms > 0 || P.f.n_terms > 0;
+    for (int d = 0; d < P.domain.dim; ++d) terms = terms || P.b[d].n_terms > 0;
+    if (terms)
+      return fail(PDD_ERR_UNSUPPORTED, "problem " + std::to_string(k) +
+                                           ": the batch takes b, c, f as dense polynomials (no generic terms)");
+  }
+  if (o.precision == PDD_FP64_PLAIN) return fail(PDD_ERR_UNSUPPORTED, "the batch has no plain variant");
+  if (o.skip_items || o.partials) return fail(PDD_ERR_UNSUPPORTED, "skip_items / partials: single-problem calls only");
+  if (a.n_nodes < 0 || a.n_nodes > (int64_t)1 << 30) return fail(PDD_ERR_INVALID_ARG, "n_nodes out of range");
+  if (a.n_nodes == 0) return PDD_OK;
+  if (a.paths == nullptr || a.node_prob == nullptr) return fail(PDD_ERR_INVALID_ARG, "paths_host or node_problem is NULL");
+  int64_t total_paths = 0;
+  for (int64_t i = 0; i < a.n_nodes; ++i) {
+    if (a.paths[i] < 0 || a.paths[i] > (int64_t)0x7FFFFFFF)
+      return fail(PDD_ERR_INVALID_ARG, "paths per node must be in [0, 2^31)");
+    if (a.node_prob[i] < 0 || a.node_prob[i] >= a.n_probs)
+      return fail(PDD_ERR_INVALID_ARG, "node_problem entry out of range");
+    total_paths += a.paths[i];
+  }
+  if ((s = check_device_ptr(a.nodes, "nodes_dev")) != PDD_OK) return s;
+  if ((s = check_device_ptr(a.out, "out_dev")) != PDD_OK) return s;
+  const bool fp32 = o.precision == PDD_FP32_STEP;
+  const bool graph = (o.schedule == PDD_SCHED_AUTO || o.schedule == PDD_SCHED_PERSISTENT_GRAPH) &&
+                     o.dump_phi == nullptr;
+  auto sources = [&](const std::vector<StageJob>& tmpl, const std::vector<JobSource>& src) {
+    std::vector<StageJob> jobs = tmpl;
+    for (size_t j = 0; j < jobs.size(); ++j) jobs[j].src = job_source(a.probs[src[j].prob], a.nodes, src[j]);
+    return jobs;
+  };
+  CallPtrs cp{};
+  cp.out = a.out;
+
+  std::string key;
+  if (graph) {
+    key_add(key, a.wos ? 5 : 4);
+    int dev = 0;
+    PDD_HIP(hipGetDevice(&dev));
+    key_add(key, dev);
+    key_add(key, st);
+    key_add(key, a.n_probs);
+    for (int k = 0; k < a.n_probs; ++k) {
+      const pdd_linear_problem& P = a.probs[k];
+      key_add(key, P.domain);
+      key_add(key, P.sigma);
+      for (int d = 0; d < 3; ++d) key_fun(key, P.b[d]);
+      key_fun(key, P.c);
+      key_fun(key, P.f);
+      key_fun(key, P.g);
+    }
+    key_add(key, a.n_nodes);
+    key.append(reinterpret_cast<const char*>(a.node_prob), sizeof(int32_t) * (size_t)a.n_nodes);
+    key.append(reinterpret_cast<const char*>(a.paths), sizeof(int64_t) * (size_t)a.n_nodes);
+    key_add(key, a.dt);
+    key_add(key, a.seed);
+    key_add(key, o);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+      Plan& hp = *it->second;
+      hp.last_use = ++g_plan_clock;
+      const std::vector<char> img = call_block_image(cp, sources(hp.jobs_host, hp.job_src));
+      PDD_HIP(hipMemcpyAsync(hp.d_call, img.data(), img.size(), hipMemcpyHostToDevice, st));
+      PDD_HIP(hipGraphLaunch(hp.exec, st));
+      PDD_HIP(hipEventRecord(hp.done, st));
+      return PDD_OK;
+    }
+  }
+
+  std::unique_ptr<Plan> plan(new Plan());
+  Plan& pl = *plan;
+  pl.batch = true;
+  PDD_HIP(hipGetDevice(&pl.device));
+  if ((s = counters(&pl.ctr)) != PDD_OK) return s;
+
+  // ---- per-problem records and the shared tables
+  Tables T;
+  std::vector<LinearParams> lps((size_t)a.n_probs);
+  for (int k = 0; k < a.n_probs; ++k) {
+    T.cur_prob = k;
+    fill_linear_params(a.probs[k], a.dt, o, a.wos, a.seed, kMaxPolyBCF, T, lps[(size_t)k]);
+  }
+  T.cur_prob = 0;
+
+  // ---- work items: one queue over every problem's nodes
+  const Tuning tune = choose_schedule(a.wos ? PDD_KERNEL_WOS_BATCH : PDD_KERNEL_WALK_BATCH, 0,
+                                      fp32 ? PDD_FP32_STEP : PDD_FP64, o, device_cus(), total_paths);
+  std::vector<double> hnodes((size_t)a.n_nodes * 3);
+  PDD_HIP(hipMemcpyAsync(hnodes.data(), a.nodes, hnodes.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  PDD_HIP(hipStreamSynchronize(st));
+  std::vector<double> cost((size_t)a.n_nodes);
+  for (int64_t i = 0; i < a.n_nodes; ++i)
+    cost[(size_t)i] = est_steps(a.probs[a.node_prob[i]], &hnodes[(size_t)i * 3], a.dt);
+  Items items = make_items(a.n_nodes, a.paths, 0, tune.chunk_paths, cost);
+  const int n_items = (int)items.q.size();
+  pl.n_items = n_items;
+  pl.n_nodes = a.n_nodes;
+  std::vector<int64_t> doff((size_t)a.n_nodes + 1, 0);
+  for (int64_t i = 0; i < a.n_nodes; ++i) doff[(size_t)i + 1] = doff[(size_t)i] + a.paths[i];
+
+  // ---- arena
+  Arena A;
+  const size_t o_call = add_call_block(A, T.jobs.size() + 1);
+  const size_t o_nodes = A.add(sizeof(double) * (size_t)a.n_nodes * 3);
+  const size_t o_perm = A.add(sizeof(int32_t) * std::max<size_t>(1, T.perm.size()));
+  const size_t o_fac = A.add(sizeof(DevFactor) * std::max<size_t>(1, T.fac.size()));
+  const size_t o_cd = A.add(sizeof(double) * std::max(1, T.ncoef));
+  const size_t o_cf = A.add(sizeof(float) * std::max(1, T.ncoef));
+  const size_t o_q = A.add(sizeof(uint32_t) * 4);
+  const size_t o_items = A.add(sizeof(WorkItem) * std::max(1, n_items));
+  const size_t o_istat = A.add(sizeof(ItemStat) * std::max(1, n_items));
+  const size_t o_first = A.add(sizeof(int64_t) * ((size_t)a.n_nodes + 1));
+  const size_t o_doff = A.add(sizeof(int64_t) * ((size_t)a.n_nodes + 1));
+  const size_t o_probs = A.add(sizeof(LinearParams) * (size_t)a.n_probs);
+  const size_t o_nprob = A.add(sizeof(int32_t) * (size_t)a.n_nodes);
+  if (graph) {
+    PDD_HIP(hipMalloc(&pl.arena, A.total));
+    pl.owned = true;
+  } else {
+    PDD_HIP(arena_alloc(&pl.arena, A.total, st));
+  }
+  char* base = (char*)pl.arena;
+  pl.d_call = (CallPtrs*)(base + o_call);
+  pl.d_jobs = (StageJob*)(base + o_call + kJobsOff);
+  pl.d_nodes = (double*)(base + o_nodes);
+  T.job(StageJob{a.nodes, pl.d_nodes, 0, (int32_t)(a.n_nodes * 3), -1, 0}, -1, 3);
+  pl.n_jobs = (int)T.jobs.size();
+  pl.jobs_host = T.jobs;
+  pl.job_src = T.src;
+  pl.d_perm = (int32_t*)(base + o_perm);
+  pl.d_cd = (double*)(base + o_cd);
+  pl.d_cf = (float*)(base + o_cf);
+  pl.d_qhead = (uint32_t*)(base + o_q);
+  pl.d_istat = (ItemStat*)(base + o_istat);
+  pl.d_first = (int64_t*)(base + o_first);
+  pl.has_out = true;
+  for (auto& lp : lps) {
+    lp.fac = (const DevFactor*)(base + o_fac);
+    lp.cd = pl.d_cd;
+    lp.cf = pl.d_cf;
+    lp.nodes = pl.d_nodes;
+  }
+  std::vector<int32_t> nprob(a.node_prob, a.node_prob + a.n_nodes);
+  std::vector<Upload> ups;
+  put(ups, o_call, call_block_image(cp, sources(T.jobs, T.src)));
+  put(ups, o_perm, T.perm);
+  put(ups, o_fac, T.fac);
+  put(ups, o_items, items.q);
+  put(ups, o_first, items.first);
+  put(ups, o_doff, doff);
+  put(ups, o_probs, lps);
+  put(ups, o_nprob, nprob);
+  for (const auto& u : ups)
+    if (!u.bytes.empty()) PDD_HIP(hipMemcpyAsync(base + u.off, u.bytes.data(), u.bytes.size(), hipMemcpyHostToDevice, st));
+
+  WalkBatchLaunch& L = pl.wbl;
+  L.probs = (const LinearParams*)(base + o_probs);
+  L.node_prob = (const int32_t*)(base + o_nprob);
+  L.nodes = pl.d_nodes;
+  L.fac = (const DevFactor*)(base + o_fac);
+  L.cd = pl.d_cd;
+  L.cf = pl.d_cf;
+  L.key0 = (uint32_t)a.seed;
+  L.key1 = (uint32_t)(a.seed >> 32);
+  L.fp32 = fp32;
+  L.layout = o.rng_layout;
+  L.wos = a.wos;
+  const int max_blocks = tune.blocks_per_cu * device_cus();
+  const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
+  L.grid = std::max(1, std::min(max_blocks, need));
+  L.items = (const WorkItem*)(base + o_items);
+  L.n_items = n_items;
+  L.qhead = pl.d_qhead;
+  L.istat = pl.d_istat;
+  L.dump_phi = o.dump_phi;
+  L.dump_steps = o.dump_steps;
+  L.dump_off = (const int64_t*)(base + o_doff);
+  L.refill_groups = tune.refill_groups;
+
+  if (!graph) {
+    hipError_t e = pl.enqueue(st);
+    if (e != hipSuccess) {
+      (void)hipFreeAsync(pl.arena, st);
+      return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    PDD_HIP(hipFreeAsync(pl.arena, st));
+    return PDD_OK;
+  }
+  return capture_plan(std::move(plan), key, st);
 }
 
 }  // namespace
@@ -1217,7 +1456,8 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   Tables T;
   BranchParams& bp = pl.bp;
   fill_branch_params(B, seed, T, bp);
-  const Tuning tune = choose_branch_tuning(B.dim, fp32, o, device_cus(), n_points * trees);
+  const Tuning tune = choose_schedule(PDD_KERNEL_BRANCH, B.dim, fp32 ? PDD_FP32_STEP : PDD_FP64, o, device_cus(),
+                                      n_points * trees);
   Items items = make_items(n_points, nullptr, trees, tune.chunk_paths, {});
   const int n_items = (int)items.q.size();
   const int max_blocks = tune.blocks_per_cu * device_cus();
@@ -1369,7 +1609,8 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   bb.g = T.add(Bd.g, B.dim, 0, true);
   bp.n_fac = (int)T.fac.size();
 
-  const Tuning tune = choose_branch_tuning(B.dim, fp32, o, device_cus(), n_points * trees);
+  const Tuning tune = choose_schedule(PDD_KERNEL_BRANCH_BVP, B.dim, fp32 ? PDD_FP32_STEP : PDD_FP64, o,
+                                      device_cus(), n_points * trees);
   Items items = make_items(n_points, nullptr, trees, tune.chunk_paths, {});
   const int n_items = (int)items.q.size();
   const int max_blocks = tune.blocks_per_cu * device_cus();
@@ -1454,6 +1695,38 @@ pdd_status pdd_mc_interface(const pdd_linear_problem* problem, const double* nod
     LinearPlanArgs a{problem, nodes_dev, n_nodes, paths_host, dt, seed, *options, out_dev, false, nullptr, nullptr,
                      nullptr, 0};
     return run_linear(a, (hipStream_t)hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_mc_interface_batch(const pdd_linear_problem* problems, int32_t n_problems,
+                                  const int32_t* node_problem_host, const double* nodes_dev, int64_t n_nodes,
+                                  const int64_t* paths_host, double dt, uint64_t seed, const pdd_options* options,
+                                  pdd_node_stat* out_dev, void* hip_stream) {
+  try {
+    if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
+    BatchArgs a{problems, n_problems, node_problem_host, nodes_dev, n_nodes, paths_host, dt, seed, *options,
+                out_dev, false};
+    return run_linear_batch(a, (hipStream_t)hip_stream);
+  } catch (const std::bad_alloc&) {
+    return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_wos_interface_batch(const pdd_linear_problem* problems, int32_t n_problems,
+                                   const int32_t* node_problem_host, const double* nodes_dev, int64_t n_nodes,
+                                   const int64_t* paths_host, double eps, uint64_t seed, const pdd_options* options,
+                                   pdd_node_stat* out_dev, void* hip_stream) {
+  try {
+    if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
+    BatchArgs a{problems, n_problems, node_problem_host, nodes_dev, n_nodes, paths_host, eps, seed, *options,
+                out_dev, true};
+    return run_linear_batch(a, (hipStream_t)hip_stream);
   } catch (const std::bad_alloc&) {
     return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
   } catch (...) {
@@ -1556,9 +1829,15 @@ pdd_status pdd_query_warnings(void* hip_stream, int64_t* censored_out, int64_t* 
   return PDD_OK;
 }
 
-int64_t pdd_item_count(int64_t n_nodes, const int64_t* paths_host, const pdd_options* options) {
+int64_t pdd_item_count(int32_t kernel, int32_t dim, int64_t n_nodes, const int64_t* paths_host,
+                       const pdd_options* options) {
   try {
     if (options == nullptr) return fail(PDD_ERR_INVALID_ARG, "options is NULL");
+    if (kernel != PDD_KERNEL_WALK && kernel != PDD_KERNEL_WOS && kernel != PDD_KERNEL_WALK_BATCH &&
+        kernel != PDD_KERNEL_WOS_BATCH)
+      return fail(PDD_ERR_INVALID_ARG, "kernel must be a forward walk kind");
+    const bool batch = kernel == PDD_KERNEL_WALK_BATCH || kernel == PDD_KERNEL_WOS_BATCH;
+    if (batch ? dim != 0 : (dim < 1 || dim > 3)) return fail(PDD_ERR_INVALID_ARG, "dim out of range");
     if (n_nodes < 0 || n_nodes > (int64_t)1 << 30) return fail(PDD_ERR_INVALID_ARG, "n_nodes out of range");
     if (n_nodes > 0 && paths_host == nullptr) return fail(PDD_ERR_INVALID_ARG, "paths_host is NULL");
     const pdd_options& o = *options;
@@ -1571,10 +1850,50 @@ int64_t pdd_item_count(int64_t n_nodes, const int64_t* paths_host, const pdd_opt
         return fail(PDD_ERR_INVALID_ARG, "paths per node must be in [0, 2^31)");
       total += paths_host[i];
     }
-    const Tuning tune = choose_tuning(0, o.precision == PDD_FP32_STEP, false, o, device_cus(), total);
+    const Tuning tune = choose_schedule(kernel, dim, o.precision == PDD_FP32_STEP ? PDD_FP32_STEP : PDD_FP64, o,
+                                        device_cus(), total);
     return (int64_t)make_items(n_nodes, paths_host, 0, tune.chunk_paths, {}).q.size();
   } catch (const std::bad_alloc&) {
     return fail(PDD_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_set_schedule(int32_t kernel, int32_t dim, int32_t precision, const pdd_launch_schedule* s) {
+  try {
+    if (!schedule_kind_valid(kernel, dim, precision)) return fail(PDD_ERR_INVALID_ARG, "unknown schedule key");
+    if (set_schedule(kernel, dim, precision, s) != 0) return fail(PDD_ERR_INVALID_ARG, "schedule out of range");
+    return PDD_OK;
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_get_schedule(int32_t kernel, int32_t dim, int32_t precision, pdd_launch_schedule* out, int32_t* tuned) {
+  try {
+    if (!schedule_kind_valid(kernel, dim, precision)) return fail(PDD_ERR_INVALID_ARG, "unknown schedule key");
+    if (out == nullptr) return fail(PDD_ERR_INVALID_ARG, "out is NULL");
+    get_schedule(kernel, dim, precision, out, tuned);
+    return PDD_OK;
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_save_schedules(const char* path) {
+  try {
+    if (save_schedules(path) != 0) return fail(PDD_ERR_INVALID_ARG, "cannot write the schedule file");
+    return PDD_OK;
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_load_schedules(const char* path) {
+  try {
+    if (load_schedules(path) < 0) return fail(PDD_ERR_INVALID_ARG, "cannot read the schedule file");
+    return PDD_OK;
   } catch (...) {
     return fail(PDD_ERR_HIP, "unexpected exception");
   }

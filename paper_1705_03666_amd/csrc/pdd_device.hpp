@@ -391,9 +391,31 @@ __device__ __forceinline__ bool inside(const Dom<R>& D, const R* x) {
 }
 
 // Distance from x to the boundary of D (negative outside): ball R - |x - c|,
-// box min_k min(x_k - lo_k, hi_k - x_k).
+// box min_k min(x_k - lo_k, hi_k - x_k).  FP64: every product and sum rounded
+// on its own (no fused multiply-add), so that walk-on-spheres paths, whose
+// jumps amplify rounding differences, follow the oracle's arithmetic exactly.
 template <typename R, int DIM>
 __device__ __forceinline__ R boundary_distance(const Dom<R>& D, const R* x) {
+  if constexpr (sizeof(R) == 8) {
+#pragma clang fp contract(off)
+    if (D.kind == DOM_BOX) {
+      R m = x[0] - D.lo[0];
+      m = fmin(m, D.hi[0] - x[0]);
+#pragma unroll
+      for (int k = 1; k < DIM; ++k) {
+        m = fmin(m, x[k] - D.lo[k]);
+        m = fmin(m, D.hi[k] - x[k]);
+      }
+      return m;
+    }
+    R r2 = (R)0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const R d = x[k] - D.ctr[k];
+      r2 += d * d;
+    }
+    return D.rad - sqrt(r2);
+  }
   if (D.kind == DOM_BOX) {
     R m = x[0] - D.lo[0];
     m = fmin(m, D.hi[0] - x[0]);
@@ -413,22 +435,42 @@ __device__ __forceinline__ R boundary_distance(const Dom<R>& D, const R* x) {
   return D.rad - sqrt(r2);
 }
 
-// x += r z / |z| (z2 = |z|^2): FP64 in the order r (z_k / |z|); FP32 with the
-// hardware reciprocal square root.
+// |z|^2 of one jump's Gaussians (FP64 without fused multiply-add, as above).
+template <typename R, int DIM>
+__device__ __forceinline__ R sum_squares(const R* z) {
+  if constexpr (sizeof(R) == 8) {
+#pragma clang fp contract(off)
+    R s = (R)0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) s += z[k] * z[k];
+    return s;
+  }
+  R s = (R)0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) s += z[k] * z[k];
+  return s;
+}
+
+// x += r z / |z| (z2 = |z|^2): FP64 in the order r (z_k / |z|) with every
+// operation rounded on its own (IEEE square root and division, no fused
+// multiply-add); FP32 with the hardware reciprocal square root.
 template <typename R, int DIM>
 __device__ __forceinline__ void jump_sphere(R* x, R r, R z2, const R* z);
 template <>
 __device__ __forceinline__ void jump_sphere<double, 1>(double* x, double r, double z2, const double* z) {
+#pragma clang fp contract(off)
   const double zn = sqrt(z2);
   x[0] = x[0] + r * (z[0] / zn);
 }
 template <>
 __device__ __forceinline__ void jump_sphere<double, 2>(double* x, double r, double z2, const double* z) {
+#pragma clang fp contract(off)
   const double zn = sqrt(z2);
   for (int k = 0; k < 2; ++k) x[k] = x[k] + r * (z[k] / zn);
 }
 template <>
 __device__ __forceinline__ void jump_sphere<double, 3>(double* x, double r, double z2, const double* z) {
+#pragma clang fp contract(off)
   const double zn = sqrt(z2);
   for (int k = 0; k < 3; ++k) x[k] = x[k] + r * (z[k] / zn);
 }

@@ -35,6 +35,29 @@ struct WalkLaunch {
   int refill_groups;
 };
 
+// Heterogeneous batch (walk_batch.hip): per-problem records, node -> problem.
+struct WalkBatchLaunch {
+  const LinearParams* probs;   // device [n_problems]
+  const int32_t* node_prob;    // device [n_nodes]
+  const double* nodes;         // device [n_nodes][3]
+  const DevFactor* fac;
+  const double* cd;
+  const float* cf;
+  uint32_t key0, key1;
+  bool fp32;
+  int layout;
+  bool wos;
+  int grid;
+  const WorkItem* items;
+  int n_items;
+  uint32_t* qhead;
+  ItemStat* istat;
+  double* dump_phi;
+  int64_t* dump_steps;
+  const int64_t* dump_off;
+  int refill_groups;
+};
+
 struct PlainLaunch {
   const LinearParams* P;
   int dfc;
@@ -88,6 +111,7 @@ struct BranchBvpLaunch {
 };
 
 hipError_t launch_walk(const WalkLaunch& L, hipStream_t st);
+hipError_t launch_walk_batch(const WalkBatchLaunch& L, hipStream_t st);
 hipError_t launch_plain(const PlainLaunch& L, hipStream_t st);
 hipError_t launch_plain_adj(const PlainLaunch& L, hipStream_t st);
 hipError_t launch_branch(const BranchLaunch& L, hipStream_t st);

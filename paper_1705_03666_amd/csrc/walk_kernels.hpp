@@ -535,9 +535,7 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
                 alive = false;
                 fin = true;
               } else {
-                R z2 = (R)0;
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) z2 += z[s * DIM + k] * z[s * DIM + k];
+                const R z2 = sum_squares<R, DIM>(&z[s * DIM]);
                 jump_sphere<R, DIM>(X, r, z2, &z[s * DIM]);
                 ++n;
               }

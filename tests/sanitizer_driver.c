@@ -36,7 +36,7 @@ int main(void) {
   H.b[0] = (orc_fun){0, 0, NULL, NULL, 0, 0, mexp, mcoef};
   H.c = H.b[0];
   H.f = H.b[0];
-  rc |= orc_wos(&H, nodes, 3, paths, 1e-3, 7, ORC_PAIR52, 100000, 4, st, NULL, NULL);
+  rc |= orc_wos(&H, nodes, 3, paths, 1e-3, 7, ORC_PAIR52, 100000, 4, st, NULL, NULL, NULL);
   orc_branching B;
   memset(&B, 0, sizeof B);
   B.dim = 2; B.max_segments = 64; B.sigma = 1.0; B.beta = 1.0; B.T = 0.7;

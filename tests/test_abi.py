@@ -263,13 +263,16 @@ def test_item_count_and_resume_options_on_the_host(abi):
     and the plain baseline refuse them."""
     lib = abi.load()
     o = _opts(abi)
+    W = abi.PDD_KERNEL_WALK
     for paths in ([100000] * 10, [1000, 20000, 3, 0, 77777], [5000] * 3000):
         ph = (C.c_int64 * len(paths))(*paths)
-        assert lib.pdd_item_count(len(paths), ph, C.byref(o)) == _items_expected(paths)
+        assert lib.pdd_item_count(W, 3, len(paths), ph, C.byref(o)) == _items_expected(paths)
     o64 = _opts(abi, precision=abi.PDD_FP64, layout=abi.PDD_RNG_PAIR52)
     ph = (C.c_int64 * 3)(300000, 1, 40000)
-    assert lib.pdd_item_count(3, ph, C.byref(o64)) == _items_expected([300000, 1, 40000], fp32=False)
-    assert lib.pdd_item_count(1, None, C.byref(o)) == abi.PDD_ERR_INVALID_ARG
+    assert lib.pdd_item_count(W, 2, 3, ph, C.byref(o64)) == _items_expected([300000, 1, 40000], fp32=False)
+    assert lib.pdd_item_count(W, 1, 1, None, C.byref(o)) == abi.PDD_ERR_INVALID_ARG
+    assert lib.pdd_item_count(W, 0, 3, ph, C.byref(o)) == abi.PDD_ERR_INVALID_ARG       # dim 0: batch kinds only
+    assert lib.pdd_item_count(abi.PDD_KERNEL_BRANCH, 3, 3, ph, C.byref(o)) == abi.PDD_ERR_INVALID_ARG
     p = _problem(abi)
     paths = (C.c_int64 * 1)(10)
     skip = (C.c_uint8 * 4)(0, 1, 0, 0)
@@ -280,6 +283,43 @@ def test_item_count_and_resume_options_on_the_host(abi):
     op = _opts(abi, precision=abi.PDD_FP64_PLAIN, layout=abi.PDD_RNG_PAIR52)
     op.partials = 1
     assert lib.pdd_mc_interface(C.byref(p), None, 1, paths, 1e-3, 0, C.byref(op), None, None) == abi.PDD_ERR_UNSUPPORTED
+
+
+def test_schedule_table_set_get_save_load_and_item_size(abi, tmp_path):
+    """A tuned entry replaces the default for its (kernel, dim, precision) key
+    only, changes the work-item decomposition calls would use, survives a
+    save / remove / load round trip, and out-of-range entries are refused."""
+    lib = abi.load()
+    S = abi.pdd_launch_schedule
+    W, FP32 = abi.PDD_KERNEL_WALK, abi.PDD_FP32_STEP
+    out, tuned = S(), C.c_int32(0)
+    assert lib.pdd_set_schedule(W, 2, FP32, None) == 0
+    assert lib.pdd_get_schedule(W, 2, FP32, C.byref(out), C.byref(tuned)) == 0
+    assert (out.chunk_paths, out.blocks_per_cu, out.refill_groups, tuned.value) == (16384, 8, 3, 0)
+    o = _opts(abi)
+    paths = [400000] * 200
+    ph = (C.c_int64 * len(paths))(*paths)
+    base = lib.pdd_item_count(W, 2, len(paths), ph, C.byref(o))
+    assert base == _items_expected(paths)
+    assert lib.pdd_set_schedule(W, 2, FP32, C.byref(S(4096, 2, 5, 0))) == 0
+    assert lib.pdd_get_schedule(W, 2, FP32, C.byref(out), C.byref(tuned)) == 0
+    assert (out.chunk_paths, out.blocks_per_cu, out.refill_groups, tuned.value) == (4096, 2, 5, 1)
+    n_small = lib.pdd_item_count(W, 2, len(paths), ph, C.byref(o))
+    n_per = (400000 - 50000) // 4096 + -(-(400000 - ((400000 - 50000) // 4096) * 4096) // 512)
+    assert n_small == 200 * n_per
+    assert lib.pdd_item_count(W, 3, len(paths), ph, C.byref(o)) == base       # other dim: default
+    f = str(tmp_path / "sub" / "sched.txt")
+    assert lib.pdd_save_schedules(f.encode()) == 0
+    assert lib.pdd_set_schedule(W, 2, FP32, None) == 0
+    assert lib.pdd_item_count(W, 2, len(paths), ph, C.byref(o)) == base
+    assert lib.pdd_load_schedules(f.encode()) == 0
+    assert lib.pdd_item_count(W, 2, len(paths), ph, C.byref(o)) == n_small
+    assert "4096 2 5" in open(f).read()
+    assert lib.pdd_set_schedule(W, 2, FP32, C.byref(S(0, 2, 5, 0))) == abi.PDD_ERR_INVALID_ARG
+    assert lib.pdd_set_schedule(W, 2, abi.PDD_FP64_PLAIN, C.byref(S(1024, 2, 5, 0))) == abi.PDD_ERR_INVALID_ARG
+    assert lib.pdd_set_schedule(9, 2, FP32, C.byref(S(1024, 2, 5, 0))) == abi.PDD_ERR_INVALID_ARG
+    assert lib.pdd_load_schedules(str(tmp_path / "missing.txt").encode()) == abi.PDD_ERR_INVALID_ARG
+    assert lib.pdd_set_schedule(W, 2, FP32, None) == 0
 
 
 def test_status_strings(abi):

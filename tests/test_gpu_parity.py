@@ -268,7 +268,7 @@ def test_fault_and_resume_reproduce_the_full_run_bitwise(pdd, precision):
     p = parts[7]
     nodes, paths = p.nodes[:40], p.paths[:40] * 3
     kw = dict(precision=precision, schedule="persistent", chunk_paths=512)
-    n_items = pdd.item_count(paths, **kw)
+    n_items = pdd.item_count(paths, p.problem.domain.ndim, **kw)
     assert n_items > 40
     full_p = torch.zeros((n_items, 6), dtype=torch.float64, device="cuda")
     full = pdd.mc_interface(p.problem, nodes, paths, p.dt, 4, partials=full_p, **kw)

@@ -225,6 +225,40 @@ def c3(scale: float = 1.0, dt: float = 1e-3, seed: int = 0, n_nodes: int = 4096,
     return out
 
 
+@dataclass
+class BatchWorkload:
+    """A heterogeneous batch: node i belongs to problems[node_problem[i]] and
+    sits at nodes[i, :ndim] (rows padded to three coordinates)."""
+    name: str
+    problems: List[LinearProblem]
+    node_problem: np.ndarray   # (n,) int32
+    nodes: np.ndarray          # (n, 3)
+    paths: np.ndarray          # (n,) int64
+    dt: float
+    seed: int
+    exact: np.ndarray          # (n,) exact solution (harmonic data)
+
+
+def c3_batch(scale: float = 1.0, dt: float = 1e-3, seed: int = 0, n_nodes: int = 4096,
+             workload_seed: int = 3) -> BatchWorkload:
+    """C3 as one batch: the same 4096 nodes, budgets and layouts as c3(), in
+    the order they were drawn (node i of the batch is the i-th draw), so the
+    eight layouts interleave in one node list."""
+    rng = np.random.default_rng(workload_seed)
+    layout_of = rng.integers(len(C3_LAYOUTS), size=n_nodes)
+    parts = c3(scale, dt, seed, n_nodes, workload_seed)
+    nodes = np.zeros((n_nodes, 3))
+    paths = np.zeros(n_nodes, np.int64)
+    exact = np.zeros(n_nodes)
+    for li, w in enumerate(parts):
+        sel = np.nonzero(layout_of == li)[0]
+        nodes[sel, :w.problem.ndim] = w.nodes
+        paths[sel] = w.paths
+        exact[sel] = c3_exact(w)
+    return BatchWorkload("C3 batch, 8 layouts", [w.problem for w in parts], layout_of.astype(np.int32), nodes,
+                         paths, dt, seed, exact)
+
+
 def eval_dense_poly(ndim: int, degree: int, coef: np.ndarray, x: np.ndarray) -> np.ndarray:
     """Reference evaluation of a dense graded-lex polynomial (workload checks only)."""
     ex = monomial_exponents(ndim, degree)
