@@ -58,6 +58,10 @@ def log(msg):
 # S/dt += m, B/dt += m Z (the factor dt is applied once per fold): 180.
 OPS_PER_PS_FWD = 120.0
 OPS_PER_PS_ADJ = 180.0
+# The same step in the survey's unit: lane-op slots with a quarter-rate
+# operation (32x32->64 multiply, transcendental) counted as 4 slots; its
+# estimate for a C5 adjoint path-step is 230.
+OPS_PER_PS_ADJ_SURVEY = 230.0
 
 # HBM bytes per launch of the dominant kernel (C5 value+Jacobian walk),
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the 256 MiB copy
@@ -168,17 +172,23 @@ def run(args):
         b, r, c = (int(v) for v in text.split(","))
         return {"blocks_per_cu": b, "refill_groups": r, "chunk_paths": c}
 
+    # schedules live in the library's table: the timed calls pass none and the
+    # library applies the table's entry (tuned here, or from an earlier run's
+    # schedule file, else its defaults)
     if args.schedule_adj:
-        sched_a = parse_sched(args.schedule_adj)
-        sched_f = parse_sched(args.schedule_fwd) if args.schedule_fwd else dict(sched_a)
-        log(f"bench: given schedules: forward {sched_f}, adjoint {sched_a}")
+        sa = parse_sched(args.schedule_adj)
+        sf = parse_sched(args.schedule_fwd) if args.schedule_fwd else dict(sa)
+        pdd.set_schedule("walk_adjoint", 3, "fp32", **sa)
+        pdd.set_schedule("walk", 3, "fp32", **sf)
+        log(f"bench: given schedules: forward {sf}, adjoint {sa}")
     elif args.tune:
         t0 = time.time()
-        sched_f = autotune.tune(P, nodes, paths, w.dt, w.seed, "fp32", False, coefs, log=log)
-        sched_a = autotune.tune(P, nodes, paths, w.dt, w.seed, "fp32", True, coefs, log=log)
-        log(f"bench: autotuned in {time.time() - t0:.1f} s: forward {sched_f}, adjoint {sched_a}")
-    else:
-        sched_f = sched_a = dict(autotune.DEFAULT)
+        autotune.tune_walk(P, nodes, paths, w.dt, w.seed, "fp32", False, coefs, log=log)
+        autotune.tune_walk(P, nodes, paths, w.dt, w.seed, "fp32", True, coefs, log=log)
+        log(f"bench: autotuned in {time.time() - t0:.1f} s")
+    sched_f = pdd.get_schedule("walk", 3, "fp32")
+    sched_a = pdd.get_schedule("walk_adjoint", 3, "fp32")
+    log(f"bench: schedules from the library table: forward {sched_f}, adjoint {sched_a}")
 
     stats = {}
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -191,15 +201,15 @@ def run(args):
         # the library.  It launches on torch's current stream, so these events
         # bracket the value+Jacobian graph (walk kernel + its small reductions).
         ev_vj[0].record()
-        r = pdd.mc_value_jacobian(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_a)
+        r = pdd.mc_value_jacobian(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts)
         ev_vj[1].record()
         m = pdd.misfit_gradient(r, d)
         return r, m["grad"]
 
     def step_recompute():
-        r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts, **sched_f)
+        r = pdd.mc_interface(P, nodes, paths, w.dt, w.seed, coefs=coefs, **opts)
         ev[1].record()
-        g = pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, 2.0 * (r["mean"] - d), coefs=coefs, **opts, **sched_a)
+        g = pdd.mc_adjoint(P, nodes, paths, w.dt, w.seed, 2.0 * (r["mean"] - d), coefs=coefs, **opts)
         return r, g
 
     for i in range(args.warmup):
@@ -234,8 +244,10 @@ def run(args):
         dur = np.median(vj_ms) / 1e3
         return {"metric": "path-steps/s (batched FP32 forward+adjoint, C5)", "value": ps / (ms_step / 1e3),
                 "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-                "ms_per_step": ms_step, "mode": "steps-only", "tuned_adjoint": sched_a,
+                "ms_per_step": ms_step, "mode": "steps-only", "schedule_adjoint": sched_a,
+                "gpu_clock_during_steps": sclk,
                 "roofline": {"bound": "alu", "achieved": ps * OPS_PER_PS_ADJ / dur / 1e12,
+                             "achieved_survey_unit": ps * OPS_PER_PS_ADJ_SURVEY / dur / 1e12,
                              "peak": PEAK_LANE_OPS / 1e12, "unit": "Top/s", "launch_ms": dur * 1e3}}
 
     # the path-recomputing route (forward kernel, then adjoint kernel), timed
@@ -259,39 +271,60 @@ def run(args):
 
     # ---- interface nodes per second at a standard error of 1e-3 (SE-target
     # mode): a pilot of 1e3 paths per node estimates s_i, then each node runs
-    # N_i = clamp(ceil(s_i^2 / 1e-6), 1e3, 1e7) paths (paths 0..N_i-1, so the
-    # pilot's paths are part of the final estimate) through the value+Jacobian
-    # pass.  Batched FP32 on `se_nodes` nodes; the plain FP64 one-node-per-
-    # launch forward+adjoint on an evenly spaced subset of them.
+    # N_i = clamp(ceil(s_i^2 / 1e-6), 1e3, 1e7) paths through the value+Jacobian
+    # pass; nodes whose standard error still comes out above 1e-3 (the pilot
+    # underestimated s_i) are run again with N_i scaled by (SE_i / 1e-3)^2 and
+    # 5% more, up to 1e7, until every node meets the target.  The wall time
+    # covers all of it.  Batched FP32 on every node; the plain FP64 one-node-
+    # per-launch forward+adjoint on an evenly spaced subset of them.
     def se_target(idx, precision, extra):
         sub = nodes[torch.as_tensor(idx, device=dev)]
         torch.cuda.synchronize()
         t = time.perf_counter()
         pilot = pdd.mc_interface(P, sub, np.full(len(idx), 1000, np.int64), w.dt, w.seed, precision=precision,
                                  coefs=coefs, **extra)
-        s2 = (pilot["var"]).cpu().numpy()
+        s2 = pilot["var"].cpu().numpy()
         budget = np.clip(np.ceil(s2 / 1e-6), 1e3, 1e7).astype(np.int64)
         res = pdd.mc_value_jacobian(P, sub, budget, w.dt, w.seed, precision=precision, coefs=coefs, **extra)
+        se = res["se"].cpu().numpy()
+        rounds, topped = 0, np.zeros(len(idx), bool)
+        while True:
+            # nodes still above the target get more paths (an independent
+            # sample: seed + 1 + round), merged into their estimate
+            over = (se > 1e-3) & (budget < 10_000_000)
+            if not over.any() or rounds >= 4:
+                break
+            sel = np.nonzero(over)[0]
+            extra_n = np.minimum(10_000_000 - budget[sel],
+                                 np.ceil(budget[sel] * ((se[sel] / 1e-3) ** 2 - 1.0) * 1.05) + 64).astype(np.int64)
+            r2 = pdd.mc_value_jacobian(P, sub[torch.as_tensor(sel, device=dev)], extra_n, w.dt, w.seed + 1 + rounds,
+                                       precision=precision, coefs=coefs, **extra)
+            res = pdd.merge_estimates(res, r2, sel)
+            se = res["se"].cpu().numpy()
+            budget[sel] += extra_n
+            topped[sel] = True
+            rounds += 1
         torch.cuda.synchronize()
         el = time.perf_counter() - t
-        se = torch.sqrt(res["var"] / res["n"].double())
-        return el, budget, res, float(se.max().item())
+        return el, budget, {"paths_run": float(budget.sum()) + 1000.0 * len(idx),
+                            "path_steps": float(res["steps"].sum().item()), "top_up_rounds": rounds,
+                            "topped_up_nodes": int(topped.sum())}, float(se.max())
 
     k_se = min(args.se_nodes, n)
     idx_se = np.linspace(0, n - 1, k_se).round().astype(int)
-    se_target(idx_se[:8], "fp32", dict(schedule="persistent", **sched_a))        # warm-up
-    el_b, budget_b, res_b, se_max_b = se_target(idx_se, "fp32", dict(schedule="persistent", **sched_a))
+    se_target(idx_se[:64], "fp32", dict(schedule="persistent"))        # warm-up
+    el_b, budget_b, info_b, se_max_b = se_target(idx_se, "fp32", dict(schedule="persistent"))
     nodes_per_s = k_se / el_b
-    ps_se = float(res_b["steps"].sum().item())
-    log(f"bench: SE-target batched FP32 fwd+adj: {k_se} nodes, {budget_b.sum():.3e} paths, {el_b:.2f} s "
-        f"-> {nodes_per_s:.1f} nodes/s (max SE {se_max_b:.2e})")
+    log(f"bench: SE-target batched FP32 fwd+adj: {k_se} nodes, {info_b['paths_run']:.3e} paths "
+        f"({info_b['top_up_rounds']} top-up rounds, {info_b['topped_up_nodes']} nodes topped up), {el_b:.2f} s "
+        f"-> {nodes_per_s:.1f} nodes/s (max SE {se_max_b:.3e})")
     k_pl = min(args.plain_nodes, k_se)
     idx_pl = idx_se[np.linspace(0, k_se - 1, k_pl).round().astype(int)]
-    el_p, budget_p, res_p, se_max_p = se_target(idx_pl, "fp64_plain", {})
+    el_p, budget_p, info_p, se_max_p = se_target(idx_pl, "fp64_plain", {})
     plain_nodes_per_s = k_pl / el_p
-    plain_ps_s = float(res_p["steps"].sum().item()) / el_p
-    log(f"bench: SE-target plain FP64 fwd+adj: {k_pl} nodes, {budget_p.sum():.3e} paths, {el_p:.2f} s "
-        f"-> {plain_nodes_per_s:.2f} nodes/s (max SE {se_max_p:.2e})")
+    plain_ps_s = info_p["path_steps"] / el_p
+    log(f"bench: SE-target plain FP64 fwd+adj: {k_pl} nodes, {info_p['paths_run']:.3e} paths, {el_p:.2f} s "
+        f"-> {plain_nodes_per_s:.2f} nodes/s (max SE {se_max_p:.3e})")
 
     fwd_ps_s = ps / fwd_s
     adj_ps_s = ps / adj_s
@@ -320,15 +353,21 @@ def run(args):
         "config": {"workload": "C5 3-D unit-ball adjoint: 4096 nodes x 1e5 paths, dt=1e-3, fwd+adjoint",
                    "nodes": n, "paths_per_node": int(paths[0]), "dt": w.dt, "seed": w.seed,
                    "schedule": "persistent+hipGraph", "accumulation": "f64",
-                   "tuned_forward": sched_f, "tuned_adjoint": sched_a},
+                   "schedule_forward": sched_f, "schedule_adjoint": sched_a},
         "step": "one value+Jacobian pass (pdd_mc_value_jacobian) + misfit loss and gradient J^T w "
                 "(pdd_misfit_gradient)",
         "forward_path_steps_per_s": fwd_ps_s,
         "adjoint_path_steps_per_s": adj_ps_s,
         "forward_plus_recomputing_adjoint_path_steps_per_s": ps / (fwd_s + adj_s),
         "interface_nodes_per_s_at_se_1e-3": nodes_per_s,
-        "se_target": {"nodes": k_se, "paths": int(budget_b.sum()), "path_steps": ps_se, "seconds": el_b,
-                      "max_se": se_max_b, "budget_rule": "pilot 1e3 paths; N_i = clamp(ceil(s_i^2/1e-6), 1e3, 1e7)"},
+        "se_target": {"nodes": k_se, "paths": info_b["paths_run"], "path_steps": info_b["path_steps"],
+                      "seconds": el_b, "max_se": se_max_b, "top_up_rounds": info_b["top_up_rounds"],
+                      "topped_up_nodes": info_b["topped_up_nodes"],
+                      "budget_rule": "pilot 1e3 paths; N_i = clamp(ceil(s_i^2/1e-6), 1e3, 1e7); nodes above SE "
+                                     "1e-3 get N_i ((SE_i/1e-3)^2 - 1) x 1.05 + 64 more paths (independent seed, "
+                                     "merged; N_i <= 1e7) until all meet it; paths include the pilot's"},
+        "plain_se_target": {"nodes": k_pl, "paths": info_p["paths_run"], "path_steps": info_p["path_steps"],
+                            "seconds": el_p, "max_se": se_max_p, "top_up_rounds": info_p["top_up_rounds"]},
         "plain_fp64_fwd_adj_nodes_per_s_at_se_1e-3": plain_nodes_per_s,
         "plain_fp64_fwd_adj_path_steps_per_s": plain_ps_s,
         "plain_sample_nodes": k_pl,
@@ -338,10 +377,13 @@ def run(args):
         "roofline": {"bound": "alu", "kernel": f"k_walk ({dominant}, FP32, DIM 3)", "achieved": achieved,
                      "peak": peak, "unit": "Top/s", "frac": achieved / peak, "traffic": traffic_bytes(),
                      "ops_per_path_step": OPS_PER_PS_ADJ if dominant == "adjoint" else OPS_PER_PS_FWD,
+                     "ops_per_path_step_survey_unit": OPS_PER_PS_ADJ_SURVEY,
+                     "achieved_survey_unit": ps * OPS_PER_PS_ADJ_SURVEY / dur / 1e12,
+                     "frac_survey_unit": ps * OPS_PER_PS_ADJ_SURVEY / dur / 1e12 / peak,
                      "launch_ms": dur * 1e3},
     }
     if args.extras:
-        out["other_workloads"] = other_workloads(pdd, dev)
+        out["other_workloads"] = other_workloads(pdd, dev, tune=args.tune)
     if args.cpu_baseline:
         out["cpu_baseline"], out["fp32_vs_fp64_oracle"] = cpu_baseline(w, args.cpu_seconds, pdd, coefs, dev)
     return out
@@ -355,12 +397,13 @@ def cva_problem(pdd, w):
                                           beta=w.beta)
 
 
-def other_workloads(pdd, dev):
-    """Throughput of the other synthetic workloads (FP32 stepping, default
-    schedule, cached graphs; one warm-up call each): C3's 4096-node batch
-    over 8 layouts with variance-targeted budgets, C2's drift/killing/source
-    problem on the disk and C4's KPP branching estimator, both at full size;
-    C6, the branching estimator with a Dirichlet boundary at 11 output times."""
+def other_workloads(pdd, dev, tune=True):
+    """Throughput of the other synthetic workloads (FP32 stepping, the
+    library's tuned schedules, cached graphs; one warm-up call each): C3's
+    4096-node batch over 8 layouts with variance-targeted budgets in one
+    launch, C2's drift/killing/source problem on the disk and C4's KPP
+    branching estimator, both at full size; C6, the branching estimator with
+    a Dirichlet boundary at 11 output times; C7, the CVA construction."""
     import torch
     from workloads import configs as CF
 
@@ -373,43 +416,43 @@ def other_workloads(pdd, dev):
         return r, time.perf_counter() - t
 
     res = {}
-    parts = CF.c3()
-    subs = [(p.problem, torch.tensor(p.nodes, device=dev), p.paths, p.dt, p.seed) for p in parts]
+    from paper_1705_03666_amd import autotune
+    # C3: 4096 nodes over 8 layouts (2-D and 3-D, box, disk and ball) in one
+    # persistent launch per call, the library's tuned batch schedule
+    cb = CF.c3_batch()
+    nb = torch.tensor(cb.nodes, device=dev)
+    if tune:
+        autotune.tune_batch(cb.problems, cb.node_problem, nb, cb.paths, cb.dt, cb.seed, "fp32", log=log)
+        autotune.tune_batch(cb.problems, cb.node_problem, nb, cb.paths, 1e-4, cb.seed, "fp32", wos=True, log=log)
 
-    # the 8 layouts are independent calls: issued on a pool of streams so that
-    # one launch's tail overlaps the next (results identical to serial calls)
-    def run_c3():
-        return pdd.mc_interface_many([((P, nd, pa, dt, sd), dict(precision="fp32")) for P, nd, pa, dt, sd in subs])
-
-    def err_se(rs_):
-        z = []
-        for p, r in zip(parts, rs_):
-            exact = CF.c3_exact(p)
-            z.append(np.abs(r["mean"].cpu().numpy() - exact) / r["se"].cpu().numpy())
-        z = np.concatenate(z)
+    def err_se(r):
+        z = np.abs(r["mean"].cpu().numpy() - cb.exact) / r["se"].cpu().numpy()
         return float(z.max()), float(np.sqrt(np.mean(z ** 2)))
 
-    rs, el = timed(run_c3)
-    ps = sum(float(r["steps"].sum().item()) for r in rs)
-    nn = sum(len(p.paths) for p in parts)
-    zmax, zrms = err_se(rs)
-    res["c3_batch"] = {"nodes": nn, "paths": int(sum(int(p.paths.sum()) for p in parts)), "path_steps": ps,
-                       "seconds": el, "path_steps_per_s": ps / el, "nodes_per_s": nn / el,
+    run_c3 = lambda: pdd.mc_interface_batch(cb.problems, cb.node_problem, nb, cb.paths, cb.dt, cb.seed,
+                                            precision="fp32")
+    rb, el = timed(run_c3)
+    ps = float(rb["steps"].sum().item())
+    nn = len(cb.paths)
+    zmax, zrms = err_se(rb)
+    res["c3_batch"] = {"nodes": nn, "paths": int(cb.paths.sum()), "path_steps": ps, "seconds": el,
+                       "path_steps_per_s": ps / el, "nodes_per_s": nn / el, "launches": 1,
+                       "schedule": pdd.get_schedule("walk_batch", 0, "fp32"),
                        "err_vs_exact_max_se": zmax, "err_vs_exact_rms_se": zrms}
-    log(f"bench: C3 batch (Euler): {nn} nodes in {el * 1e3:.1f} ms, {ps / el:.3e} path-steps/s, "
+    log(f"bench: C3 batch (Euler, one launch): {nn} nodes in {el * 1e3:.1f} ms, {ps / el:.3e} path-steps/s, "
         f"error vs exact max {zmax:.1f} SE, rms {zrms:.1f} SE")
 
     # the same batch by walk on spheres (b = c = f = 0), eps = 1e-4
-    def run_c3_wos():
-        return [pdd.wos_interface(P, nd, pa, 1e-4, sd, precision="fp32") for P, nd, pa, dt, sd in subs]
-
+    run_c3_wos = lambda: pdd.wos_interface_batch(cb.problems, cb.node_problem, nb, cb.paths, 1e-4, cb.seed,
+                                                 precision="fp32")
     rw, elw = timed(run_c3_wos)
-    jumps = sum(float(r["steps"].sum().item()) for r in rw)
+    jumps = float(rw["steps"].sum().item())
     zmax, zrms = err_se(rw)
     res["c3_batch_walk_on_spheres"] = {"eps": 1e-4, "jumps": jumps, "seconds": elw, "jumps_per_s": jumps / elw,
-                                       "nodes_per_s": nn / elw, "err_vs_exact_max_se": zmax,
-                                       "err_vs_exact_rms_se": zrms}
-    log(f"bench: C3 batch (walk on spheres): {elw * 1e3:.1f} ms, {jumps / elw:.3e} jumps/s, "
+                                       "nodes_per_s": nn / elw, "launches": 1,
+                                       "schedule": pdd.get_schedule("wos_batch", 0, "fp32"),
+                                       "err_vs_exact_max_se": zmax, "err_vs_exact_rms_se": zrms}
+    log(f"bench: C3 batch (walk on spheres, one launch): {elw * 1e3:.1f} ms, {jumps / elw:.3e} jumps/s, "
         f"error vs exact max {zmax:.1f} SE, rms {zrms:.1f} SE")
     # C2 at its full size (256 nodes x 1e6 paths, dt = 1e-4); the first call
     # also compiles the problem-specialised kernel (timed separately)
@@ -447,11 +490,14 @@ def other_workloads(pdd, dev):
         f"corrected max {acc['corrected']['max_err_se']:.1f}")
     c4 = CF.c4()
     p4 = torch.tensor(c4.points, device=dev)
+    if tune:
+        autotune.tune_branching(c4.problem, p4, c4.trees, c4.seed, "fp32", log=log)
     r4, el4 = timed(lambda: pdd.branching_eval(c4.problem, p4, c4.trees, c4.seed, precision="fp32"))
     segs = float(r4["steps"].sum().item())
     trees = float(len(c4.points) * c4.trees)
     res["c4"] = {"points": len(c4.points), "trees_per_point": c4.trees, "segments": segs, "seconds": el4,
-                 "trees_per_s": trees / el4, "segments_per_s": segs / el4}
+                 "trees_per_s": trees / el4, "segments_per_s": segs / el4,
+                 "schedule": pdd.get_schedule("branch", 3, "fp32")}
     log(f"bench: C4: {trees:.3e} trees, {segs:.3e} segments in {el4 * 1e3:.1f} ms")
     # C7: the CVA construction of Sec. 3.3 (signed quartic, marks q ~ |alpha|),
     # 1024 points x 1e5 trees, compared with the method-of-lines solution of
@@ -459,6 +505,8 @@ def other_workloads(pdd, dev):
     c7 = CF.c7()
     prob7, scale7 = cva_problem(pdd, c7)
     p7 = torch.tensor(c7.points, device=dev)
+    if tune:
+        autotune.tune_branching(prob7, p7, c7.trees, c7.seed, "fp32", log=log)
     r7, el7 = timed(lambda: pdd.branching_eval(prob7, p7, c7.trees, c7.seed, precision="fp32"))
     segs7 = float(r7["steps"].sum().item())
     ref7 = CF.c7_reference(c7.points[:, 0])
@@ -473,6 +521,8 @@ def other_workloads(pdd, dev):
     # Algorithm 3.1); the travelling wave is the exact solution
     c6 = CF.c6()
     p6 = torch.tensor(c6.points, device=dev)
+    if tune:
+        autotune.tune_branching(c6.problem, p6, c6.trees, c6.seed, "fp32", boundary=c6.boundary, log=log)
     r6, el6 = timed(lambda: pdd.branching_bvp(c6.problem, c6.boundary, p6, c6.trees, c6.seed, precision="fp32"))
     sub = float(r6["steps"][0].sum().item())
     tr6 = float(len(c6.points) * c6.trees)
@@ -481,7 +531,8 @@ def other_workloads(pdd, dev):
     res["c6_branching_boundary"] = {"points": len(c6.points), "trees_per_point": c6.trees,
                                     "output_times": len(c6.boundary.times), "dt": c6.boundary.dt,
                                     "particle_substeps": sub, "seconds": el6, "trees_per_s": tr6 / el6,
-                                    "substeps_per_s": sub / el6, "err_vs_exact_max_se": float(z6.max()),
+                                    "substeps_per_s": sub / el6, "schedule": pdd.get_schedule("branch_bvp", 1, "fp32"),
+                                    "err_vs_exact_max_se": float(z6.max()),
                                     "err_vs_exact_rms_se": float(np.sqrt(np.mean(z6 ** 2)))}
     log(f"bench: C6: {tr6:.3e} trees x {len(c6.boundary.times)} times, {sub:.3e} particle sub-steps in "
         f"{el6 * 1e3:.1f} ms ({sub / el6:.3e}/s); error vs exact max {z6.max():.1f} SE, "
@@ -504,13 +555,15 @@ def run_only(name, scale):
     from workloads import configs as CF
     dev = "cuda"
     if name in ("c3", "c3wos"):
-        subs = [(p.problem, torch.tensor(p.nodes, device=dev), p.paths, p.dt, p.seed) for p in CF.c3(scale=scale)]
+        cb = CF.c3_batch(scale=scale)
+        nb = torch.tensor(cb.nodes, device=dev)
         if name == "c3":
-            call = lambda: pdd.mc_interface_many([((P, nd, pa, dt, sd), dict(precision="fp32"))
-                                                  for P, nd, pa, dt, sd in subs])
+            call = lambda: pdd.mc_interface_batch(cb.problems, cb.node_problem, nb, cb.paths, cb.dt, cb.seed,
+                                                  precision="fp32")
         else:
-            call = lambda: [pdd.wos_interface(P, nd, pa, 1e-4, sd, precision="fp32") for P, nd, pa, dt, sd in subs]
-        work = lambda rs: sum(float(r["steps"].sum().item()) for r in rs)
+            call = lambda: pdd.wos_interface_batch(cb.problems, cb.node_problem, nb, cb.paths, 1e-4, cb.seed,
+                                                   precision="fp32")
+        work = lambda r: float(r["steps"].sum().item())
         unit = "path_steps" if name == "c3" else "jumps"
     elif name == "c2":
         w = CF.c2(scale=scale)
@@ -542,14 +595,40 @@ def run_only(name, scale):
                           unit + "_per_s": n / el}), flush=True)
 
 
+def host_cpu():
+    """(threads to use, description) of the host CPU share this process may
+    use: the CPUs in its affinity mask, bounded by a cgroup CPU quota and by
+    OMP_NUM_THREADS when either is set, and the CPU model."""
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = max(1, int(int(q) / int(per)))
+    except (OSError, ValueError):
+        pass
+    omp = os.environ.get("OMP_NUM_THREADS")
+    limits = [affinity] + ([quota] if quota else []) + ([int(omp)] if omp and omp.isdigit() and int(omp) > 0 else [])
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return min(limits), {"model": model, "affinity_cpus": affinity, "cgroup_quota_cpus": quota,
+                         "omp_num_threads": omp, "os_cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(w, seconds, pdd, coefs, dev):
     """The FP64 oracle (forward + adjoint) on a bounded sample of the same
-    workload, timed on the host's cores; the GPU FP32 path is then run on the
-    same sample (same nodes, paths and seed) and its node values and gradient
-    are compared with the oracle's."""
+    workload, timed on the host's CPU share; the GPU FP32 path is then run on
+    the same sample (same nodes, paths and seed) and its node values and
+    gradient are compared with the oracle's."""
     import torch
     import oracle
-    threads = oracle.default_threads()
+    threads, cpu = host_cpu()
     P = w.problem_template
     # calibrate on a tiny sample, then size the sample for ~`seconds`
     nc = 2 * threads
@@ -571,7 +650,7 @@ def cpu_baseline(w, seconds, pdd, coefs, dev):
     ps = float(r["stats"]["steps"].sum())
     base = {"value": ps / el, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"C5 forward+adjoint, {nn} nodes x {per_node} paths ({ps:.3e} path-steps, {el:.1f} s), FP64",
-            "cpu": platform.processor() or platform.machine()}
+            "cpu": cpu}
     # error of the FP32-stepping GPU path against the FP64 oracle on this sample
     sub = torch.tensor(w.nodes[idx], device=dev)
     g = pdd.mc_adjoint(P, sub, pa, w.dt, w.seed, torch.ones(nn, dtype=torch.float64, device=dev), precision="fp32",
@@ -616,8 +695,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=float, default=1.0, help="path budget scale (1 = 1e5 paths/node)")
     ap.add_argument("--nodes", type=int, default=4096)
-    ap.add_argument("--plain-nodes", type=int, default=8, help="plain FP64 nodes in the SE-target comparison")
-    ap.add_argument("--se-nodes", type=int, default=1024, help="nodes in the SE-target run")
+    ap.add_argument("--plain-nodes", type=int, default=32, help="plain FP64 nodes in the SE-target comparison")
+    ap.add_argument("--se-nodes", type=int, default=4096, help="nodes in the SE-target run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--no-extras", dest="extras", action="store_false", help="skip the C2/C3/C4 throughput lines")

@@ -431,6 +431,22 @@ pdd_status pdd_misfit_gradient(const pdd_node_stat* stats_dev, const double* dat
                                const double* jac_dev, int64_t jac_ld, int64_t n_params, double* loss_dev,
                                double* grad_dev, void* hip_stream);
 
+/* Refines estimates with more samples: merges a second, independent sample of
+ * some nodes (for instance a call with another seed over the nodes whose
+ * standard error is still above a target) into existing node statistics, so
+ * that the result is the sample mean over both samples (Sec. 2.1's per-node
+ * mean over N + N' paths).  For k < n_add, node i = index_dev[k] of acc_dev
+ * receives add_dev[k]: Welford triples merged (Chan et al.), n, steps and
+ * censored summed; with Jacobians, row i of acc_jac_dev becomes the path-count
+ * weighted mean (n_i row_i + n_k add_row_k) / (n_i + n_k).
+ *  acc_dev: device [*] pdd_node_stat, updated; add_dev: device [n_add];
+ *  index_dev: device [n_add] int64, distinct node indices (duplicates race);
+ *  acc_jac_dev / add_jac_dev: device [*][acc_ld] / [n_add][add_ld] FP64, both
+ *  or neither; n_params columns are merged. */
+pdd_status pdd_merge_estimates(pdd_node_stat* acc_dev, double* acc_jac_dev, int64_t acc_ld,
+                               const pdd_node_stat* add_dev, const double* add_jac_dev, int64_t add_ld,
+                               int64_t n_params, const int64_t* index_dev, int64_t n_add, void* hip_stream);
+
 /* Sample variance and standard error of every node (the unbiased estimator:
  * var = m2 / (n - 1), 0 for n < 2; se = sqrt(var / n), 0 for n = 0).
  *  stats_dev: device [n_nodes]; var_dev, se_dev: device [n_nodes] or NULL. */

@@ -31,7 +31,7 @@ __all__ = ["mc_interface", "mc_interface_noalloc", "mc_interface_batch", "wos_in
            "item_count", "set_schedule", "get_schedule", "save_schedules", "load_schedules",
            "PDDInterface", "PddError",
            "release_workspace", "query_warnings", "library", "version", "param_layout", "jacobian_blocks",
-           "jacobian_apply", "misfit_gradient", "cached_plan_count", "nonlinear"]
+           "jacobian_apply", "misfit_gradient", "merge_estimates", "cached_plan_count", "nonlinear"]
 
 
 class PddError(RuntimeError):
@@ -510,6 +510,34 @@ def mc_value_jacobian(problem, nodes, paths, dt: float, seed: int = 0, precision
         res["phi"], res["path_steps"] = dphi[:total], dst[:total]
     res["_keep"] = keep
     return res
+
+
+def merge_estimates(acc: Dict[str, torch.Tensor], add: Dict[str, torch.Tensor], index) -> Dict[str, torch.Tensor]:
+    """Merges `add` (the result of a call over some nodes, with an independent
+    sample: another seed) into `acc` (a result over all nodes) in place, node
+    acc[index[k]] receiving add's node k (pdd_merge_estimates); Jacobians are
+    merged too when both results carry one.  Returns acc's statistics
+    recomputed from the merged records (with acc's Jacobian)."""
+    _need_gpu()
+    idx = torch.as_tensor(np.asarray(index, dtype=np.int64), device="cuda").contiguous()
+    n_add = idx.numel()
+    ra, rb = acc["_raw"], add["_raw"]
+    if rb.shape[0] != n_add:
+        raise ValueError("index must have one entry per node of `add`")
+    ja, jb = acc.get("jac"), add.get("jac")
+    both = ja is not None and jb is not None
+    npar = ja.shape[1] if both else 0
+    st = library().pdd_merge_estimates(ra.data_ptr(), ja.data_ptr() if both else None,
+                                       int(acc.get("jac_ld", npar)) if both else 0, rb.data_ptr(),
+                                       jb.data_ptr() if both else None, int(add.get("jac_ld", npar)) if both else 0,
+                                       npar, idx.data_ptr(), n_add, _stream_handle())
+    _check(st, "pdd_merge_estimates")
+    out = _stats(ra)
+    for k in ("jac", "jac_ld"):
+        if k in acc:
+            out[k] = acc[k]
+    out["_keep"] = (acc.get("_keep"), idx)
+    return out
 
 
 def jacobian_apply(jac: torch.Tensor, w) -> torch.Tensor:

@@ -21,7 +21,7 @@ EXPORTED = ["pdd_mc_interface", "pdd_mc_interface_noalloc", "pdd_mc_interface_ba
             "pdd_wos_interface", "pdd_branching_eval", "pdd_branching_bvp", "pdd_mc_adjoint",
             "pdd_mc_value_jacobian", "pdd_item_count", "pdd_set_schedule", "pdd_get_schedule",
             "pdd_save_schedules", "pdd_load_schedules",
-            "pdd_param_count", "pdd_jacobian_apply", "pdd_misfit_gradient", "pdd_node_moments",
+            "pdd_param_count", "pdd_jacobian_apply", "pdd_misfit_gradient", "pdd_node_moments", "pdd_merge_estimates",
             "pdd_query_warnings", "pdd_release_workspace", "pdd_cached_plan_count", "pdd_status_string",
             "pdd_last_error", "pdd_version"]
 
@@ -133,6 +133,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.pdd_misfit_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int64,
                                       C.c_void_p, C.c_void_p, C.c_void_p]
     L.pdd_misfit_gradient.restype = C.c_int
+    L.pdd_merge_estimates.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+    L.pdd_merge_estimates.restype = C.c_int
     L.pdd_node_moments.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
     L.pdd_node_moments.restype = C.c_int
     L.pdd_cached_plan_count.argtypes = []

@@ -40,7 +40,7 @@ struct BrScalars<float> {
   __device__ static float sigma(const BranchParams& P) { return P.sigmaf; }
   __device__ static float T(const BranchParams& P) { return P.Tf; }
   __device__ static float lifetime(const BranchParams& P, float u) {
-    return -0.6931471805599453f * __builtin_amdgcn_logf(u) * __builtin_amdgcn_rcpf(P.betaf);
+    return -0.6931471805599453f * __builtin_amdgcn_logf(u) * P.inv_betaf;
   }
 };
 template <>
@@ -60,7 +60,11 @@ __device__ __forceinline__ void br_uniforms(uint64_t label, int attempt, uint32_
   uint32_t c0 = (uint32_t)label;
   uint32_t c1 = (1u << 24) | ((uint32_t)attempt << 20) | (uint32_t)((label >> 32) & 0xFFFFu);
   uint32_t c2 = tree, c3 = point;
-  philox4x32_10(c0, c1, c2, c3, k0, k1);
+  // opaque copies of the key: the round keys are rebuilt with scalar adds at
+  // each use instead of holding twenty scalar registers through the loop
+  uint32_t ka = k0, kb = k1;
+  asm volatile("" : "+s"(ka), "+s"(kb));
+  philox4x32_10(c0, c1, c2, c3, ka, kb);
   if constexpr (LAYOUT == RNG_QUAD24) {
     if constexpr (sizeof(R) == 4) {
       ulife = u24f(c0);
@@ -82,12 +86,47 @@ __device__ __forceinline__ void br_normals(uint64_t label, int attempt, uint32_t
   using NZr = Normals<R, LAYOUT>;
   R tmp[4];
   const uint32_t base = (2u << 24) | ((uint32_t)attempt << 20) | (uint32_t)((label >> 32) & 0xFFFFu);
-  NZr::gen((uint32_t)label, base, tree, point, k0, k1, tmp);
+  uint32_t ka = k0, kb = k1;
+  asm volatile("" : "+s"(ka), "+s"(kb));
+  NZr::gen((uint32_t)label, base, tree, point, ka, kb, tmp);
   if constexpr (NZr::kPerBlock == 2) {
-    if constexpr (DIM > 2) NZr::gen((uint32_t)label, base | (1u << 16), tree, point, k0, k1, tmp + 2);
+    if constexpr (DIM > 2) {
+      uint32_t kc = k0, kd = k1;
+      asm volatile("" : "+s"(kc), "+s"(kd));
+      NZr::gen((uint32_t)label, base | (1u << 16), tree, point, kc, kd, tmp + 2);
+    }
   }
 #pragma unroll
   for (int k = 0; k < DIM; ++k) z[k] = tmp[k];
+}
+
+// Offspring class of a branching particle with type uniform u: the index j
+// into the compact law (class size P.cls[j], mark P.mark[j]), i.e. the number
+// of class thresholds at or below u -- the first class whose cumulative
+// probability exceeds u, the last class for larger u.
+template <typename R>
+__device__ __forceinline__ int offspring_class(const BranchParams& P, R u) {
+  int j = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const bool ge = sizeof(R) == 4 ? ((float)u >= P.thrf[m]) : ((double)u >= P.thr[m]);
+    j += ge ? 1 : 0;
+  }
+  return j;
+}
+
+__device__ __forceinline__ int class_size(const BranchParams& P, int j) {
+  int I = P.cls[0];
+#pragma unroll
+  for (int m = 1; m < 5; ++m) I = j == m ? P.cls[m] : I;
+  return I;
+}
+
+__device__ __forceinline__ double class_mark(const BranchParams& P, int j) {
+  double r = P.mark[0];
+#pragma unroll
+  for (int m = 1; m < 5; ++m) r = j == m ? P.mark[m] : r;
+  return r;
 }
 
 template <typename R, int DIM>
@@ -145,7 +184,11 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
     double W = 1.0, prod = 1.0;
     int segs = 0, sp = 0, attempt = 0;
 
-    double wn = 0.0, wmean = 0.0, wm2 = 0.0;
+    // per-lane accumulation of the finished trees' values as shifted sums
+    // (count, shift = the lane's first value, sums of v - shift and of its
+    // square): no division per tree; converted to a Welford triple and
+    // merged across the wavefront once per item
+    double wn = 0.0, wk = 0.0, ws1 = 0.0, ws2 = 0.0;
     int64_t lsegs = 0, lcens = 0, lredraw = 0;
 
     while (__any(active)) {
@@ -168,22 +211,9 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
           bool pop = false;
           if (E < rem) {
             // offspring count: smallest I with u < q_0 + ... + q_I (among q_I > 0)
-            int I = 0;
-            int last = 0;
-            bool found = false;
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-              if (P.q[k] > 0.0) {
-                last = k;
-                const bool hit = sizeof(R) == 4 ? ((float)utype < P.qcumf[k]) : ((double)utype < P.qcum[k]);
-                if (!found && hit) { I = k; found = true; }
-              }
-            }
-            if (!found) I = last;
-            double ratio = P.ratio[0];
-#pragma unroll
-            for (int k = 1; k < 5; ++k) if (I == k) ratio = P.ratio[k];
-            W = W * ratio;
+            const int jc = offspring_class<R>(P, utype);
+            const int I = class_size(P, jc);
+            W = W * class_mark(P, jc);
             if (I == 0) {
               pop = true;
             } else {
@@ -246,10 +276,11 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
           }
         }
         if (done) {
+          wk = wn == 0.0 ? value : wk;
+          const double dv = value - wk;
           wn += 1.0;
-          const double d1 = value - wmean;
-          wmean += d1 / wn;
-          wm2 += d1 * (value - wmean);
+          ws1 += dv;
+          ws2 += dv * dv;
           lsegs += segs;
           if (dump_val != nullptr) {
             const int64_t o = (int64_t)point * trees + (int64_t)tree;
@@ -282,6 +313,13 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
       }
     }
 
+    double wmean = 0.0, wm2 = 0.0;
+    if (wn > 0.0) {
+      const double a = ws1 / wn;
+      wmean = wk + a;
+      wm2 = ws2 - ws1 * a;
+      wm2 = wm2 > 0.0 ? wm2 : 0.0;
+    }
     wave_welford(wn, wmean, wm2);
     lsegs = wave_sum(lsegs);
     lcens = wave_sum(lcens);
@@ -414,8 +452,12 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
   const int64_t nlanes = (int64_t)gridDim.x * kBlock;
   constexpr int kLdsDepth = lds_depth<R>();
   __shared__ StackEntry<R> lds[kBlock / kWave][kLdsDepth][kWave];
-  // per-wave Welford triples per output time, updated by lane 0 tree by tree
-  __shared__ double wst[kBlock / kWave][2 * kMaxTimes + 1];
+  // per wavefront and output time i: shifted sums of the finished trees'
+  // values (sum of v - K_i, sum of (v - K_i)^2, K_i = the first tree's
+  // value), lane i updating time i; plus the tree count and a staging row
+  // through which a finished tree hands its values to those lanes
+  __shared__ double wst[kBlock / kWave][3 * kMaxTimes + 1];
+  __shared__ double wrow[kBlock / kWave][kMaxTimes];
 
   const uint32_t k0 = P.key0, k1 = P.key1;
   const R sigma = BrScalars<R>::sigma(P);
@@ -441,8 +483,7 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
     const bool x0_in = !bounded || inside<R, DIM>(D, x0);
     const double psi0 = x0_in ? (double)psi_value<R, DIM>(P, x0) : 1.0;
     __builtin_amdgcn_wave_barrier();
-    if (lane == 0)
-      for (int i = 0; i < 2 * kMaxTimes + 1; ++i) W[i] = 0.0;
+    if (lane < 3 * kMaxTimes + 1) W[lane] = 0.0;
     __builtin_amdgcn_wave_barrier();
 
     uint32_t tree = it.p0 + (uint32_t)lane;
@@ -541,7 +582,9 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
           const uint32_t c1 = (5u << 28) | ((uint32_t)attempt << 24) | ((uint32_t)((label >> 32) & 0xFFFFu) << 8) |
                               ((j >> 8) & 0xFFu);
           const uint32_t c3 = ((uint32_t)point & 0xFFFFFFu) | ((j & 0xFFu) << 24);
-          NZr::gen(c0, c1, tree, c3, k0, k1, &zb[b * kPer]);
+          uint32_t ka = k0, kb = k1;
+          asm volatile("" : "+s"(ka), "+s"(kb));
+          NZr::gen(c0, c1, tree, c3, ka, kb, &zb[b * kPer]);
         }
       }
       for (int q = 0; q < kSub; ++q) {
@@ -608,20 +651,9 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
           pop = true;   // reached the last output time
         } else if (ev & EV_DEATH) {
           // offspring count: smallest I with u < q_0 + ... + q_I (among q_I > 0)
-          int I = 0, last = 0;
-          bool found = false;
-#pragma unroll
-          for (int k = 0; k < 5; ++k) {
-            if (P.q[k] > 0.0) {
-              last = k;
-              const bool hit = sizeof(R) == 4 ? ((float)utype < P.qcumf[k]) : ((double)utype < P.qcum[k]);
-              if (!found && hit) { I = k; found = true; }
-            }
-          }
-          if (!found) I = last;
-          double ratio = P.ratio[0];
-#pragma unroll
-          for (int k = 1; k < 5; ++k) if (I == k) ratio = P.ratio[k];
+          const int jc = offspring_class<R>(P, utype);
+          const int I = class_size(P, jc);
+          const double ratio = class_mark(P, jc);
 #pragma unroll
           for (int i = 0; i < kMaxTimes; ++i)
             if (i < nt && BvScalars<R>::t(BB, i) > sdeath) Pt[i] *= ratio;
@@ -690,25 +722,31 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
           if (dump_segs != nullptr) dump_segs[(int64_t)point * trees + (int64_t)tree] = segs;
         }
       }
-      // finished trees enter the wave's Welford triples in lane order
+      // finished trees enter the wave's sums in lane order: the tree's lane
+      // stages its values in LDS, lane i adds value i to time i's sums
       uint64_t dmask = ballot(done);
       const uint64_t dmask0 = dmask;
+      double* const row = &wrow[wid][0];
       while (dmask != 0) {
         const int l = __builtin_ctzll(dmask);
         dmask &= dmask - 1;
-        if (lane == 0) W[2 * kMaxTimes] += 1.0;
-        const double n = W[2 * kMaxTimes];
+        __builtin_amdgcn_wave_barrier();
+        if (lane == l) {
 #pragma unroll
-        for (int i = 0; i < kMaxTimes; ++i) {
-          if (i < nt) {
-            const double v = __shfl(Pt[i], l);
-            if (lane == 0) {
-              const double d1 = v - W[i];
-              W[i] += d1 / n;
-              W[kMaxTimes + i] += d1 * (v - W[i]);
-            }
-          }
+          for (int i = 0; i < kMaxTimes; ++i) row[i] = Pt[i];
         }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nt) {
+          const double v = row[lane];
+          const bool first = W[3 * kMaxTimes] == 0.0;
+          const double K = first ? v : W[2 * kMaxTimes + lane];
+          if (first) W[2 * kMaxTimes + lane] = v;
+          const double dv = v - K;
+          W[lane] += dv;
+          W[kMaxTimes + lane] += dv * dv;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) W[3 * kMaxTimes] += 1.0;
         __builtin_amdgcn_wave_barrier();
       }
       // refill
@@ -732,11 +770,14 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
     lredraw = wave_sum(lredraw);
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
+      const double n = W[3 * kMaxTimes];
       for (int i = 0; i < nt; ++i) {
         ItemStat st;
-        st.mean = W[i];
-        st.m2 = W[kMaxTimes + i];
-        st.n = (int64_t)W[2 * kMaxTimes];
+        const double a = n > 0.0 ? W[i] / n : 0.0;
+        st.mean = n > 0.0 ? W[2 * kMaxTimes + i] + a : 0.0;
+        const double m2 = W[kMaxTimes + i] - W[i] * a;
+        st.m2 = m2 > 0.0 ? m2 : 0.0;
+        st.n = (int64_t)n;
         st.steps = lsub;
         st.censored = lcens;
         st.redrawn = i == 0 ? lredraw : 0;

@@ -1426,6 +1426,24 @@ void fill_branch_params(const pdd_branching_problem& B, uint64_t seed, Tables& T
     bp.qcum[k] = cum;
     bp.qcumf[k] = (float)cum;
   }
+  bp.inv_betaf = (float)(1.0 / B.beta);
+  // compact offspring law: classes with q > 0, their cumulative thresholds
+  bp.n_cls = 0;
+  for (int k = 0; k < 5; ++k)
+    if (B.q[k] > 0.0) {
+      bp.cls[bp.n_cls] = k;
+      bp.mark[bp.n_cls] = bp.ratio[k];
+      ++bp.n_cls;
+    }
+  for (int j = 0; j < 4; ++j) {
+    const bool real = j < bp.n_cls - 1;
+    bp.thr[j] = real ? bp.qcum[bp.cls[j]] : INFINITY;
+    bp.thrf[j] = real ? bp.qcumf[bp.cls[j]] : INFINITY;
+  }
+  for (int j = bp.n_cls; j < 5; ++j) {
+    bp.cls[j] = bp.cls[bp.n_cls - 1];
+    bp.mark[j] = bp.mark[bp.n_cls - 1];
+  }
   bp.key0 = (uint32_t)seed;
   bp.key1 = (uint32_t)(seed >> 32);
   bp.psi = T.add(B.psi, B.dim, 0, true);
@@ -1948,6 +1966,32 @@ pdd_status pdd_misfit_gradient(const pdd_node_stat* stats_dev, const double* dat
     }
     PDD_HIP(launch_jacobian_apply(jac_dev, n_nodes, jac_ld, n_params, nullptr, stats_dev, data_dev,
                                   n_params > 0 ? grad_dev : nullptr, loss_dev, (hipStream_t)hip_stream));
+    return PDD_OK;
+  } catch (...) {
+    return fail(PDD_ERR_HIP, "unexpected exception");
+  }
+}
+
+pdd_status pdd_merge_estimates(pdd_node_stat* acc_dev, double* acc_jac_dev, int64_t acc_ld,
+                               const pdd_node_stat* add_dev, const double* add_jac_dev, int64_t add_ld,
+                               int64_t n_params, const int64_t* index_dev, int64_t n_add, void* hip_stream) {
+  try {
+    if (n_add < 0 || n_params < 0) return fail(PDD_ERR_INVALID_ARG, "negative size");
+    if (n_add == 0) return PDD_OK;
+    if ((acc_jac_dev == nullptr) != (add_jac_dev == nullptr))
+      return fail(PDD_ERR_INVALID_ARG, "give both Jacobians or neither");
+    if (acc_jac_dev != nullptr && (acc_ld < n_params || add_ld < n_params))
+      return fail(PDD_ERR_INVALID_ARG, "Jacobian leading dimension below n_params");
+    pdd_status s;
+    if ((s = check_device_ptr(acc_dev, "acc_dev")) != PDD_OK) return s;
+    if ((s = check_device_ptr(add_dev, "add_dev")) != PDD_OK) return s;
+    if ((s = check_device_ptr(index_dev, "index_dev")) != PDD_OK) return s;
+    if (acc_jac_dev != nullptr) {
+      if ((s = check_device_ptr(acc_jac_dev, "acc_jac_dev")) != PDD_OK) return s;
+      if ((s = check_device_ptr(add_jac_dev, "add_jac_dev")) != PDD_OK) return s;
+    }
+    PDD_HIP(launch_merge_estimates(acc_dev, acc_jac_dev, acc_ld, add_dev, add_jac_dev, add_ld, n_params, index_dev,
+                                   n_add, (hipStream_t)hip_stream));
     return PDD_OK;
   } catch (...) {
     return fail(PDD_ERR_HIP, "unexpected exception");

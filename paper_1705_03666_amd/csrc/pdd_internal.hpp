@@ -63,9 +63,19 @@ struct LinearParams {
 struct BranchParams {
   int32_t dim, max_segments, label_base, n_fac;
   double sigma, beta, T;
-  float sigmaf, betaf, Tf, pad0;
+  float sigmaf, betaf, Tf, inv_betaf;
   double alpha[5], q[5], ratio[5], qcum[5];
   float qcumf[5], pad1[3];
+  // The offspring law in compact form: the n_cls classes with q > 0 in
+  // increasing order, class j drawn when thr[j-1] <= u < thr[j] (thr[-1] = 0,
+  // the last class for every u beyond), with its size and mark alpha / q.
+  // thr[j] for j >= n_cls - 1 is +infinity, so the class index is the
+  // number of thresholds at or below u.
+  int32_t n_cls, pad2;
+  int32_t cls[5], pad3;
+  float thrf[4];
+  double thr[4];
+  double mark[5];
   uint32_t key0, key1;
   DevFun psi;
   const DevFactor* fac;

@@ -132,6 +132,9 @@ hipError_t launch_scatter_add(const double* src, const int32_t* map, int count, 
 hipError_t launch_jacobian_apply(const double* jac, int64_t n_rows, int64_t ld, int64_t n_cols, const double* w,
                                  const void* stats, const double* data, double* grad, double* loss, hipStream_t st);
 hipError_t launch_node_moments(const void* stats, int64_t n, double* var, double* se, hipStream_t st);
+hipError_t launch_merge_estimates(void* acc, double* acc_jac, int64_t acc_ld, const void* add, const double* add_jac,
+                                  int64_t add_ld, int64_t n_params, const int64_t* index, int64_t n_add,
+                                  hipStream_t st);
 hipError_t launch_stage(const StageJob* jobs, int n_jobs, const int32_t* perm, double* cd, float* cf,
                         hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t st);

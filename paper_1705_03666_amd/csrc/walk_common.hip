@@ -145,6 +145,34 @@ __global__ void k_jacobian_apply(const double* __restrict__ jac, int64_t n_rows,
   }
 }
 
+// Merges a second sample of node index[k] into the node's estimate: Chan's
+// merge of the Welford triples, sums of the counts, and the Jacobian rows
+// weighted by their path counts.  One block per merged node.
+__global__ void k_merge_estimates(pdd_node_stat_dev* __restrict__ acc, double* __restrict__ acc_jac,
+                                  int64_t acc_ld, const pdd_node_stat_dev* __restrict__ add,
+                                  const double* __restrict__ add_jac, int64_t add_ld, int64_t n_params,
+                                  const int64_t* __restrict__ index) {
+  const int64_t k = blockIdx.x;
+  const int64_t i = index[k];
+  const pdd_node_stat_dev a = acc[i];
+  const pdd_node_stat_dev b = add[k];
+  const double na = (double)a.n, nb = (double)b.n;
+  const double tot = na + nb;
+  if (acc_jac != nullptr && add_jac != nullptr && tot > 0.0) {
+    for (int64_t c = threadIdx.x; c < n_params; c += blockDim.x) {
+      const double v = (na * acc_jac[(size_t)i * acc_ld + c] + nb * add_jac[(size_t)k * add_ld + c]) / tot;
+      acc_jac[(size_t)i * acc_ld + c] = v;
+    }
+  }
+  if (threadIdx.x == 0) {
+    double n = na, m = a.mean, q = a.m2;
+    chan_merge(n, m, q, nb, b.mean, b.m2);
+    pdd_node_stat_dev r;
+    r.mean = m; r.m2 = q; r.n = a.n + b.n; r.steps = a.steps + b.steps; r.censored = a.censored + b.censored;
+    acc[i] = r;
+  }
+}
+
 // var_i = m2_i / (n_i - 1) (0 for n_i < 2), se_i = sqrt(var_i / n_i).
 __global__ void k_node_moments(const pdd_node_stat_dev* __restrict__ stats, int64_t n, double* __restrict__ var,
                                double* __restrict__ se) {
@@ -227,6 +255,14 @@ hipError_t launch_jacobian_apply(const double* jac, int64_t n_rows, int64_t ld, 
   const int64_t blocks = (n_cols + kWave - 1) / kWave;
   hipLaunchKernelGGL(k_jacobian_apply, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kBlock), 0, st, jac, n_rows,
                      ld, n_cols, w, (const pdd_node_stat_dev*)stats, data, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_estimates(void* acc, double* acc_jac, int64_t acc_ld, const void* add, const double* add_jac,
+                                  int64_t add_ld, int64_t n_params, const int64_t* index, int64_t n_add,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_merge_estimates, dim3((unsigned)n_add), dim3(kBlock), 0, st, (pdd_node_stat_dev*)acc, acc_jac,
+                     acc_ld, (const pdd_node_stat_dev*)add, add_jac, add_ld, n_params, index);
   return hipGetLastError();
 }
 

@@ -232,3 +232,41 @@ def test_graph_plans_do_not_depend_on_caller_buffers(pdd):
     assert pdd.cached_plan_count() <= 16
     pdd.release_workspace()
     assert pdd.cached_plan_count() == 0
+
+
+def test_merge_estimates_equals_the_pooled_sample(pdd):
+    """A second sample (another seed) of some nodes merged into an estimate
+    gives the statistics of the pooled per-path values (mean, sum of squared
+    deviations, counts) and the path-count weighted Jacobian."""
+    P, nodes = _c5_small(8, 6, deg_terms=False)
+    pa = np.array([500, 80, 1000, 3, 256, 700], np.int64)
+    dt = 2e-3
+    kw = dict(precision="fp64", schedule="persistent", chunk_paths=256, dump=True)
+    a = pdd.mc_value_jacobian(P, nodes, pa, dt, 1, **kw)
+    sel = np.array([4, 0, 2])
+    pb = np.array([300, 41, 999], np.int64)
+    b = pdd.mc_value_jacobian(P, nodes[sel], pb, dt, 2, **kw)
+    torch.cuda.synchronize()
+    ja, jb = a["jac"].cpu().numpy().copy(), b["jac"].cpu().numpy().copy()
+    offa = np.concatenate([[0], np.cumsum(pa)])
+    offb = np.concatenate([[0], np.cumsum(pb)])
+    phia, phib = a["phi"].cpu().numpy(), b["phi"].cpu().numpy()
+    stepsa, stepsb = a["steps"].cpu().numpy().copy(), b["steps"].cpu().numpy().copy()
+    m = pdd.merge_estimates(a, b, sel)
+    torch.cuda.synchronize()
+    mean, m2, n = m["mean"].cpu().numpy(), m["m2"].cpu().numpy(), m["n"].cpu().numpy()
+    J = m["jac"].cpu().numpy()
+    for i in range(6):
+        vals = phia[offa[i]:offa[i + 1]]
+        want_j = ja[i]
+        if i in sel:
+            k = int(np.nonzero(sel == i)[0][0])
+            vals = np.concatenate([vals, phib[offb[k]:offb[k + 1]]])
+            want_j = (pa[i] * ja[i] + pb[k] * jb[k]) / (pa[i] + pb[k])
+            assert m["steps"].cpu().numpy()[i] == stepsa[i] + stepsb[k]
+        assert n[i] == len(vals)
+        assert mean[i] == pytest.approx(vals.mean(), rel=1e-12, abs=1e-14)
+        assert m2[i] == pytest.approx(np.sum((vals - vals.mean()) ** 2), rel=1e-10, abs=1e-12)
+        assert np.allclose(J[i], want_j, rtol=1e-13, atol=1e-15)
+    var = np.where(n > 1, m2 / np.maximum(n - 1, 1), 0.0)
+    assert np.allclose(m["se"].cpu().numpy(), np.sqrt(var / n), rtol=1e-15)
