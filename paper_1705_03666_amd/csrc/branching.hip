@@ -345,15 +345,16 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
 // and is tested against the boundary after each sub-step except the one that
 // ends at its death (the children are tested at their birth instead; a test
 // there would anticipate the death time).  With the boundary correction the
-// test after a sub-step of length h uses D shrunk by c0 sigma sqrt(h).  A particle found outside is
-// projected and stopped: every output time t_i >= s picks up g(P X, t_i - s).
+// test after a sub-step of length h uses D shrunk by c0 sigma sqrt(h).  A
+// particle found outside is projected and stopped: every output time t_i >= s picks up g(P X, t_i - s).
 // A particle inside at an output time t_k multiplies factor k by psi(X); a
 // branching at time s multiplies every factor with t_i > s by alpha_I / q_I.
 // The per-tree factors are FP64 products; a finished tree enters the
 // wavefront's FP64 Welford triple of every output time (kept in LDS, lanes
-// in order).  Lanes run up to eight sub-steps per round and stop at their
-// first event (output time, stop, death, end), which is handled after the
-// round, so the rare event code is not interleaved with every sub-step.
+// in order).  Lanes run sub-steps in rounds over windows of their Gaussians
+// (bvp_round) and stop at their first event (output time, stop, death, end),
+// which is handled after the round, so the rare event code is not
+// interleaved with every sub-step.
 // The statistics' step count is the number of particle sub-steps.
 //
 // Gaussians: number n DIM + c of a particle (sub-step n, coordinate c) is
@@ -374,26 +375,6 @@ struct BvScalars<double> {
   __device__ static double t(const BranchBoundary& B, int i) { return B.times[i]; }
   __device__ static double shift(const BranchBoundary& B) { return B.shift; }
 };
-
-// inside D shrunk by delta >= 0 (box faces moved in; ball radius R - delta, at least 0)
-template <typename R, int DIM>
-__device__ __forceinline__ bool inside_shrunk(const Dom<R>& D, const R* x, R delta) {
-  if (D.kind == DOM_BOX) {
-    bool in = true;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) in = in && (x[k] > D.lo[k] + delta) && (x[k] < D.hi[k] - delta);
-    return in;
-  }
-  R r2 = (R)0;
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    const R d = x[k] - D.ctr[k];
-    r2 += d * d;
-  }
-  R rs = D.rad - delta;
-  rs = rs > (R)0 ? rs : (R)0;
-  return r2 < rs * rs;
-}
 
 template <typename R>
 __device__ __forceinline__ Dom<R> bvp_dom(const BranchBoundary& B);
@@ -429,6 +410,167 @@ __device__ __forceinline__ R bvp_g(const BranchParams& P, const BranchBoundary& 
   return v;
 }
 
+// Event batching: lanes with an event wait until this many have one (or the
+// conditions in k_branch_bvp), so the event code runs for several at once.
+constexpr int kEvBatch = 64;
+constexpr int kEvWait = 32;
+
+// Sub-steps per round: the Gaussians of a particle are taken in windows of
+// kW = steps * DIM numbers, a whole number of Philox blocks (1-D and 2-D: two
+// blocks of four; 3-D: three), so every lane of a round draws the same kNB
+// blocks of its own window and finds its Gaussians at fixed slots.
+template <int DIM>
+constexpr int bvp_round_steps() { return DIM == 1 ? 8 : 4; }
+
+// One round of sub-steps over each stepping lane's current window of
+// Gaussians (window gidx / kW): a lane whose next Gaussian is number o DIM of
+// the window takes sub-steps o, o + 1, .. until its first event or the end of
+// the window.  A sub-step ends at min(s + dt, lim), lim = min(end of stepping,
+// next output time); the particle is tested against D shrunk by shift sd
+// unless the sub-step ends at its death (dlim: lim is the death time, so a
+// sub-step ending at lim is the death).  Predicated, without branches:
+// `stepping` is cleared at the first event, `stopped` set when that event is
+// a boundary stop.  KIND is the domain kind and SHIFT whether shift != 0
+// (both uniform over the launch).  In FP32 the uniform parameters are copied
+// into vector registers first, so the instructions that read them can share
+// an issue slot.
+template <typename R, int DIM, int LAYOUT, int KIND, bool SHIFT>
+__device__ __forceinline__ void bvp_round(const Dom<R>& D, R sigma, R dt, R shift, uint64_t label, int attempt,
+                                          uint32_t tree, uint32_t point, uint32_t k0, uint32_t k1, R lim, bool dlim,
+                                          R* X, R& s, uint32_t& gidx, bool& stepping, bool& stopped, int& nsub) {
+  using NZr = Normals<R, LAYOUT>;
+  constexpr int kPer = NZr::kPerBlock;
+  constexpr int kSub = bvp_round_steps<DIM>();
+  constexpr int kW = kSub * DIM;
+  constexpr int kNB = kW / kPer;
+  static_assert(kW % kPer == 0, "a window is a whole number of Philox blocks");
+  R zb[kW];
+  const uint32_t w = gidx / (uint32_t)kW;
+  const int o = (int)((gidx % (uint32_t)kW) / (uint32_t)DIM);
+#pragma unroll
+  for (int b = 0; b < kNB; ++b) {
+    const uint32_t j = w * (uint32_t)kNB + (uint32_t)b;
+    const uint32_t c0 = (uint32_t)label;
+    const uint32_t c1 = (5u << 28) | ((uint32_t)attempt << 24) | ((uint32_t)((label >> 32) & 0xFFFFu) << 8) |
+                        ((j >> 8) & 0xFFu);
+    const uint32_t c3 = (point & 0xFFFFFFu) | ((j & 0xFFu) << 24);
+    uint32_t ka = k0, kb = k1;
+    asm volatile("" : "+s"(ka), "+s"(kb));
+    NZr::gen(c0, c1, tree, c3, ka, kb, &zb[b * kPer]);
+  }
+  R lo[DIM], hi[DIM], ctr[DIM], rad = D.rad;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    lo[k] = D.lo[k];
+    hi[k] = D.hi[k];
+    ctr[k] = D.ctr[k];
+  }
+  if constexpr (sizeof(R) == 4) {
+    asm volatile("" : "+v"(sigma), "+v"(dt), "+v"(shift));
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      if constexpr (KIND == DOM_BOX) asm volatile("" : "+v"(lo[k]), "+v"(hi[k]));
+      if constexpr (KIND == DOM_BALL) asm volatile("" : "+v"(ctr[k]));
+    }
+    if constexpr (KIND == DOM_BALL) asm volatile("" : "+v"(rad));
+  }
+  int n = 0;
+#pragma unroll
+  for (int q = 0; q < kSub; ++q) {
+    const bool st = stepping && o <= q;
+    const R sn = fmin(s + dt, lim);
+    const R sd = sigma * fsqrt(sn - s);
+    R Xn[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) Xn[k] = X[k] + sd * zb[q * DIM + k];
+    bool out = false;
+    if constexpr (KIND == DOM_BOX) {
+      bool in = true;
+      if constexpr (SHIFT) {
+        const R delta = shift * sd;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) in = in && (Xn[k] > lo[k] + delta) && (Xn[k] < hi[k] - delta);
+      } else {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) in = in && (Xn[k] > lo[k]) && (Xn[k] < hi[k]);
+      }
+      out = !in;
+    } else if constexpr (KIND == DOM_BALL) {
+      R r2 = (R)0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const R d = Xn[k] - ctr[k];
+        r2 += d * d;
+      }
+      R rs = rad;
+      if constexpr (SHIFT) {
+        rs = rad - shift * sd;
+        rs = rs > (R)0 ? rs : (R)0;
+      }
+      out = !(r2 < rs * rs);
+    }
+    const bool at = !(sn < lim);
+    const bool stop = out && !(dlim && at);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) X[k] = st ? Xn[k] : X[k];
+    s = st ? sn : s;
+    n += st ? 1 : 0;
+    stopped = stopped || (st && stop);
+    stepping = stepping && !(st && (stop || at));
+  }
+  gidx += (uint32_t)(n * DIM);
+  nsub += n;
+}
+
+// Boundary stops of several lanes at once: every lane with `need` multiplies
+// Pt[i] by g(xp, t_i - s0) for each output time index f <= i < nt, f the
+// first with t_i >= s0.  The (lane, time) pairs are dealt out one per lane,
+// 64 per pass, through cross-lane reads, so a batch of stops costs about one
+// evaluation of g per pass instead of one per output time; every factor is
+// still the single product Pt[i] * g, so results do not change.  All lanes
+// of the wavefront must call it.  `tms` holds the output times.
+template <typename R, int DIM>
+__device__ __forceinline__ void stop_products(bool need, const R* xp, R s0, double* Pt, const BranchParams& P,
+                                              const BranchBoundary& BB, const R* tms, int nt, int lane) {
+  if (!__any(need)) return;
+  int f = nt;
+#pragma unroll
+  for (int i = kMaxTimes - 1; i >= 0; --i)
+    if (i < nt && tms[i] >= s0) f = i;
+  const int c = need ? nt - f : 0;
+  int incl = c;   // inclusive prefix sum of c over the lanes
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int v = __shfl_up(incl, (unsigned)d);
+    if (lane >= d) incl += v;
+  }
+  const int off = incl - c;
+  const int total = __shfl(incl, kWave - 1);
+  for (int base = 0; base < total; base += kWave) {
+    const int g = base + lane;
+    int l = 0;   // the lane whose pairs hold g: the first with incl > g
+#pragma unroll
+    for (int step = kWave / 2; step > 0; step >>= 1) {
+      const int v = __shfl(incl, l + step - 1);
+      if (v <= g) l += step;
+    }
+    l = l < kWave ? l : kWave - 1;
+    R xs[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) xs[k] = __shfl(xp[k], l);
+    const R sl = __shfl(s0, l);
+    const int i = __shfl(f, l) + (g - __shfl(off, l));
+    double r = 1.0;
+    if (g < total) r = (double)bvp_g<R, DIM>(P, BB, xs, tms[i] - sl);
+#pragma unroll
+    for (int i2 = 0; i2 < kMaxTimes; ++i2) {
+      const int src = off + (i2 - f) - base;
+      const double v = __shfl(r, src >= 0 && src < kWave ? src : 0);
+      if (need && i2 >= f && i2 < nt && src >= 0 && src < kWave) Pt[i2] *= v;
+    }
+  }
+}
+
 // Events of a particle found at the end of a sub-step.
 enum : int { EV_OUT = 1, EV_STOP = 2, EV_DEATH = 4, EV_END = 8 };
 
@@ -438,14 +580,6 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
              uint32_t* __restrict__ qhead, ItemStat* __restrict__ istat, double* __restrict__ dump_val,
              int64_t* __restrict__ dump_segs, int64_t trees, StackEntry<R>* __restrict__ spill,
              int64_t spill_entries) {
-  using NZr = Normals<R, LAYOUT>;
-  constexpr int kPer = NZr::kPerBlock;
-  // sub-steps per round between event handling, and the Philox blocks a
-  // round may draw on: every stepping lane generates kNB blocks at the start
-  // of a round (all lanes together), starting with the block that holds its
-  // next Gaussian
-  constexpr int kSub = DIM == 1 ? 8 : (DIM == 2 ? 4 : 2);
-  constexpr int kNB = (kPer - 1 + kSub * DIM + kPer - 1) / kPer;
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const int wid = (int)(threadIdx.x / kWave);
   const int64_t glane = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -458,6 +592,10 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
   // through which a finished tree hands its values to those lanes
   __shared__ double wst[kBlock / kWave][3 * kMaxTimes + 1];
   __shared__ double wrow[kBlock / kWave][kMaxTimes];
+  // the output times, for lanes that index them at run time
+  __shared__ R tms[kMaxTimes];
+  if (threadIdx.x < (unsigned)kMaxTimes) tms[threadIdx.x] = BvScalars<R>::t(BB, (int)threadIdx.x);
+  __syncthreads();
 
   const uint32_t k0 = P.key0, k1 = P.key1;
   const R sigma = BrScalars<R>::sigma(P);
@@ -514,6 +652,9 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
     };
     start_tree();
     int64_t lsub = 0, lcens = 0, lredraw = 0;
+    // a lane's pending event (0: none); rounds since events were last handled
+    int ev = 0;
+    int since = 0;
 
     while (__any(active)) {
       bool done = false, censored = false, fail = false;
@@ -522,13 +663,13 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
       for (;;) {
         const bool need = active && fresh && !done && !fail;
         if (!__any(need)) break;
+        bool stop0 = false;
         if (need) {
-          bool stop0 = false;
           ++segs;
           if (segs > P.max_segments) {
             fail = true;
           } else if (bounded && !inside<R, DIM>(D, X)) {
-            stop0 = true;   // born outside: stopped at its birth time
+            stop0 = true;
           } else {
             R ulife;
             br_uniforms<R, LAYOUT>(label, attempt, tree, (uint32_t)point, k0, k1, ulife, utype);
@@ -545,14 +686,15 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
             gidx = 0;
             fresh = false;
           }
+        }
+        {
+          // born outside: stopped at its birth time
+          R xp[3] = {(R)0, (R)0, (R)0};
+          if (stop0) project<R, DIM>(D, X, xp);
+          stop_products<R, DIM>(stop0, xp, s, Pt, P, BB, tms, nt, lane);
+        }
+        if (need) {
           if (stop0) {
-            R xp[3];
-            project<R, DIM>(D, X, xp);
-#pragma unroll
-            for (int i = 0; i < kMaxTimes; ++i) {
-              const R ti = BvScalars<R>::t(BB, i);
-              if (i < nt && ti >= s) Pt[i] *= (double)bvp_g<R, DIM>(P, BB, xp, ti - s);
-            }
             if (sp == 0) {
               done = true;
             } else {
@@ -567,201 +709,193 @@ k_branch_bvp(const BranchParams P, const BranchBoundary BB, const WorkItem* __re
           }
         }
       }
-      // ---- up to kSub sub-steps per stepping lane; a lane stops at its first event
-      int ev = 0;
-      bool stepping = active && !fresh && !done && !fail;
-      R zb[kNB * kPer];
-      int o0 = 0;
-      if (stepping) {
-        const uint32_t j0 = gidx / (uint32_t)kPer;
-        o0 = (int)(gidx % (uint32_t)kPer);
-#pragma unroll
-        for (int b = 0; b < kNB; ++b) {
-          const uint32_t j = j0 + (uint32_t)b;
-          const uint32_t c0 = (uint32_t)label;
-          const uint32_t c1 = (5u << 28) | ((uint32_t)attempt << 24) | ((uint32_t)((label >> 32) & 0xFFFFu) << 8) |
-                              ((j >> 8) & 0xFFu);
-          const uint32_t c3 = ((uint32_t)point & 0xFFFFFFu) | ((j & 0xFFu) << 24);
-          uint32_t ka = k0, kb = k1;
-          asm volatile("" : "+s"(ka), "+s"(kb));
-          NZr::gen(c0, c1, tree, c3, ka, kb, &zb[b * kPer]);
-        }
+      // ---- a round of sub-steps; a lane stops at its first event, whose kind
+      // follows from where it stopped
+      bool stepping = active && !fresh && !done && !fail && ev == 0;
+      if (stepping && !(s < send)) {   // nothing left to step (a last output time of 0)
+        ev = EV_END;
+        stepping = false;
       }
-      for (int q = 0; q < kSub; ++q) {
-        if (stepping && !(s < send)) {   // nothing left to step (a last output time of 0)
-          ev = EV_END;
-          stepping = false;
+      const bool stepped = stepping;
+      bool stopped = false;
+      {
+        R lim = send;
+        if (kout < nt && tk < lim) lim = tk;
+        const bool dcand = sdeath < tend;
+        // the sub-step that ends at lim ends at the death: no boundary test
+        const bool dlim = dcand && lim == sdeath;
+        int nsub = 0;
+#define PDD_BVP_ROUND(KIND, SHIFT)                                                                              \
+  bvp_round<R, DIM, LAYOUT, KIND, SHIFT>(D, sigma, dt, shift, label, attempt, tree, (uint32_t)point, k0, k1, lim, \
+                                         dlim, X, s, gidx, stepping, stopped, nsub)
+        if (D.kind == DOM_BOX) {
+          if (shift != (R)0) PDD_BVP_ROUND(DOM_BOX, true);
+          else PDD_BVP_ROUND(DOM_BOX, false);
+        } else if (D.kind == DOM_BALL) {
+          if (shift != (R)0) PDD_BVP_ROUND(DOM_BALL, true);
+          else PDD_BVP_ROUND(DOM_BALL, false);
+        } else {
+          PDD_BVP_ROUND(DOM_FREE, false);
         }
-        if (stepping) {
-          R sn = s + dt;
-          if (send < sn) sn = send;
-          if (kout < nt && tk < sn) sn = tk;
-          // Gaussians gidx .. gidx + DIM - 1 sit at o0 + q DIM + c of the round's blocks
-          R z[DIM];
-#pragma unroll
-          for (int c = 0; c < DIM; ++c) {
-            const int k = q * DIM + c;
-            R v = zb[k];
-#pragma unroll
-            for (int m = 1; m < kPer; ++m) v = o0 == m ? zb[k + m] : v;
-            z[c] = v;
-          }
-          gidx += DIM;
-          const R sd = sigma * fsqrt(sn - s);
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) X[k] = X[k] + sd * z[k];
-          s = sn;
-          ++lsub;
-          const bool dies = s == sdeath && sdeath < tend;
-          const bool out =
-              bounded && (shift > (R)0 ? !inside_shrunk<R, DIM>(D, X, shift * sd) : !inside<R, DIM>(D, X));
-          if (!dies && out) {
+#undef PDD_BVP_ROUND
+        lsub += nsub;
+        if (stepped && !stepping) {
+          if (stopped) {
             ev = EV_STOP;
-          } else {
+          } else {   // s == lim
             if (kout < nt && s == tk) ev |= EV_OUT;
-            if (!(s < send)) ev |= dies ? EV_DEATH : EV_END;
+            if (!(s < send)) ev |= (dcand && s == sdeath) ? EV_DEATH : EV_END;
           }
-          stepping = ev == 0;
         }
       }
-      // ---- events
-      if (ev != 0) {
-        bool pop = false;
-        if (ev & EV_OUT) {
-          const double pv = (double)psi_value<R, DIM>(P, X);
-#pragma unroll
-          for (int i = 0; i < kMaxTimes; ++i)
-            if (i == kout) Pt[i] *= pv;
-          ++kout;
-#pragma unroll
-          for (int i = 0; i < kMaxTimes; ++i)
-            if (i == kout) tk = BvScalars<R>::t(BB, i);
-        }
-        if (ev & EV_STOP) {
+      // ---- events, handled for several lanes at once: a lane with an event
+      // waits (takes no sub-steps) until kEvBatch lanes have one, every active
+      // lane has one, kEvWait rounds have passed, or a tree has ended
+      const uint64_t pmask = ballot(ev != 0);
+      const bool handle = __popcll(pmask) >= kEvBatch || pmask == ballot(active) || since >= kEvWait ||
+                          __any(done || fail);
+      since = handle ? 0 : since + 1;
+      if (handle) {
+        {
           // projected onto the boundary and stopped at time s
-          R xp[3];
-          project<R, DIM>(D, X, xp);
+          const bool stopnow = (ev & EV_STOP) != 0;
+          R xp[3] = {(R)0, (R)0, (R)0};
+          if (stopnow) project<R, DIM>(D, X, xp);
+          stop_products<R, DIM>(stopnow, xp, s, Pt, P, BB, tms, nt, lane);
+        }
+        if (ev != 0) {
+          bool pop = false;
+          if (ev & EV_OUT) {
+            const double pv = (double)psi_value<R, DIM>(P, X);
 #pragma unroll
-          for (int i = 0; i < kMaxTimes; ++i) {
-            const R ti = BvScalars<R>::t(BB, i);
-            if (i < nt && ti >= s) Pt[i] *= (double)bvp_g<R, DIM>(P, BB, xp, ti - s);
+            for (int i = 0; i < kMaxTimes; ++i)
+              if (i == kout) Pt[i] *= pv;
+            ++kout;
+#pragma unroll
+            for (int i = 0; i < kMaxTimes; ++i)
+              if (i == kout) tk = BvScalars<R>::t(BB, i);
           }
-          pop = true;
-        } else if (ev & EV_END) {
-          pop = true;   // reached the last output time
-        } else if (ev & EV_DEATH) {
-          // offspring count: smallest I with u < q_0 + ... + q_I (among q_I > 0)
-          const int jc = offspring_class<R>(P, utype);
-          const int I = class_size(P, jc);
-          const double ratio = class_mark(P, jc);
-#pragma unroll
-          for (int i = 0; i < kMaxTimes; ++i)
-            if (i < nt && BvScalars<R>::t(BB, i) > sdeath) Pt[i] *= ratio;
-          if (I == 0) {
+          if (ev & EV_STOP) {
             pop = true;
-          } else {
-            const uint64_t first = B * label;
-            if (label >= (1ull << 47) || first + (uint64_t)(I - 1) >= (1ull << 48) ||
-                sp + I - 1 > spill_entries + kLdsDepth) {
-              fail = true;
-            } else {
-              for (int i = I - 1; i >= 1; --i) {
-                StackEntry<R> e;
-                const uint64_t cl = first + (uint64_t)i;
-                e.lo = (uint32_t)cl;
-                e.hi = (uint32_t)(cl >> 32);
+          } else if (ev & EV_END) {
+            pop = true;   // reached the last output time
+          } else if (ev & EV_DEATH) {
+            // offspring count: smallest I with u < q_0 + ... + q_I (among q_I > 0)
+            const int jc = offspring_class<R>(P, utype);
+            const int I = class_size(P, jc);
+            const double ratio = class_mark(P, jc);
+            if (ratio != 1.0) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) e.x[k] = k < DIM ? X[k] : (R)0;
-                e.t = sdeath;
-                if (sp < kLdsDepth) lds[wid][sp][lane] = e;
-                else spill[(int64_t)(sp - kLdsDepth) * nlanes + glane] = e;
-                ++sp;
+              for (int i = 0; i < kMaxTimes; ++i)
+                if (i < nt && BvScalars<R>::t(BB, i) > sdeath) Pt[i] *= ratio;
+            }
+            if (I == 0) {
+              pop = true;
+            } else {
+              const uint64_t first = B * label;
+              if (label >= (1ull << 47) || first + (uint64_t)(I - 1) >= (1ull << 48) ||
+                  sp + I - 1 > spill_entries + kLdsDepth) {
+                fail = true;
+              } else {
+                for (int i = I - 1; i >= 1; --i) {
+                  StackEntry<R> e;
+                  const uint64_t cl = first + (uint64_t)i;
+                  e.lo = (uint32_t)cl;
+                  e.hi = (uint32_t)(cl >> 32);
+#pragma unroll
+                  for (int k = 0; k < 3; ++k) e.x[k] = k < DIM ? X[k] : (R)0;
+                  e.t = sdeath;
+                  if (sp < kLdsDepth) lds[wid][sp][lane] = e;
+                  else spill[(int64_t)(sp - kLdsDepth) * nlanes + glane] = e;
+                  ++sp;
+                }
+                label = first;
+                s = sdeath;
+                fresh = true;
               }
-              label = first;
-              s = sdeath;
+            }
+          }
+          if (pop && !fail) {
+            if (sp == 0) {
+              done = true;
+            } else {
+              --sp;
+              const StackEntry<R> e = sp < kLdsDepth ? lds[wid][sp][lane]
+                                                     : spill[(int64_t)(sp - kLdsDepth) * nlanes + glane];
+              label = (uint64_t)e.lo | ((uint64_t)e.hi << 32);
+#pragma unroll
+              for (int k = 0; k < DIM; ++k) X[k] = e.x[k];
+              s = e.t;
               fresh = true;
             }
           }
         }
-        if (pop && !fail) {
-          if (sp == 0) {
+        if (fail) {
+          ++lredraw;
+          ++attempt;
+          if (attempt >= 16) {
             done = true;
+            censored = true;
+            ++lcens;
           } else {
-            --sp;
-            const StackEntry<R> e = sp < kLdsDepth ? lds[wid][sp][lane]
-                                                   : spill[(int64_t)(sp - kLdsDepth) * nlanes + glane];
-            label = (uint64_t)e.lo | ((uint64_t)e.hi << 32);
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) X[k] = e.x[k];
-            s = e.t;
-            fresh = true;
-          }
-        }
-      }
-      if (fail) {
-        ++lredraw;
-        ++attempt;
-        if (attempt >= 16) {
-          done = true;
-          censored = true;
-          ++lcens;
-        } else {
-          start_tree();
-        }
-      }
-      if (done) {
-        if (censored) {
-#pragma unroll
-          for (int i = 0; i < kMaxTimes; ++i) Pt[i] = 0.0;
-        }
-        if (dump_val != nullptr) {
-          const int64_t o = ((int64_t)point * trees + (int64_t)tree) * nt;
-#pragma unroll
-          for (int i = 0; i < kMaxTimes; ++i)
-            if (i < nt) dump_val[o + i] = Pt[i];
-          if (dump_segs != nullptr) dump_segs[(int64_t)point * trees + (int64_t)tree] = segs;
-        }
-      }
-      // finished trees enter the wave's sums in lane order: the tree's lane
-      // stages its values in LDS, lane i adds value i to time i's sums
-      uint64_t dmask = ballot(done);
-      const uint64_t dmask0 = dmask;
-      double* const row = &wrow[wid][0];
-      while (dmask != 0) {
-        const int l = __builtin_ctzll(dmask);
-        dmask &= dmask - 1;
-        __builtin_amdgcn_wave_barrier();
-        if (lane == l) {
-#pragma unroll
-          for (int i = 0; i < kMaxTimes; ++i) row[i] = Pt[i];
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane < nt) {
-          const double v = row[lane];
-          const bool first = W[3 * kMaxTimes] == 0.0;
-          const double K = first ? v : W[2 * kMaxTimes + lane];
-          if (first) W[2 * kMaxTimes + lane] = v;
-          const double dv = v - K;
-          W[lane] += dv;
-          W[kMaxTimes + lane] += dv * dv;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) W[3 * kMaxTimes] += 1.0;
-        __builtin_amdgcn_wave_barrier();
-      }
-      // refill
-      if (dmask0 != 0) {
-        const uint32_t ntr = cursor + (uint32_t)lane_rank(dmask0);
-        cursor += (uint32_t)__popcll(dmask0);
-        if (done) {
-          if (ntr < pend) {
-            tree = ntr;
-            attempt = 0;
             start_tree();
-          } else {
-            active = false;
           }
         }
+        if (done) {
+          if (censored) {
+#pragma unroll
+            for (int i = 0; i < kMaxTimes; ++i) Pt[i] = 0.0;
+          }
+          if (dump_val != nullptr) {
+            const int64_t o = ((int64_t)point * trees + (int64_t)tree) * nt;
+#pragma unroll
+            for (int i = 0; i < kMaxTimes; ++i)
+              if (i < nt) dump_val[o + i] = Pt[i];
+            if (dump_segs != nullptr) dump_segs[(int64_t)point * trees + (int64_t)tree] = segs;
+          }
+        }
+        // finished trees enter the wave's sums in lane order: the tree's lane
+        // stages its values in LDS, lane i adds value i to time i's sums
+        uint64_t dmask = ballot(done);
+        const uint64_t dmask0 = dmask;
+        double* const row = &wrow[wid][0];
+        while (dmask != 0) {
+          const int l = __builtin_ctzll(dmask);
+          dmask &= dmask - 1;
+          __builtin_amdgcn_wave_barrier();
+          if (lane == l) {
+#pragma unroll
+            for (int i = 0; i < kMaxTimes; ++i) row[i] = Pt[i];
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (lane < nt) {
+            const double v = row[lane];
+            const bool first = W[3 * kMaxTimes] == 0.0;
+            const double K = first ? v : W[2 * kMaxTimes + lane];
+            if (first) W[2 * kMaxTimes + lane] = v;
+            const double dv = v - K;
+            W[lane] += dv;
+            W[kMaxTimes + lane] += dv * dv;
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (lane == 0) W[3 * kMaxTimes] += 1.0;
+          __builtin_amdgcn_wave_barrier();
+        }
+        // refill
+        if (dmask0 != 0) {
+          const uint32_t ntr = cursor + (uint32_t)lane_rank(dmask0);
+          cursor += (uint32_t)__popcll(dmask0);
+          if (done) {
+            if (ntr < pend) {
+              tree = ntr;
+              attempt = 0;
+              start_tree();
+            } else {
+              active = false;
+            }
+          }
+        }
+        ev = 0;
       }
     }
 
