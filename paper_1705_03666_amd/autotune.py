@@ -159,11 +159,14 @@ def tune_batch(problems, node_problem, nodes, paths, dt_or_eps: float, seed: int
 
 
 def tune_branching(problem, points, trees: int, seed: int = 0, precision: str = "fp32", boundary=None,
-                   items_per_wave: int = 1, repeats: int = 1, force: bool = False, log=None) -> dict:
+                   items_per_wave: int = 8, repeats: int = 1, force: bool = False, log=None) -> dict:
     """Best schedule of the branching estimator (free space, or with a
     boundary when `boundary` is given) for this dimension and precision,
     compared by simulated segments (sub-steps) per second; stored in the
-    library's table."""
+    library's table.  The sample gives every resident wavefront at least
+    `items_per_wave` items, so it sees the imbalance at the end of a launch
+    that the caller's workload will see (with 1024 points x 1e5 trees it is
+    the whole workload)."""
     kernel = "branch_bvp" if boundary is not None else "branch"
     dim = int(problem.ndim)
     s = _start(kernel, dim, precision)

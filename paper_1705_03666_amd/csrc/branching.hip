@@ -420,7 +420,7 @@ constexpr int kEvWait = 32;
 // blocks of four; 3-D: three), so every lane of a round draws the same kNB
 // blocks of its own window and finds its Gaussians at fixed slots.
 template <int DIM>
-constexpr int bvp_round_steps() { return DIM == 1 ? 8 : 4; }
+constexpr int bvp_round_steps() { return DIM == 1 ? 16 : (DIM == 2 ? 8 : 4); }
 
 // One round of sub-steps over each stepping lane's current window of
 // Gaussians (window gidx / kW): a lane whose next Gaussian is number o DIM of

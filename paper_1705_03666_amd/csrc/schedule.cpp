@@ -109,11 +109,13 @@ bool lookup(int kernel, int dim, int precision, Entry* out) {
 // Built-in defaults, measured on MI355X: the 3-D C5 walk (forward and
 // adjoint alike) for the linear kernels; C4 / C7 (k_branch) and C6
 // (k_branch_bvp), 1024 points x 1e5 trees, for branching: four blocks per
-// CU (the FP32 branching kernels are built for four waves per SIMD) and
-// items of 16384 trees (2 blocks and 2048-tree items took 2.0x on C4 and
-// 1.2x on C6).
+// CU (the FP32 branching kernels are built for four waves per SIMD), items of
+// 16384 trees for k_branch (2 blocks and 2048-tree items took 2.0x on C4) and
+// of 4096 trees for k_branch_bvp, whose trees are long enough that the last
+// items of a launch decide its end (16384-tree items took 1.15x on C6).
 Entry defaults(int kernel, bool fp32) {
-  if (kernel == PDD_KERNEL_BRANCH || kernel == PDD_KERNEL_BRANCH_BVP) return Entry{16384, fp32 ? 4 : 2, 1};
+  if (kernel == PDD_KERNEL_BRANCH) return Entry{16384, fp32 ? 4 : 2, 1};
+  if (kernel == PDD_KERNEL_BRANCH_BVP) return Entry{4096, fp32 ? 4 : 2, 1};
   return Entry{16384, fp32 ? 8 : 4, 3};
 }
 
