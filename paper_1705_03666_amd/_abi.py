@@ -5,7 +5,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpdd.so")
+# PDD_LIBRARY selects another build of the library (e.g. a host-sanitizer build)
+LIB_PATH = os.environ.get("PDD_LIBRARY") or os.path.join(HERE, "libpdd.so")
 
 PDD_OK, PDD_WARN_CENSORED, PDD_WARN_REDRAWN = 0, 1, 2
 PDD_ERR_INVALID_ARG, PDD_ERR_UNSUPPORTED, PDD_ERR_NOT_ADMISSIBLE, PDD_ERR_HIP, PDD_ERR_NO_MEMORY = -1, -2, -3, -4, -5

@@ -239,6 +239,82 @@ def test_branching_bvp_arguments_are_checked_on_the_host(abi):
     assert lib.pdd_branching_bvp(None, C.byref(bd), None, 1, 10, 0, C.byref(o), None, None) == abi.PDD_ERR_INVALID_ARG
 
 
+def test_batch_arguments_are_checked_on_the_host(abi):
+    """pdd_mc_interface_batch / pdd_wos_interface_batch: the problem array,
+    every problem (same checks as a single call), the batch restrictions and
+    the node->problem map are checked before any GPU work."""
+    lib = abi.load()
+    probs = (abi.pdd_linear_problem * 2)(_problem(abi), _problem(abi, kind=abi.PDD_DOM_BOX))
+    probs[1].domain.lo[0] = probs[1].domain.lo[1] = -1.0
+    probs[1].domain.hi[0] = probs[1].domain.hi[1] = 1.0
+    o = _opts(abi)
+    n = 2
+    node_problem = (C.c_int32 * n)(0, 1)
+    paths = (C.c_int64 * n)(10, 10)
+
+    def call(problems=probs, n_problems=2, fn=lib.pdd_mc_interface_batch, dt=1e-3, opts=o, nodes=n,
+             node_map=node_problem):
+        return fn(problems, n_problems, node_map, None, nodes, paths, dt, 0, C.byref(opts), None, None)
+
+    assert call() == abi.PDD_ERR_INVALID_ARG                      # valid batch: only nodes_dev (NULL) fails
+    assert "nodes_dev" in lib.pdd_last_error().decode()
+    assert call(problems=None) == abi.PDD_ERR_INVALID_ARG
+    assert call(n_problems=0) == abi.PDD_ERR_INVALID_ARG
+    big = (abi.pdd_linear_problem * 65)(*([_problem(abi)] * 65))
+    assert call(problems=big, n_problems=65) == abi.PDD_ERR_INVALID_ARG
+    assert call(dt=0.0) == abi.PDD_ERR_INVALID_ARG
+    probs[1].sigma = -1.0
+    assert call() == abi.PDD_ERR_INVALID_ARG
+    assert lib.pdd_last_error().decode().startswith("problem 1")
+    probs[1].sigma = 1.0
+    coef = (C.c_double * 1)(1.0)
+    fac = (abi.pdd_factor * 1)()
+    fac[0].fn, fac[0].dim, fac[0].power, fac[0].a = 1, 0, 1, 1.0
+    probs[0].c.n_terms, probs[0].c.n_factors = 1, 1
+    probs[0].c.factors = C.cast(fac, C.POINTER(abi.pdd_factor))
+    probs[0].c.coef = C.cast(coef, C.c_void_p).value
+    assert call() == abi.PDD_ERR_UNSUPPORTED                     # generic terms are single-problem only
+    probs[0].c.n_terms, probs[0].c.n_factors = 0, 0
+    probs[0].c.factors, probs[0].c.coef = None, None
+    plain = _opts(abi, precision=abi.PDD_FP64_PLAIN, layout=abi.PDD_RNG_PAIR52)
+    assert call(opts=plain) == abi.PDD_ERR_UNSUPPORTED
+    bad_map = (C.c_int32 * n)(0, 2)
+    assert call(node_map=bad_map) == abi.PDD_ERR_INVALID_ARG
+    assert "node_problem" in lib.pdd_last_error().decode()
+    assert call(node_map=None) == abi.PDD_ERR_INVALID_ARG
+    paths[1] = -1
+    assert call() == abi.PDD_ERR_INVALID_ARG
+    paths[1] = 10
+    assert call(nodes=0) == abi.PDD_OK                            # nothing to do
+    probs[0].c.poly_degree = 0                                    # c = 1: not a Laplace problem
+    probs[0].c.poly = C.cast(coef, C.c_void_p).value
+    assert call(fn=lib.pdd_wos_interface_batch) == abi.PDD_ERR_UNSUPPORTED
+
+
+def test_device_reductions_check_sizes_and_pointers_on_the_host(abi):
+    """pdd_jacobian_apply, pdd_misfit_gradient, pdd_merge_estimates and
+    pdd_node_moments reject bad sizes and NULL buffers before any GPU work,
+    and return at once when there is nothing to do."""
+    lib = abi.load()
+    INV, OK = abi.PDD_ERR_INVALID_ARG, abi.PDD_OK
+    assert lib.pdd_jacobian_apply(None, -1, 4, 4, None, None, None) == INV
+    assert lib.pdd_jacobian_apply(None, 3, 2, 4, None, None, None) == INV       # leading dimension < n_params
+    assert lib.pdd_jacobian_apply(None, 3, 4, 0, None, None, None) == OK        # no parameters
+    assert lib.pdd_jacobian_apply(None, 3, 4, 4, None, None, None) == INV       # grad_dev NULL
+    assert lib.pdd_misfit_gradient(None, None, 3, None, 4, 4, None, None, None) == INV   # loss_dev NULL
+    assert lib.pdd_misfit_gradient(None, None, -3, None, 4, 4, None, None, None) == INV
+    assert lib.pdd_misfit_gradient(None, None, 3, None, 2, 4, None, None, None) == INV
+    assert lib.pdd_merge_estimates(None, None, 0, None, None, 0, 0, None, -1, None) == INV
+    assert lib.pdd_merge_estimates(None, None, 0, None, None, 0, 0, None, 0, None) == OK
+    one = (C.c_double * 1)()
+    assert lib.pdd_merge_estimates(None, one, 4, None, None, 4, 4, None, 1, None) == INV  # one Jacobian only
+    assert lib.pdd_merge_estimates(None, one, 2, None, one, 4, 4, None, 1, None) == INV   # ld < n_params
+    assert lib.pdd_merge_estimates(None, None, 0, None, None, 0, 0, None, 1, None) == INV  # acc_dev NULL
+    assert lib.pdd_node_moments(None, -1, None, None, None) == INV
+    assert lib.pdd_node_moments(None, 0, None, None, None) == OK
+    assert lib.pdd_node_moments(None, 5, None, None, None) == INV
+
+
 def _items_expected(paths, fp32=True, cus=256):
     """The library's default item decomposition, restated: item size 16384
     halved (down to 1024) until the call has about four items per resident
