@@ -60,9 +60,23 @@ std::string cache_dir() {
 
 // One cache entry is one file, written to a temporary name and renamed into
 // place, so a reader sees either a whole entry or none:
-//   "PDDJIT2\n", three little-endian uint64 lengths (key, symbol, code
-//   object), then the three byte strings.
-constexpr char kEntryMagic[8] = {'P', 'D', 'D', 'J', 'I', 'T', '2', '\n'};
+//   "PDDJIT3\n", four little-endian uint64 (the lengths of the key, the
+//   symbol and the code object, then a 64-bit FNV-1a checksum of those three
+//   byte strings in that order), then the three byte strings.
+// An entry whose checksum does not match (damaged in place) is treated as
+// missing: the kernel is compiled again and the entry replaced.  The checksum
+// guards against damage, not against someone who can write the cache
+// directory.
+constexpr char kEntryMagic[8] = {'P', 'D', 'D', 'J', 'I', 'T', '3', '\n'};
+
+uint64_t entry_checksum(const char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= (unsigned char)p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
 
 bool read_entry(const std::string& p, const std::string& key, std::string* sym, std::string* code) {
   std::ifstream f(p, std::ios::binary);
@@ -70,12 +84,13 @@ bool read_entry(const std::string& p, const std::string& key, std::string* sym, 
   std::stringstream ss;
   ss << f.rdbuf();
   const std::string d = ss.str();
-  const size_t head = sizeof kEntryMagic + 3 * sizeof(uint64_t);
+  const size_t head = sizeof kEntryMagic + 4 * sizeof(uint64_t);
   if (d.size() < head || d.compare(0, sizeof kEntryMagic, kEntryMagic, sizeof kEntryMagic) != 0) return false;
-  uint64_t n[3];
+  uint64_t n[4];
   std::memcpy(n, d.data() + sizeof kEntryMagic, sizeof n);
   if (n[0] > d.size() || n[1] > d.size() || n[2] > d.size() || head + n[0] + n[1] + n[2] != d.size()) return false;
   if (n[1] == 0 || n[2] == 0 || d.compare(head, n[0], key) != 0) return false;
+  if (entry_checksum(d.data() + head, n[0] + n[1] + n[2]) != n[3]) return false;
   sym->assign(d, head + n[0], n[1]);
   code->assign(d, head + n[0] + n[1], n[2]);
   return true;
@@ -86,10 +101,11 @@ void write_entry(const std::string& p, const std::string& key, const std::string
   {
     std::ofstream f(tmp, std::ios::binary);
     if (!f) return;
-    const uint64_t n[3] = {key.size(), sym.size(), code.size()};
+    const std::string body = key + sym + code;
+    const uint64_t n[4] = {key.size(), sym.size(), code.size(), entry_checksum(body.data(), body.size())};
     f.write(kEntryMagic, sizeof kEntryMagic);
     f.write(reinterpret_cast<const char*>(n), sizeof n);
-    f << key << sym << code;
+    f << body;
     if (!f) {
       f.close();
       std::remove(tmp.c_str());

@@ -1,6 +1,7 @@
 """The on-disk cache of problem-specialised kernels: an entry written by one
 process is reused by the next, and a damaged or foreign entry under the same
-name is recompiled and replaced, with bitwise the same results every time.
+name (truncated, a byte of the code object changed in place, another key) is
+recompiled and replaced, with bitwise the same results every time.
 Each step runs in a child process (the in-process cache would otherwise
 answer first)."""
 import glob
@@ -35,6 +36,23 @@ print(json.dumps({"mean": r["mean"].cpu().numpy().tolist(), "steps": r["steps"].
 """
 
 
+def _valid_entry(path):
+    """The entry's layout and checksum, restated: magic, little-endian uint64
+    lengths of key, symbol and code object, their 64-bit FNV-1a checksum."""
+    import struct
+    with open(path, "rb") as f:
+        d = f.read()
+    if d[:8] != b"PDDJIT3\n" or len(d) < 40:
+        return False
+    nk, ns, nc, cs = struct.unpack("<4Q", d[8:40])
+    if 40 + nk + ns + nc != len(d):
+        return False
+    h = 1469598103934665603
+    for b in d[40:]:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h == cs
+
+
 def _run(cache_dir):
     env = dict(os.environ, PDD_JIT_CACHE=str(cache_dir))
     p = subprocess.run([sys.executable, "-c", CHILD, ROOT], env=env, capture_output=True, text=True, timeout=240)
@@ -56,8 +74,7 @@ def test_disk_cache_reuse_and_repair(gpu, tmp_path):
     entry = entries[0]
     size = os.path.getsize(entry)
     assert size > 1000
-    with open(entry, "rb") as f:
-        assert f.read(8) == b"PDDJIT2\n"
+    assert _valid_entry(entry)
 
     print("jit cache: second process loads the entry", flush=True)
     second = _run(tmp_path)
@@ -71,14 +88,29 @@ def test_disk_cache_reuse_and_repair(gpu, tmp_path):
     assert third["mean"] == first["mean"] and third["steps"] == first["steps"]
     assert os.path.getsize(entry) == size          # rewritten whole
 
-    print("jit cache: entry of another key under the same name", flush=True)
+    head = 8 + 32                                  # magic, three lengths and the checksum
     with open(entry, "rb") as f:
-        data = bytearray(f.read())
-    data[8 + 24 + 5] ^= 0x01                       # one byte of the stored key
+        good = f.read()
+
+    print("jit cache: a byte of the code object changed in place", flush=True)
+    data = bytearray(good)
+    data[-100] ^= 0x40                             # inside the code object; sizes unchanged
     with open(entry, "wb") as f:
         f.write(bytes(data))
     fourth = _run(tmp_path)
     assert fourth["mean"] == first["mean"] and fourth["steps"] == first["steps"]
     with open(entry, "rb") as f:
-        assert f.read()[8 + 24 + 5] == data[8 + 24 + 5] ^ 0x01   # the true key again
+        again = f.read()
+    assert again != bytes(data) and len(again) == len(good) and _valid_entry(entry)   # refused, rebuilt
+
+    print("jit cache: entry of another key under the same name", flush=True)
+    data = bytearray(good)
+    data[head + 5] ^= 0x01                         # one byte of the stored key
+    with open(entry, "wb") as f:
+        f.write(bytes(data))
+    fifth = _run(tmp_path)
+    assert fifth["mean"] == first["mean"] and fifth["steps"] == first["steps"]
+    with open(entry, "rb") as f:
+        assert f.read()[head + 5] == good[head + 5]   # the true key again
+    assert _valid_entry(entry)
     assert not glob.glob(str(tmp_path / "*.tmp*"))
