@@ -65,20 +65,29 @@ OPS_PER_PS_ADJ_SURVEY = 230.0
 
 # HBM bytes per launch of the dominant kernel (C5 value+Jacobian walk),
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the 256 MiB copy
-# calibration (x 2.000 / x 1.000).  Valid only for the kernel sources they
-# were counted on: any change to them makes the bench report null.
+# calibration (x 2.000 / x 1.000), counted at the schedule below (the item
+# count, and with it the per-item writes, depends on it).  Valid only for the
+# kernel sources and the schedule they were counted on: otherwise the bench
+# reports null.
 TRAFFIC_SOURCES = ['paper_1705_03666_amd/csrc/walk_kernels.hpp', 'paper_1705_03666_amd/csrc/pdd_device.hpp', 'paper_1705_03666_amd/csrc/pdd_internal.hpp', 'paper_1705_03666_amd/csrc/walk_adj_f32.hip']
-TRAFFIC_SHA256 = "282f8fa0c6b0a952ac712099d7ebaf3582d0b0426329efbdf012fa571ef19d2b"
-TRAFFIC_BYTES = 59.41e6 + 131.81e6
+TRAFFIC_SHA256 = "0da4b453361811ca76c80c56fb7cd615eb25269d18cdd1336590644071a9a7d2"
+TRAFFIC_SCHEDULE = {"chunk_paths": 32768, "blocks_per_cu": 8, "refill_groups": 3}
+TRAFFIC_BYTES = 61.10e6 + 238.48e6
 
 
-def traffic_bytes():
+def traffic_bytes(schedule=None):
+    """TRAFFIC_BYTES when the kernel sources hash to TRAFFIC_SHA256 and the
+    adjoint schedule (if given) is TRAFFIC_SCHEDULE, else None."""
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC_BYTES if h.hexdigest() == TRAFFIC_SHA256 else None
+    if h.hexdigest() != TRAFFIC_SHA256:
+        return None
+    if schedule is not None and any(int(schedule.get(k, -1)) != v for k, v in TRAFFIC_SCHEDULE.items()):
+        return None
+    return TRAFFIC_BYTES
 
 
 class ClockSampler:
@@ -375,7 +384,7 @@ def run(args):
         "mean_steps_per_path": float(mean_steps.mean().item()),
         "gpu_clock_during_steps": sclk,
         "roofline": {"bound": "alu", "kernel": f"k_walk ({dominant}, FP32, DIM 3)", "achieved": achieved,
-                     "peak": peak, "unit": "Top/s", "frac": achieved / peak, "traffic": traffic_bytes(),
+                     "peak": peak, "unit": "Top/s", "frac": achieved / peak, "traffic": traffic_bytes(sched_a),
                      "ops_per_path_step": OPS_PER_PS_ADJ if dominant == "adjoint" else OPS_PER_PS_FWD,
                      "ops_per_path_step_survey_unit": OPS_PER_PS_ADJ_SURVEY,
                      "achieved_survey_unit": ps * OPS_PER_PS_ADJ_SURVEY / dur / 1e12,

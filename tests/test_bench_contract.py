@@ -25,14 +25,18 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 def test_traffic_figure_is_reported_only_for_the_sources_it_was_counted_on(tmp_path, monkeypatch):
     """roofline.traffic is the HBM byte count taken on the dominant kernel's
-    sources with the recorded hash; once they differ, bench.py reports null
-    rather than a stale figure.  When reported, it is at least the
-    algorithmic bytes of a launch (57344 items x (160 x 8 + 48) B)."""
+    sources with the recorded hash, at the recorded schedule; once either
+    differs, bench.py reports null rather than a stale figure.  When reported,
+    it is at least the algorithmic bytes of a launch at that schedule (11
+    items per node of 1e5 paths, 4096 nodes, each (160 x 8 + 48) B)."""
     b = _bench()
-    t = b.traffic_bytes()
-    assert t is None or t >= 57344 * (160 * 8 + 48)
+    sched = dict(b.TRAFFIC_SCHEDULE)
+    t = b.traffic_bytes(sched)
+    assert t is None or t >= 4096 * 11 * (160 * 8 + 48)
+    other = dict(sched, chunk_paths=16384)
+    assert b.traffic_bytes(other) is None
     monkeypatch.setattr(b, "TRAFFIC_SHA256", "0" * 64)
-    assert b.traffic_bytes() is None
+    assert b.traffic_bytes(sched) is None
 
 
 def test_op_table_and_peak():
