@@ -45,6 +45,12 @@ def _n_cu() -> int:
     return torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
 
 
+# a candidate replaces the current schedule only when it is at least this
+# much faster, so that timing noise between near-equal schedules does not
+# move the table from run to run
+MIN_GAIN = 1.01
+
+
 def _search(run: Callable[[dict], float], start: dict, space: Dict[str, list], log=None, tag="") -> tuple:
     """Coordinate descent from `start` over `space`; run(cfg) returns a rate
     (work units per second, higher is better)."""
@@ -60,7 +66,7 @@ def _search(run: Callable[[dict], float], start: dict, space: Dict[str, list], l
             r = run(cand)
             if log:
                 log(f"autotune {tag} {cand}: {r:.4g}/s")
-            if r > r_cur:
+            if r > r_cur * MIN_GAIN:
                 cur, r_cur = cand, r
     return cur, r_cur, r0
 

@@ -116,6 +116,9 @@ bool lookup(int kernel, int dim, int precision, Entry* out) {
 Entry defaults(int kernel, bool fp32) {
   if (kernel == PDD_KERNEL_BRANCH) return Entry{16384, fp32 ? 4 : 2, 1};
   if (kernel == PDD_KERNEL_BRANCH_BVP) return Entry{4096, fp32 ? 4 : 2, 1};
+  // the adjoint / value+Jacobian walk: the autotuner's choice on C5 (items of
+  // 32768 paths, 0.3-1% ahead of 16384)
+  if (kernel == PDD_KERNEL_WALK_ADJOINT && fp32) return Entry{32768, 8, 3};
   return Entry{16384, fp32 ? 8 : 4, 3};
 }
 
