@@ -450,6 +450,15 @@ def other_workloads(pdd, dev, tune=True):
                        "err_vs_exact_max_se": zmax, "err_vs_exact_rms_se": zrms}
     log(f"bench: C3 batch (Euler, one launch): {nn} nodes in {el * 1e3:.1f} ms, {ps / el:.3e} path-steps/s, "
         f"error vs exact max {zmax:.1f} SE, rms {zrms:.1f} SE")
+    # the same batch with the boundary-corrected exit test: the O(sqrt dt)
+    # exit bias that dominates the plain test's error at this budget
+    rbc, elc = timed(lambda: pdd.mc_interface_batch(cb.problems, cb.node_problem, nb, cb.paths, cb.dt, cb.seed,
+                                                    precision="fp32", boundary_correction=True))
+    zmaxc, zrmsc = err_se(rbc)
+    res["c3_batch"]["corrected"] = {"seconds": elc, "path_steps_per_s": float(rbc["steps"].sum().item()) / elc,
+                                    "err_vs_exact_max_se": zmaxc, "err_vs_exact_rms_se": zrmsc}
+    log(f"bench: C3 batch, boundary-corrected: {elc * 1e3:.1f} ms, error vs exact max {zmaxc:.1f} SE, "
+        f"rms {zrmsc:.1f} SE")
 
     # the same batch by walk on spheres (b = c = f = 0), eps = 1e-4
     run_c3_wos = lambda: pdd.wos_interface_batch(cb.problems, cb.node_problem, nb, cb.paths, 1e-4, cb.seed,
@@ -482,6 +491,13 @@ def other_workloads(pdd, dev, tune=True):
                  "err_vs_exact_max_se": float(z2.max()), "err_vs_exact_rms_se": float(np.sqrt(np.mean(z2 ** 2)))}
     log(f"bench: C2: {ps2:.3e} path-steps in {el2 * 1e3:.1f} ms, {ps2 / el2:.3e} path-steps/s (first call "
         f"{first2:.2f} s); error vs exact max {z2.max():.1f} SE, rms {np.sqrt(np.mean(z2 ** 2)):.1f} SE")
+    r2c, el2c = timed(lambda: pdd.mc_interface(c2.problem, n2, c2.paths, c2.dt, c2.seed, precision="fp32",
+                                               boundary_correction=True))
+    z2c = np.abs(r2c["mean"].cpu().numpy() - CF.c2_exact(c2.nodes)) / r2c["se"].cpu().numpy()
+    res["c2"]["corrected"] = {"seconds": el2c, "path_steps_per_s": float(r2c["steps"].sum().item()) / el2c,
+                              "err_vs_exact_max_se": float(z2c.max()),
+                              "err_vs_exact_rms_se": float(np.sqrt(np.mean(z2c ** 2)))}
+    log(f"bench: C2, boundary-corrected: error vs exact max {z2c.max():.1f} SE, rms {np.sqrt(np.mean(z2c ** 2)):.1f} SE")
     # boundary-corrected exit test vs the plain one: C1 (harmonic data, exact
     # u = g) at dt = 4e-3 with 1e6 FP32 paths per node; error in SE units
     c1 = CF.c1(scale=100.0, dt=4e-3)

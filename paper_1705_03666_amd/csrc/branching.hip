@@ -26,8 +26,13 @@ namespace pdd {
 // entries go to the per-lane spill area in global memory.  Six FP32 entries
 // keep a 256-thread block at 37 KB of LDS, so four blocks fit a CU (eight
 // entries allowed three: measured 13% slower on C6, 6-12% on C4 / C7).
+// k_branch in 3-D keeps three (18 KB per block, six blocks per CU: C4 4.42
+// -> 4.11 ms at its best schedule); its 1-D trees (C7: up to four children
+// per branching) are deeper, and there three entries were slower.
 template <typename R>
 constexpr int lds_depth() { return sizeof(R) == 4 ? 6 : 4; }
+template <typename R, int DIM>
+constexpr int lds_depth_free() { return (sizeof(R) == 4 && DIM == 3) ? 3 : lds_depth<R>(); }
 
 // FP32 kernels are built for four waves per SIMD (at most 128 VGPRs).
 template <typename R>
@@ -153,7 +158,7 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
   const int wid = (int)(threadIdx.x / kWave);
   const int64_t glane = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t nlanes = (int64_t)gridDim.x * kBlock;
-  constexpr int kLdsDepth = lds_depth<R>();
+  constexpr int kLdsDepth = lds_depth_free<R, DIM>();
   __shared__ StackEntry<R> lds[kBlock / kWave][kLdsDepth][kWave];
 
   const uint32_t k0 = P.key0, k1 = P.key1;
@@ -972,7 +977,11 @@ static hipError_t launch_branch_t(const BranchLaunch& L, hipStream_t st) {
 }
 
 size_t branch_stack_entry_bytes(bool fp32) { return fp32 ? sizeof(StackEntry<float>) : sizeof(StackEntry<double>); }
-int branch_lds_depth(bool fp32) { return fp32 ? lds_depth<float>() : lds_depth<double>(); }
+int branch_lds_depth(bool fp32, int dim, bool boundary) {
+  if (boundary) return fp32 ? lds_depth<float>() : lds_depth<double>();
+  if (fp32) return dim == 3 ? lds_depth_free<float, 3>() : lds_depth_free<float, 1>();
+  return lds_depth_free<double, 1>();
+}
 
 hipError_t launch_branch(const BranchLaunch& L, hipStream_t st) {
   if (L.fp32) return launch_branch_t<float, RNG_QUAD24>(L, st);

@@ -1481,7 +1481,7 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   const int max_blocks = tune.blocks_per_cu * device_cus();
   const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
   const int grid = std::max(1, std::min(max_blocks, need));
-  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32));
+  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32, B.dim, false));
 
   Arena A;
   const size_t o_call = add_call_block(A, T.jobs.size());
@@ -1634,7 +1634,7 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   const int max_blocks = tune.blocks_per_cu * device_cus();
   const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
   const int grid = std::max(1, std::min(max_blocks, need));
-  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32));
+  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32, B.dim, true));
 
   Arena A;
   const size_t o_call = add_call_block(A, T.jobs.size());

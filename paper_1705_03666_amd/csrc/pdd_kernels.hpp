@@ -117,7 +117,8 @@ hipError_t launch_plain_adj(const PlainLaunch& L, hipStream_t st);
 hipError_t launch_branch(const BranchLaunch& L, hipStream_t st);
 hipError_t launch_branch_bvp(const BranchBvpLaunch& L, hipStream_t st);
 size_t branch_stack_entry_bytes(bool fp32);
-int branch_lds_depth(bool fp32);
+// LDS stack entries per lane of k_branch (boundary = false) or k_branch_bvp
+int branch_lds_depth(bool fp32, int dim, bool boundary);
 hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, int64_t n_nodes, const CallPtrs* cp,
                                  int64_t out_off, unsigned long long* counters, hipStream_t st);
 hipError_t launch_finalize_grad(const double* igrad, int stride, int n_cols, int n_items, const int32_t* slot_node,

@@ -112,8 +112,11 @@ bool lookup(int kernel, int dim, int precision, Entry* out) {
 // CU (the FP32 branching kernels are built for four waves per SIMD), items of
 // 16384 trees for k_branch (2 blocks and 2048-tree items took 2.0x on C4) and
 // of 4096 trees for k_branch_bvp, whose trees are long enough that the last
-// items of a launch decide its end (16384-tree items took 1.15x on C6).
-Entry defaults(int kernel, bool fp32) {
+// items of a launch decide its end (16384-tree items took 1.15x on C6).  The
+// 3-D FP32 k_branch keeps a shallower LDS stack, so six blocks fit a CU; with
+// six, items of 8192 trees (C4: 4.11 ms against 4.83 ms with 16384).
+Entry defaults(int kernel, bool fp32, int dim) {
+  if (kernel == PDD_KERNEL_BRANCH && fp32 && dim == 3) return Entry{8192, 6, 1};
   if (kernel == PDD_KERNEL_BRANCH) return Entry{16384, fp32 ? 4 : 2, 1};
   if (kernel == PDD_KERNEL_BRANCH_BVP) return Entry{4096, fp32 ? 4 : 2, 1};
   // the adjoint / value+Jacobian walk: the autotuner's choice on C5 (items of
@@ -126,7 +129,7 @@ Entry defaults(int kernel, bool fp32) {
 
 Tuning choose_schedule(int kernel, int dim, int precision, const pdd_options& o, int n_cus, int64_t total_work) {
   const bool fp32 = precision == PDD_FP32_STEP;
-  Entry e = defaults(kernel, fp32);
+  Entry e = defaults(kernel, fp32, dim);
   Entry tuned;
   if (lookup(kernel, dim, precision, &tuned)) e = tuned;
   Tuning t;
@@ -171,7 +174,7 @@ int set_schedule(int kernel, int dim, int precision, const pdd_launch_schedule* 
 int get_schedule(int kernel, int dim, int precision, pdd_launch_schedule* out, int32_t* tuned) {
   Entry e;
   const bool have = lookup(kernel, dim, precision, &e);
-  if (!have) e = defaults(kernel, precision == PDD_FP32_STEP);
+  if (!have) e = defaults(kernel, precision == PDD_FP32_STEP, dim);
   if (out) {
     out->chunk_paths = e.chunk;
     out->blocks_per_cu = e.blocks;
