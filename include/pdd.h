@@ -41,16 +41,20 @@
  *    returns, except that device arrays must stay valid until the enqueued
  *    work finishes.
  *  - Scratch memory.  A call's scratch (tables, work queue, per-item
- *    partials, branching stacks) is taken stream-ordered from a memory pool
- *    of the library's own, which keeps up to 2 GiB mapped between calls.  The
+ *    partials, branching stacks) lives in the call arena of its (device,
+ *    stream): one buffer from a memory pool of the library's own, kept from
+ *    one call to the next and grown (stream-ordered) when a call needs more,
+ *    so a call frees nothing and does not wait for earlier work; calls on one
+ *    stream use it in stream order, and calls from several host threads on
+ *    one stream enqueue one at a time.  The
  *    graph schedule (PDD_SCHED_AUTO / PDD_SCHED_PERSISTENT_GRAPH) instead
  *    keeps a captured launch plan with its own scratch per (problem
  *    structure, budgets, step, seed, options, outputs requested, stream); at
  *    most 16 plans are cached, the least recently used one is dropped once
  *    its last launch has finished.  A plan does not depend on the caller's
  *    buffers (nodes, coefficient arrays, outputs, weights): they are handed
- *    to every replay.  pdd_release_workspace() frees the plans and returns
- *    the pool's memory.
+ *    to every replay.  pdd_release_workspace() frees the plans and the
+ *    call arenas and returns the pool's memory.
  *  - Per-path values and step counts are a pure function of (problem, node,
  *    path index, dt, seed, precision, rng layout): independent of the
  *    schedule, the work-item size and the device.  Node statistics merge
@@ -487,8 +491,9 @@ pdd_status pdd_get_schedule(int32_t kernel, int32_t dim, int32_t precision, pdd_
 pdd_status pdd_save_schedules(const char* path);
 pdd_status pdd_load_schedules(const char* path);
 
-/* Frees cached launch plans and their device memory, and returns the memory
- * the library's pools keep (synchronizes the device). */
+/* Frees cached launch plans, the per-stream call arenas and their device
+ * memory, and returns the memory the library's pools keep (synchronizes the
+ * device; no other call may run meanwhile). */
 pdd_status pdd_release_workspace(void);
 
 /* Number of cached graph launch plans (at most 16). */

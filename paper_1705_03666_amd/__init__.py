@@ -113,6 +113,29 @@ def _dev_f64(x) -> torch.Tensor:
     return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device="cuda")
 
 
+# Device copies of the constant arrays of problem data (coefficients) passed
+# as host arrays, keyed by their content: a repeated call with the same data
+# reuses the copy instead of a blocking host-to-device copy, so calls queue on
+# the stream without waiting for earlier GPU work.  The library only reads
+# these buffers.
+_CONST_CACHE: "Dict[bytes, torch.Tensor]" = {}
+_CONST_CACHE_MAX = 512
+
+
+def _dev_const_f64(x) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return _dev_f64(x)
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    key = a.tobytes() + bytes(str(a.shape), "ascii")
+    t = _CONST_CACHE.get(key)
+    if t is None:
+        if len(_CONST_CACHE) >= _CONST_CACHE_MAX:
+            _CONST_CACHE.pop(next(iter(_CONST_CACHE)))
+        t = torch.as_tensor(a, device="cuda")
+        _CONST_CACHE[key] = t
+    return t
+
+
 class _Keep(list):
     pass
 
@@ -133,14 +156,14 @@ def _fun(F, keep: _Keep, coef=None, poly=None) -> A.pdd_fun:
         keep.append(facs)
         f.factors = C.cast(facs, C.POINTER(A.pdd_factor))
     if T > 0:
-        ct = _dev_f64(F.coef if coef is None else coef)
+        ct = _dev_const_f64(F.coef if coef is None else coef)
         if ct.numel() != T:
             raise ValueError("coefficient count does not match the term table")
         keep.append(ct)
         f.coef = ct.data_ptr()
     f.poly_degree = int(F.poly_degree)
     if F.poly_degree >= 0:
-        pt = _dev_f64(F.poly if poly is None else poly)
+        pt = _dev_const_f64(F.poly if poly is None else poly)
         keep.append(pt)
         f.poly = pt.data_ptr()
     return f

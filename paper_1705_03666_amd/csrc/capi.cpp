@@ -82,6 +82,88 @@ hipError_t arena_alloc(void** p, size_t bytes, hipStream_t st) {
   return hipMallocFromPoolAsync(p, bytes, pool, st);
 }
 
+// The call arena of a (device, stream): kept from one call to the next and
+// grown when a call needs more, so a call frees nothing (a stream-ordered
+// free here waited for the work queued before it: about 3 ms per C4 call,
+// which made every call block the host).  Calls on one stream run in order,
+// so a call's uploads into the arena cannot overtake the previous call's
+// kernels; the lease holds the arena's lock while a call enqueues, so two host
+// threads cannot interleave their uploads and launches on one stream.  An
+// event recorded after each use orders the next one even if the stream handle
+// is reused by a new stream.  pdd_release_workspace() returns the memory.
+struct StreamArena {
+  int dev = 0;
+  hipStream_t st = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t last = nullptr;
+  std::mutex mu;
+};
+std::mutex g_sa_mu;
+std::vector<std::unique_ptr<StreamArena>> g_stream_arenas;
+
+struct ArenaLease {
+  StreamArena* a = nullptr;
+  std::unique_lock<std::mutex> lk;
+  hipStream_t st = nullptr;
+  // marks the end of this call's use (after its last launch)
+  hipError_t done() { return a != nullptr ? hipEventRecord(a->last, st) : hipSuccess; }
+};
+
+hipError_t lease_arena(size_t bytes, hipStream_t st, ArenaLease* L, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  StreamArena* a = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_sa_mu);
+    for (auto& x : g_stream_arenas)
+      if (x->dev == dev && x->st == st) {
+        a = x.get();
+        break;
+      }
+    if (a == nullptr) {
+      g_stream_arenas.emplace_back(new StreamArena());
+      a = g_stream_arenas.back().get();
+      a->dev = dev;
+      a->st = st;
+    }
+  }
+  L->lk = std::unique_lock<std::mutex>(a->mu);
+  L->a = a;
+  L->st = st;
+  if (a->last == nullptr) {
+    if ((e = hipEventCreateWithFlags(&a->last, hipEventDisableTiming)) != hipSuccess) return e;
+  } else if ((e = hipStreamWaitEvent(st, a->last, 0)) != hipSuccess) {
+    return e;
+  }
+  if (a->bytes < bytes) {
+    if (a->p != nullptr && (e = hipFreeAsync(a->p, st)) != hipSuccess) return e;
+    a->p = nullptr;
+    a->bytes = 0;
+    const size_t nb = (bytes + ((size_t)2 << 20) - 1) & ~(((size_t)2 << 20) - 1);   // 2 MiB granules
+    if ((e = arena_alloc(&a->p, nb, st)) != hipSuccess) return e;
+    a->bytes = nb;
+  }
+  *out = a->p;
+  return hipSuccess;
+}
+
+// Returns every call arena (after a device synchronisation; no call may run).
+hipError_t release_stream_arenas() {
+  std::lock_guard<std::mutex> g(g_sa_mu);
+  for (auto& x : g_stream_arenas) {
+    std::lock_guard<std::mutex> lk(x->mu);
+    if (x->p != nullptr) {
+      hipError_t e = hipFreeAsync(x->p, nullptr);
+      if (e != hipSuccess) return e;
+    }
+    if (x->last != nullptr) (void)hipEventDestroy(x->last);
+  }
+  g_stream_arenas.clear();
+  return hipDeviceSynchronize();
+}
+
 // Unmaps every page the library pools hold (call after a device synchronisation).
 hipError_t trim_pools() {
   std::lock_guard<std::mutex> lock(g_pool_mu);
@@ -926,6 +1008,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   }
 
   // ---- allocate
+  ArenaLease lease;
   if (a.fixed != nullptr) {
     if (A.total > a.fixed_bytes)
       return fail(PDD_ERR_UNSUPPORTED, "this call needs " + std::to_string(A.total) +
@@ -936,7 +1019,7 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
     PDD_HIP(hipMalloc(&pl.arena, A.total));
     pl.owned = true;
   } else {
-    PDD_HIP(arena_alloc(&pl.arena, A.total, st));
+    PDD_HIP(lease_arena(A.total, st, &lease, &pl.arena));
   }
   char* base = (char*)pl.arena;
   pl.d_call = (CallPtrs*)(base + o_call);
@@ -1056,11 +1139,8 @@ pdd_status run_linear(const LinearPlanArgs& a, hipStream_t st) {
   // ---- run
   if (!graph) {
     hipError_t e = pl.enqueue(st);
-    if (e != hipSuccess) {
-      if (a.fixed == nullptr) (void)hipFreeAsync(pl.arena, st);
-      return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
-    }
-    if (a.fixed == nullptr) PDD_HIP(hipFreeAsync(pl.arena, st));
+    (void)lease.done();
+    if (e != hipSuccess) return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return PDD_OK;
   }
   return capture_plan(std::move(plan), key, st);
@@ -1206,11 +1286,12 @@ pdd_status run_linear_batch(const BatchArgs& a, hipStream_t st) {
   const size_t o_doff = A.add(sizeof(int64_t) * ((size_t)a.n_nodes + 1));
   const size_t o_probs = A.add(sizeof(LinearParams) * (size_t)a.n_probs);
   const size_t o_nprob = A.add(sizeof(int32_t) * (size_t)a.n_nodes);
+  ArenaLease lease;
   if (graph) {
     PDD_HIP(hipMalloc(&pl.arena, A.total));
     pl.owned = true;
   } else {
-    PDD_HIP(arena_alloc(&pl.arena, A.total, st));
+    PDD_HIP(lease_arena(A.total, st, &lease, &pl.arena));
   }
   char* base = (char*)pl.arena;
   pl.d_call = (CallPtrs*)(base + o_call);
@@ -1272,11 +1353,8 @@ pdd_status run_linear_batch(const BatchArgs& a, hipStream_t st) {
 
   if (!graph) {
     hipError_t e = pl.enqueue(st);
-    if (e != hipSuccess) {
-      (void)hipFreeAsync(pl.arena, st);
-      return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
-    }
-    PDD_HIP(hipFreeAsync(pl.arena, st));
+    (void)lease.done();
+    if (e != hipSuccess) return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return PDD_OK;
   }
   return capture_plan(std::move(plan), key, st);
@@ -1495,7 +1573,8 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   const size_t o_first = A.add(sizeof(int64_t) * ((size_t)n_points + 1));
   const size_t o_spill =
       A.add(branch_stack_entry_bytes(fp32) * (size_t)std::max<int64_t>(1, spill_entries) * (size_t)grid * kBlock);
-  PDD_HIP(arena_alloc(&pl.arena, A.total, st));
+  ArenaLease lease;
+  PDD_HIP(lease_arena(A.total, st, &lease, &pl.arena));
   char* base = (char*)pl.arena;
   pl.d_call = (CallPtrs*)(base + o_call);
   pl.d_jobs = (StageJob*)(base + o_call + kJobsOff);
@@ -1537,11 +1616,8 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   BL.stack = base + o_spill;
   BL.stack_entries = spill_entries;
   hipError_t e = pl.enqueue(st);
-  if (e != hipSuccess) {
-    (void)hipFreeAsync(pl.arena, st);
-    return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
-  }
-  PDD_HIP(hipFreeAsync(pl.arena, st));
+  (void)lease.done();
+  if (e != hipSuccess) return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return PDD_OK;
 }
 
@@ -1648,7 +1724,8 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   const size_t o_first = A.add(sizeof(int64_t) * ((size_t)n_points + 1));
   const size_t o_spill =
       A.add(branch_stack_entry_bytes(fp32) * (size_t)std::max<int64_t>(1, spill_entries) * (size_t)grid * kBlock);
-  PDD_HIP(arena_alloc(&pl.arena, A.total, st));
+  ArenaLease lease;
+  PDD_HIP(lease_arena(A.total, st, &lease, &pl.arena));
   char* base = (char*)pl.arena;
   pl.d_call = (CallPtrs*)(base + o_call);
   pl.d_jobs = (StageJob*)(base + o_call + kJobsOff);
@@ -1692,11 +1769,8 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   L.stack = base + o_spill;
   L.stack_entries = spill_entries;
   hipError_t e = pl.enqueue(st);
-  if (e != hipSuccess) {
-    (void)hipFreeAsync(pl.arena, st);
-    return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
-  }
-  PDD_HIP(hipFreeAsync(pl.arena, st));
+  (void)lease.done();
+  if (e != hipSuccess) return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return PDD_OK;
 }
 
@@ -1923,6 +1997,7 @@ pdd_status pdd_release_workspace(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_plans.clear();
   }
+  PDD_HIP(release_stream_arenas());
   PDD_HIP(trim_pools());
   return PDD_OK;
 }
