@@ -454,11 +454,20 @@ def other_workloads(pdd, dev, tune=True):
     # exit bias that dominates the plain test's error at this budget
     rbc, elc = timed(lambda: pdd.mc_interface_batch(cb.problems, cb.node_problem, nb, cb.paths, cb.dt, cb.seed,
                                                     precision="fp32", boundary_correction=True))
-    zmaxc, zrmsc = err_se(rbc)
+    # nodes closer to the boundary than the shift c0 sigma sqrt(dt) exit at
+    # once with phi = g(P x): no spread (SE 0), so their error is reported in
+    # absolute terms, the others' in SE units
+    mc, sc = rbc["mean"].cpu().numpy(), rbc["se"].cpu().numpy()
+    band = sc == 0.0
+    zc = np.abs(mc[~band] - cb.exact[~band]) / sc[~band]
     res["c3_batch"]["corrected"] = {"seconds": elc, "path_steps_per_s": float(rbc["steps"].sum().item()) / elc,
-                                    "err_vs_exact_max_se": zmaxc, "err_vs_exact_rms_se": zrmsc}
-    log(f"bench: C3 batch, boundary-corrected: {elc * 1e3:.1f} ms, error vs exact max {zmaxc:.1f} SE, "
-        f"rms {zrmsc:.1f} SE")
+                                    "err_vs_exact_max_se": float(zc.max()),
+                                    "err_vs_exact_rms_se": float(np.sqrt(np.mean(zc ** 2))),
+                                    "nodes_exiting_at_start": int(band.sum()),
+                                    "their_max_abs_err": float(np.abs(mc[band] - cb.exact[band]).max()) if band.any()
+                                    else 0.0}
+    log(f"bench: C3 batch, boundary-corrected: {elc * 1e3:.1f} ms, error vs exact max {zc.max():.1f} SE, "
+        f"rms {np.sqrt(np.mean(zc ** 2)):.1f} SE ({int(band.sum())} nodes inside the shift exit at once)")
 
     # the same batch by walk on spheres (b = c = f = 0), eps = 1e-4
     run_c3_wos = lambda: pdd.wos_interface_batch(cb.problems, cb.node_problem, nb, cb.paths, 1e-4, cb.seed,
