@@ -122,6 +122,9 @@ Entry defaults(int kernel, bool fp32, int dim) {
   // the adjoint / value+Jacobian walk: the autotuner's choice on C5 (items of
   // 32768 paths, 0.3-1% ahead of 16384)
   if (kernel == PDD_KERNEL_WALK_ADJOINT && fp32) return Entry{32768, 8, 3};
+  // the heterogeneous batch: the autotuner's choice on the C3 batch (items of
+  // 4096 paths, 6 blocks per CU; 37 ms against 47 ms at 16384 / 8)
+  if (kernel == PDD_KERNEL_WALK_BATCH || kernel == PDD_KERNEL_WOS_BATCH) return Entry{4096, fp32 ? 6 : 4, 4};
   return Entry{16384, fp32 ? 8 : 4, 3};
 }
 

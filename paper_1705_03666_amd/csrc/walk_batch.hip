@@ -65,10 +65,53 @@ __device__ __forceinline__ const R PDD_CONST_AS* batch_coefs(const double* cd, c
   else return (const R PDD_CONST_AS*)const_table(cd);
 }
 
+// The exit test of a problem whose domain kind is KIND, with the bounds (box)
+// or the centre and squared radius (ball) held in vector registers in FP32,
+// so the comparisons that read them can share an issue slot; the same
+// arithmetic as inside().
+template <typename R, int DIM, int KIND>
+struct ExitTest {
+  R lo[DIM], hi[DIM], ctr[DIM], rad2;
+  __device__ __forceinline__ explicit ExitTest(const Dom<R>& D) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      lo[k] = D.lo[k];
+      hi[k] = D.hi[k];
+      ctr[k] = D.ctr[k];
+    }
+    rad2 = D.rad2;
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        if constexpr (KIND == DOM_BOX) asm volatile("" : "+v"(lo[k]), "+v"(hi[k]));
+        else asm volatile("" : "+v"(ctr[k]));
+      }
+      if constexpr (KIND != DOM_BOX) asm volatile("" : "+v"(rad2));
+    }
+  }
+  __device__ __forceinline__ bool inside(const R* x) const {
+    if constexpr (KIND == DOM_BOX) {
+      bool in = true;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) in = in && (x[k] > lo[k]) && (x[k] < hi[k]);
+      return in;
+    } else {
+      R r2 = (R)0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const R d = x[k] - ctr[k];
+        r2 += d * d;
+      }
+      return r2 < rad2;
+    }
+  }
+};
+
 // The paths [it.p0, it.p0 + it.count) of one node of a DIM-dimensional
-// problem: stepping, parking ended paths as exit records, refilling lanes,
-// flushing records 64 at a time, and the item's statistics into istat.
-template <typename R, int DIM, int LAYOUT, bool WOS>
+// problem whose domain kind is KIND: stepping, parking ended paths as exit
+// records, refilling lanes, flushing records 64 at a time, and the item's
+// statistics into istat.
+template <typename R, int DIM, int LAYOUT, bool WOS, int KIND>
 __device__ __forceinline__ void batch_item(const LinearParams PDD_CONST_AS* P, const WorkItem it,
                                            const double* __restrict__ nodes, const DevFactor* __restrict__ fac,
                                            const double* __restrict__ cd, const float* __restrict__ cf, uint32_t k0,
@@ -81,6 +124,7 @@ __device__ __forceinline__ void batch_item(const LinearParams PDD_CONST_AS* P, c
   constexpr int NM = GradedLex<DIM, kMaxPolyBCF>::N;
   const Dom<R> D = batch_dom<R>(P, false);
   const Dom<R> Dt = batch_dom<R>(P, true);
+  const ExitTest<R, DIM, KIND> exit_test(Dt);
   R dt = batch_dt<R>(P);
   R sdt = batch_sdt<R>(P);
   if constexpr (sizeof(R) == 4) asm volatile("" : "+v"(dt), "+v"(sdt));
@@ -199,7 +243,7 @@ __device__ __forceinline__ void batch_item(const LinearParams PDD_CONST_AS* P, c
             for (int k = 0; k < DIM; ++k) X[k] = X[k] + sdt * z[s * DIM + k];
           }
           ++n;
-          if (!inside<R, DIM>(Dt, X)) {
+          if (!exit_test.inside(X)) {
             alive = false;
             fin = true;
           }
@@ -283,20 +327,25 @@ k_walk_batch(const LinearParams* __restrict__ probs, const int32_t* __restrict__
     const WorkItem it = items[it_idx];
     const int k = __builtin_amdgcn_readfirstlane(node_prob[it.node]);
     const LinearParams PDD_CONST_AS* P = const_table(probs) + k;
+    const bool box = P->dom_kind == DOM_BOX;
+#define PDD_BATCH_ITEM(DIM, KIND)                                                                                \
+  batch_item<R, DIM, LAYOUT, WOS, KIND>(P, it, nodes, fac, cd, cf, k0, k1, refill_groups, area[wid], rec_i[wid][0], \
+                                        rec_i[wid][1], lane, istat, dump_phi, dump_steps, dump_off)
     switch (P->dim) {
       case 1:
-        batch_item<R, 1, LAYOUT, WOS>(P, it, nodes, fac, cd, cf, k0, k1, refill_groups, area[wid], rec_i[wid][0],
-                                      rec_i[wid][1], lane, istat, dump_phi, dump_steps, dump_off);
+        if (box) PDD_BATCH_ITEM(1, DOM_BOX);
+        else PDD_BATCH_ITEM(1, DOM_BALL);
         break;
       case 2:
-        batch_item<R, 2, LAYOUT, WOS>(P, it, nodes, fac, cd, cf, k0, k1, refill_groups, area[wid], rec_i[wid][0],
-                                      rec_i[wid][1], lane, istat, dump_phi, dump_steps, dump_off);
+        if (box) PDD_BATCH_ITEM(2, DOM_BOX);
+        else PDD_BATCH_ITEM(2, DOM_BALL);
         break;
       default:
-        batch_item<R, 3, LAYOUT, WOS>(P, it, nodes, fac, cd, cf, k0, k1, refill_groups, area[wid], rec_i[wid][0],
-                                      rec_i[wid][1], lane, istat, dump_phi, dump_steps, dump_off);
+        if (box) PDD_BATCH_ITEM(3, DOM_BOX);
+        else PDD_BATCH_ITEM(3, DOM_BALL);
         break;
     }
+#undef PDD_BATCH_ITEM
   }
 }
 
