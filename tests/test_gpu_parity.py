@@ -522,6 +522,11 @@ BVP_CASES = {
     "logistic_disk": lambda: (*CF.kpp_bvp_logistic(ball(2, 0.6), 0.3, 1.0, 0.05, (0.25, 0.5, 1.0)),
                               np.array([[0.0, 0.0], [0.3, 0.1], [0.5, -0.2]])),
     "marked_box3": _bvp_marked_box3,
+    # a narrow interval and 12 output times: most particles stop early, each
+    # with up to 11 later output times, so one batch of stops holds hundreds
+    # of (lane, time) pairs and the products are dealt out over several passes
+    "tw_narrow_12_times": lambda: (*CF.kpp_bvp_travelling_wave(-0.5, 0.7, 0.01, tuple(0.09 * k for k in range(12))),
+                                   np.array([[-0.45], [-0.2], [0.1], [0.4], [0.68]])),
 }
 
 
