@@ -233,9 +233,10 @@ typedef struct {
                                   sub-step of length h uses the domain shrunk by c0 sigma sqrt(h).
                                   Ignored by pdd_branching_eval. */
   int32_t specialize;     /* batched linear walks (PDD_FP64, PDD_FP32_STEP) whose b, c or f have generic
-                             terms: 0 = auto: compile, at run time, a kernel with the problem's factor
-                             structure (functions, coordinates, scales, shifts, powers) written in as
-                             constants, and fall back to the table-driven kernel (with a note on
+                             terms, and pdd_branching_eval / pdd_branching_bvp whose psi (or g) has
+                             generic terms: 0 = auto: compile, at run time, a kernel with the problem's
+                             factor structure (functions, coordinates, scales, shifts, powers) written
+                             in as constants, and fall back to the table-driven kernel (with a note on
                              stderr) if the runtime compiler is unavailable; 1 = required (a failed
                              compilation returns PDD_ERR_HIP); -1 = never.  Both kernels evaluate the
                              same operations in the same order.  Coefficients stay run-time data, so

@@ -76,7 +76,8 @@ def _stream_handle() -> int:
 _PREC = {"fp64_plain": A.PDD_FP64_PLAIN, "fp64": A.PDD_FP64, "fp32": A.PDD_FP32_STEP}
 _LAYOUT = {"pair52": A.PDD_RNG_PAIR52, "quad24": A.PDD_RNG_QUAD24}
 _SCHED = {"auto": A.PDD_SCHED_AUTO, "persistent": A.PDD_SCHED_PERSISTENT, "graph": A.PDD_SCHED_PERSISTENT_GRAPH}
-# problem-specialised kernels for generic terms in b, c, f (pdd_options.specialize)
+# problem-specialised kernels for generic terms in b, c, f (walks) and psi, g
+# (branching) (pdd_options.specialize)
 _SPEC = {"auto": 0, "on": 1, "off": -1}
 
 
@@ -611,9 +612,12 @@ def jacobian_blocks(problem, jac: torch.Tensor) -> Dict[str, torch.Tensor]:
 
 def branching_eval(problem, points, trees: int, seed: int = 0, precision: str = "fp32",
                    layout: Optional[str] = None, dump: bool = False, schedule: str = "persistent",
-                   chunk_paths: int = 0, blocks_per_cu: int = 0) -> Dict[str, torch.Tensor]:
+                   chunk_paths: int = 0, blocks_per_cu: int = 0, specialize: str = "auto") -> Dict[str, torch.Tensor]:
     """Marked branching estimator at every point (pdd_branching_eval).  With
-    dump=True also the per-tree values `value` [n, trees] and segment counts."""
+    dump=True also the per-tree values `value` [n, trees] and segment counts.
+    `specialize` ("auto", "on", "off"): when psi has generic terms, run a
+    kernel compiled at run time with psi's factor structure written in (same
+    results as the table-driven kernel)."""
     _need_gpu()
     keep = _Keep()
     b = A.pdd_branching_problem()
@@ -632,7 +636,7 @@ def branching_eval(problem, points, trees: int, seed: int = 0, precision: str = 
     if dump:
         dv = torch.empty(max(n * trees, 1), dtype=torch.float64, device="cuda")
         ds = torch.empty(max(n * trees, 1), dtype=torch.int64, device="cuda")
-    o = _options(precision, layout, 0, schedule, chunk_paths, blocks_per_cu, 0, dv, ds)
+    o = _options(precision, layout, 0, schedule, chunk_paths, blocks_per_cu, 0, dv, ds, specialize=specialize)
     st = library().pdd_branching_eval(C.byref(b), pt.data_ptr() if n else None, n, int(trees),
                                       int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(), _stream_handle())
     _check(st, "pdd_branching_eval")
@@ -646,12 +650,14 @@ def branching_eval(problem, points, trees: int, seed: int = 0, precision: str = 
 
 def branching_bvp(problem, boundary, points, trees: int, seed: int = 0, precision: str = "fp32",
                   layout: Optional[str] = None, dump: bool = False, chunk_paths: int = 0,
-                  blocks_per_cu: int = 0, boundary_correction: bool = False) -> Dict[str, torch.Tensor]:
+                  blocks_per_cu: int = 0, boundary_correction: bool = False,
+                  specialize: str = "auto") -> Dict[str, torch.Tensor]:
     """Branching estimator with particles stopped on a Dirichlet boundary,
     evaluated at every output time of one tree (pdd_branching_bvp).
     `boundary` is a workloads.problem.BranchingBoundary.  Statistics have
     shape [n_times, n_points]; with dump=True also `value` [n, trees, n_times]
-    and `segments` [n, trees]."""
+    and `segments` [n, trees].  `specialize` as for branching_eval (psi or g
+    with generic terms)."""
     _need_gpu()
     keep = _Keep()
     b = A.pdd_branching_problem()
@@ -684,7 +690,8 @@ def branching_bvp(problem, boundary, points, trees: int, seed: int = 0, precisio
     if dump:
         dv = torch.empty(max(n * trees * nt, 1), dtype=torch.float64, device="cuda")
         ds = torch.empty(max(n * trees, 1), dtype=torch.int64, device="cuda")
-    o = _options(precision, layout, 0, "persistent", chunk_paths, blocks_per_cu, 0, dv, ds, boundary_correction)
+    o = _options(precision, layout, 0, "persistent", chunk_paths, blocks_per_cu, 0, dv, ds, boundary_correction,
+                 specialize)
     st = library().pdd_branching_bvp(C.byref(b), C.byref(bd), pt.data_ptr() if n else None, n, int(trees),
                                      int(seed) & (2 ** 64 - 1), C.byref(o), raw.data_ptr(), _stream_handle())
     _check(st, "pdd_branching_bvp")

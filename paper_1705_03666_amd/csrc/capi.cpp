@@ -1528,6 +1528,30 @@ void fill_branch_params(const pdd_branching_problem& B, uint64_t seed, Tables& T
   bp.n_fac = (int)T.fac.size();
 }
 
+// Problem-specialised branching kernel when psi (or g) has generic terms,
+// under options.specialize as for the walks: 0 = compile at run time and fall
+// back to the table-driven kernel (with a note on stderr), 1 = required, -1 =
+// never.  *fn stays null when the table-driven kernel is to be used.
+pdd_status branch_spec(const pdd_options& o, const BranchParams& bp, const DevFun* g, const Tables& T, bool fp32,
+                       int dim, bool boundary, hipFunction_t* fn) {
+  *fn = nullptr;
+  const bool terms = bp.psi.n_terms > 0 || (g != nullptr && g->n_terms > 0);
+  if (!terms || o.specialize < 0) return PDD_OK;
+  const std::string src = spec_psi_source(bp.psi, g, T.fac);
+  std::string why = "a scale or shift is not finite";
+  if (src.empty() ||
+      !spec_branch_kernel(src, fp32, dim, fp32 ? (int)PDD_RNG_QUAD24 : o.rng_layout, boundary, fn, &why)) {
+    *fn = nullptr;
+    if (o.specialize == 1) return fail(PDD_ERR_HIP, "problem-specialised kernel: " + why);
+    static std::once_flag once;
+    std::call_once(once, [&] {
+      std::fprintf(stderr, "pdd: problem-specialised branching kernel unavailable, using the table-driven kernel: %s\n",
+                   why.c_str());
+    });
+  }
+  return PDD_OK;
+}
+
 pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, int64_t n_points, int64_t trees,
                          uint64_t seed, const pdd_options* op, pdd_node_stat* out, hipStream_t st) {
   if (Bp == nullptr || op == nullptr) return fail(PDD_ERR_INVALID_ARG, "problem or options is NULL");
@@ -1552,6 +1576,8 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   Tables T;
   BranchParams& bp = pl.bp;
   fill_branch_params(B, seed, T, bp);
+  hipFunction_t spec = nullptr;
+  if ((s = branch_spec(o, bp, nullptr, T, fp32, B.dim, false, &spec)) != PDD_OK) return s;
   const Tuning tune = choose_schedule(PDD_KERNEL_BRANCH, B.dim, fp32 ? PDD_FP32_STEP : PDD_FP64, o, device_cus(),
                                       n_points * trees);
   Items items = make_items(n_points, nullptr, trees, tune.chunk_paths, {});
@@ -1559,7 +1585,7 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   const int max_blocks = tune.blocks_per_cu * device_cus();
   const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
   const int grid = std::max(1, std::min(max_blocks, need));
-  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32, B.dim, false));
+  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32));
 
   Arena A;
   const size_t o_call = add_call_block(A, T.jobs.size());
@@ -1615,6 +1641,7 @@ pdd_status run_branching(const pdd_branching_problem* Bp, const double* points, 
   BL.trees = trees;
   BL.stack = base + o_spill;
   BL.stack_entries = spill_entries;
+  BL.spec = spec;
   hipError_t e = pl.enqueue(st);
   (void)lease.done();
   if (e != hipSuccess) return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -1702,6 +1729,8 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   }
   bb.g = T.add(Bd.g, B.dim, 0, true);
   bp.n_fac = (int)T.fac.size();
+  hipFunction_t spec = nullptr;
+  if ((s = branch_spec(o, bp, &bb.g, T, fp32, B.dim, true, &spec)) != PDD_OK) return s;
 
   const Tuning tune = choose_schedule(PDD_KERNEL_BRANCH_BVP, B.dim, fp32 ? PDD_FP32_STEP : PDD_FP64, o,
                                       device_cus(), n_points * trees);
@@ -1710,7 +1739,7 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   const int max_blocks = tune.blocks_per_cu * device_cus();
   const int need = (n_items + kBlock / kWave - 1) / (kBlock / kWave);
   const int grid = std::max(1, std::min(max_blocks, need));
-  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32, B.dim, true));
+  const int64_t spill_entries = std::max(0, B.max_segments - branch_lds_depth(fp32));
 
   Arena A;
   const size_t o_call = add_call_block(A, T.jobs.size());
@@ -1768,6 +1797,7 @@ pdd_status run_branching_bvp(const pdd_branching_problem* Bp, const pdd_branchin
   L.trees = trees;
   L.stack = base + o_spill;
   L.stack_entries = spill_entries;
+  L.spec = spec;
   hipError_t e = pl.enqueue(st);
   (void)lease.done();
   if (e != hipSuccess) return fail(PDD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));

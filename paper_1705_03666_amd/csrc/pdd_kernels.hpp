@@ -89,6 +89,7 @@ struct BranchLaunch {
   int64_t trees;
   void* stack;               // spill stack for deep trees
   int64_t stack_entries;     // entries per lane
+  hipFunction_t spec;        // problem-specialised k_branch (same arguments), or null
 };
 
 // Branching with a Dirichlet boundary and output times; istat is
@@ -108,6 +109,7 @@ struct BranchBvpLaunch {
   int64_t trees;
   void* stack;
   int64_t stack_entries;
+  hipFunction_t spec;        // problem-specialised k_branch_bvp (same arguments), or null
 };
 
 hipError_t launch_walk(const WalkLaunch& L, hipStream_t st);
@@ -117,8 +119,8 @@ hipError_t launch_plain_adj(const PlainLaunch& L, hipStream_t st);
 hipError_t launch_branch(const BranchLaunch& L, hipStream_t st);
 hipError_t launch_branch_bvp(const BranchBvpLaunch& L, hipStream_t st);
 size_t branch_stack_entry_bytes(bool fp32);
-// LDS stack entries per lane of k_branch (boundary = false) or k_branch_bvp
-int branch_lds_depth(bool fp32, int dim, bool boundary);
+// LDS stack entries per lane of k_branch and k_branch_bvp
+int branch_lds_depth(bool fp32);
 hipError_t launch_finalize_nodes(const ItemStat* istat, const int64_t* first, int64_t n_nodes, const CallPtrs* cp,
                                  int64_t out_off, unsigned long long* counters, hipStream_t st);
 hipError_t launch_finalize_grad(const double* igrad, int stride, int n_cols, int n_items, const int32_t* slot_node,

@@ -1,4 +1,4 @@
-// Problem-specialised walk kernels (host side).
+// Problem-specialised walk and branching kernels (host side).
 //
 // A problem whose b, c or f carry generic terms (products of exp, sin, cos,
 // tanh and powers of affine functions of one coordinate) pays, in the
@@ -13,6 +13,12 @@
 // another wavefront's instruction that reads a scalar register), while g's
 // stay in the table.  The specialised kernel evaluates the same products in
 // the same order as the table-driven one.
+//
+// The branching kernels get the same treatment for psi (at leaves and output
+// times) and g (at boundary stops): a generated policy struct with their
+// factor structure written in replaces the table walk; coefficients are read
+// from the staged table as in the table-driven kernels, and the results are
+// the same bits.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -36,5 +42,17 @@ std::string spec_terms_source(const LinearParams& P, const std::vector<DevFactor
 // ~/.cache/pdd_jit).
 bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc, int layout, bool adjoint,
                       hipFunction_t* fn, std::string* err);
+
+// Source of the psi / g policy (struct pdd_spec::SpecPsi) of the branching
+// kernels for psi (and, with a boundary, g: coordinates 0..dim-1 and the time
+// argument as coordinate dim) described by the factor records `fac`; empty
+// when a value cannot be written as a literal.
+std::string spec_psi_source(const DevFun& psi, const DevFun* g, const std::vector<DevFactor>& fac);
+
+// Loads (compiling on first use, per device) k_branch<R, DIM, LAYOUT,
+// SpecPsi>, or k_branch_bvp with `boundary`; caches and errors as for
+// spec_walk_kernel.
+bool spec_branch_kernel(const std::string& psi_src, bool fp32, int dim, int layout, bool boundary,
+                        hipFunction_t* fn, std::string* err);
 
 }  // namespace pdd

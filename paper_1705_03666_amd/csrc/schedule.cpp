@@ -109,16 +109,16 @@ bool lookup(int kernel, int dim, int precision, Entry* out) {
 // Built-in defaults, measured on MI355X: the 3-D C5 walk (forward and
 // adjoint alike) for the linear kernels; C4 / C7 (k_branch) and C6
 // (k_branch_bvp), 1024 points x 1e5 trees, for branching: four blocks per
-// CU (the FP32 branching kernels are built for four waves per SIMD), items of
-// 16384 trees for k_branch (2 blocks and 2048-tree items took 2.0x on C4) and
-// of 4096 trees for k_branch_bvp, whose trees are long enough that the last
-// items of a launch decide its end (16384-tree items took 1.15x on C6).  The
-// 3-D FP32 k_branch keeps a shallower LDS stack, so six blocks fit a CU; with
-// six, items of 8192 trees (C4: 4.11 ms against 4.83 ms with 16384).
+// CU (the FP32 branching kernels are built for four waves per SIMD, and
+// their LDS stacks allow four blocks), items of 16384 trees for k_branch
+// (C4: 3.36 ms against 3.60 with 8192 and 4.77 with 32768; 2 blocks and
+// 2048-tree items took 2.0x) and of 8192 trees for k_branch_bvp, whose trees
+// are long enough that the last items of a launch decide its end (C6: 233.5
+// ms against 238.1 with 4096).
 Entry defaults(int kernel, bool fp32, int dim) {
-  if (kernel == PDD_KERNEL_BRANCH && fp32 && dim == 3) return Entry{8192, 6, 1};
+  (void)dim;
   if (kernel == PDD_KERNEL_BRANCH) return Entry{16384, fp32 ? 4 : 2, 1};
-  if (kernel == PDD_KERNEL_BRANCH_BVP) return Entry{4096, fp32 ? 4 : 2, 1};
+  if (kernel == PDD_KERNEL_BRANCH_BVP) return Entry{8192, fp32 ? 4 : 2, 1};
   // the adjoint / value+Jacobian walk: the autotuner's choice on C5 (items of
   // 32768 paths, 0.3-1% ahead of 16384)
   if (kernel == PDD_KERNEL_WALK_ADJOINT && fp32) return Entry{32768, 8, 3};

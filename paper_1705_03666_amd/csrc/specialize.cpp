@@ -1,5 +1,5 @@
-// Problem-specialised walk kernels: source generation, runtime compilation
-// (hiprtc) and a two-level cache of the compiled code objects.
+// Problem-specialised walk and branching kernels: source generation, runtime
+// compilation (hiprtc) and a two-level cache of the compiled code objects.
 #include "pdd_spec.hpp"
 
 #include <hip/hiprtc.h>
@@ -238,8 +238,71 @@ std::string spec_terms_source(const LinearParams& P, const std::vector<DevFactor
   return o.str();
 }
 
-bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc, int layout, bool adjoint,
-                      hipFunction_t* fn, std::string* err) {
+namespace {
+
+// Sum of the generic terms of F at the coordinates `x` (DIMS of them), then
+// its dense polynomial part at `xp` (degree and offset written in, so the
+// loops unroll), into `v`: the operations of terms_sum and poly_nested in
+// their order.
+bool emit_fun(std::ostringstream& o, const DevFun& F, const std::vector<DevFactor>& fac, const char* dims,
+              const char* x, const char* xp) {
+  o << "    R v = (R)0;\n";
+  if (F.n_terms > 0) {
+    o << "    {\n      R s = (R)0;\n";
+    for (int t = 0; t < F.n_terms; ++t) {
+      o << "      {\n        R p = (R)1;\n";
+      for (int j = 0; j < F.n_factors; ++j) {
+        const DevFactor& d = fac[(size_t)(F.fac_off + t * F.n_factors + j)];
+        std::string a, b;
+        if (!literal(d.ad, &a) || !literal(d.bd, &b)) return false;
+        o << "        p *= pdd::factor_fixed<R, " << dims << ", " << d.fn << ", " << d.power << ">(" << x << ", "
+          << d.dim << ", " << a << ", " << b << ");\n";
+      }
+      o << "        s += pdd::coef_const<R>(P.cd, P.cf, " << (F.coef_off + t) << ") * p;\n      }\n";
+    }
+    o << "      v = s;\n    }\n";
+  }
+  if (F.poly_deg >= 0)
+    o << "    v += pdd::poly_nested<R, DIM>(P.cd, P.cf, " << F.poly_deg << ", " << F.poly_off << ", " << xp << ");\n";
+  o << "    return v;\n";
+  return true;
+}
+
+}  // namespace
+
+std::string spec_psi_source(const DevFun& psi, const DevFun* g, const std::vector<DevFactor>& fac) {
+  std::ostringstream o;
+  o << "namespace pdd_spec {\n"
+       "struct SpecPsi {\n"
+       "  template <typename R, int DIM>\n"
+       "  __device__ static __forceinline__ R psi(const pdd::BranchParams& P, const R* x) {\n"
+       "    (void)P;\n";
+  if (!emit_fun(o, psi, fac, "DIM", "x", "x")) return "";
+  o << "  }\n";
+  if (g != nullptr) {
+    o << "  template <typename R, int DIM>\n"
+         "  __device__ static __forceinline__ R g(const pdd::BranchParams& P, const pdd::BranchBoundary& B,\n"
+         "                                        const R* xp, R ts) {\n"
+         "    (void)P;\n"
+         "    (void)B;\n"
+         "    R xs[DIM + 1];\n"
+         "#pragma unroll\n"
+         "    for (int k = 0; k < DIM; ++k) xs[k] = xp[k];\n"
+         "    xs[DIM] = ts;\n"
+         "    (void)xs;\n";
+    if (!emit_fun(o, *g, fac, "DIM + 1", "xs", "xp")) return "";
+    o << "  }\n";
+  }
+  o << "};\n"
+       "}  // namespace pdd_spec\n";
+  return o.str();
+}
+
+namespace {
+
+// Loads the instantiation `name` of `src` for the current device: from the
+// in-memory table, else from the disk cache, else compiled now.
+bool load_spec(const std::string& name, const std::string& src, hipFunction_t* fn, std::string* err) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     *err = "hipGetDevice failed";
@@ -251,11 +314,6 @@ bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc,
     return false;
   }
   const std::string arch = prop.gcnArchName;
-  std::ostringstream nm;
-  nm << "pdd::k_walk<" << (fp32 ? "float" : "double") << ", " << dim << ", " << dfc << ", " << layout << ", true, "
-     << (adjoint ? "true" : "false") << ", false, pdd_spec::SpecTerms>";
-  const std::string name = nm.str();
-  const std::string src = "#include \"walk_kernels.hpp\"\n" + terms_src;
   // the key covers the generated source, the instantiation, the target and
   // the embedded device headers
   std::string key = arch + "\n" + name + "\n" + src;
@@ -305,6 +363,25 @@ bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc,
   g_spec[mkey] = f;
   *fn = f;
   return true;
+}
+
+}  // namespace
+
+bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc, int layout, bool adjoint,
+                      hipFunction_t* fn, std::string* err) {
+  std::ostringstream nm;
+  nm << "pdd::k_walk<" << (fp32 ? "float" : "double") << ", " << dim << ", " << dfc << ", " << layout << ", true, "
+     << (adjoint ? "true" : "false") << ", false, pdd_spec::SpecTerms>";
+  const std::string name = nm.str();
+  return load_spec(name, "#include \"walk_kernels.hpp\"\n" + terms_src, fn, err);
+}
+
+bool spec_branch_kernel(const std::string& psi_src, bool fp32, int dim, int layout, bool boundary,
+                        hipFunction_t* fn, std::string* err) {
+  std::ostringstream nm;
+  nm << "pdd::" << (boundary ? "k_branch_bvp<" : "k_branch<") << (fp32 ? "float" : "double") << ", " << dim << ", "
+     << layout << ", pdd_spec::SpecPsi>";
+  return load_spec(nm.str(), "#include \"branch_kernels.hpp\"\n" + psi_src, fn, err);
 }
 
 }  // namespace pdd

@@ -552,6 +552,38 @@ def test_branching_bvp_fp64_matches_oracle_per_tree(pdd, orc, case, layout):
         assert np.all(g["steps"][k].cpu().numpy() == o["steps"][k])
 
 
+# ----------------------------------------------------------------------------- problem-specialised branching kernels
+def _same_trees(a, b, what):
+    assert torch.equal(a["segments"], b["segments"]), what
+    assert torch.equal(a["value"], b["value"]), what
+    for k in ("mean", "m2", "n", "steps"):
+        assert torch.equal(a[k], b[k]), (what, k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_specialised_branching_matches_table_kernel_per_tree(pdd, precision):
+    """psi (and g) compiled in at run time: the same operations in the same
+    order as the table-driven kernels, so the same segments and bit for bit
+    the same value for every tree and the same statistics, with and without a
+    boundary, in 1-3 dimensions."""
+    for case in sorted(BR_CASES):
+        B, pts = BR_CASES[case]()
+        kw = dict(precision=precision, dump=True, chunk_paths=200)
+        log(f"specialised vs table branching: case={case} {precision}")
+        a = pdd.branching_eval(B, pts, 600, 4, specialize="on", **kw)
+        b = pdd.branching_eval(B, pts, 600, 4, specialize="off", **kw)
+        torch.cuda.synchronize()
+        _same_trees(a, b, case)
+    for case in sorted(BVP_CASES):
+        B, Bd, pts = BVP_CASES[case]()
+        kw = dict(precision=precision, dump=True, chunk_paths=100)
+        log(f"specialised vs table branching with a boundary: case={case} {precision}")
+        a = pdd.branching_bvp(B, Bd, pts, 300, 4, specialize="on", **kw)
+        b = pdd.branching_bvp(B, Bd, pts, 300, 4, specialize="off", **kw)
+        torch.cuda.synchronize()
+        _same_trees(a, b, case)
+
+
 @pytest.mark.parametrize("case", ["tw_interval", "marked_box3"])
 def test_branching_bvp_boundary_correction_matches_oracle_per_tree(pdd, orc, case):
     B, Bd, pts = BVP_CASES[case]()
