@@ -55,4 +55,16 @@ std::string spec_psi_source(const DevFun& psi, const DevFun* g, const std::vecto
 bool spec_branch_kernel(const std::string& psi_src, bool fp32, int dim, int layout, bool boundary,
                         hipFunction_t* fn, std::string* err);
 
+// The pieces of the two loaders above, for checks that compile without
+// loading (no GPU needed): the instantiation names and full sources of the
+// specialised kernels, and the runtime compilation itself (code object and
+// lowered kernel name for the target `arch`, e.g. "gfx950"; false with the
+// compiler log in *err on failure).
+std::string spec_walk_name(bool fp32, int dim, int dfc, int layout, bool adjoint);
+std::string spec_walk_source(const std::string& terms_src);
+std::string spec_branch_name(bool fp32, int dim, int layout, bool boundary);
+std::string spec_branch_source(const std::string& psi_src);
+bool spec_compile(const std::string& src, const std::string& name, const std::string& arch, std::string* code,
+                  std::string* lowered, std::string* err);
+
 }  // namespace pdd

@@ -120,8 +120,13 @@ void make_dirs(const std::string& d) {
     if (i == d.size() || d[i] == '/') mkdir(d.substr(0, i).c_str(), 0755);
 }
 
-bool compile(const std::string& src, const std::string& name, const std::string& arch, std::string* code,
-             std::string* lowered, std::string* err) {
+std::mutex g_spec_mu;
+std::map<std::string, hipFunction_t> g_spec;   // (device, key) -> loaded kernel
+
+}  // namespace
+
+bool spec_compile(const std::string& src, const std::string& name, const std::string& arch, std::string* code,
+                  std::string* lowered, std::string* err) {
   hiprtcProgram prog;
   if (hiprtcCreateProgram(&prog, src.c_str(), "pdd_spec.hip", kRtcHeaderCount, kRtcHeaderBodies, kRtcHeaderNames) !=
       HIPRTC_SUCCESS) {
@@ -160,11 +165,6 @@ bool compile(const std::string& src, const std::string& name, const std::string&
   hiprtcDestroyProgram(&prog);
   return true;
 }
-
-std::mutex g_spec_mu;
-std::map<std::string, hipFunction_t> g_spec;   // (device, key) -> loaded kernel
-
-}  // namespace
 
 std::string spec_terms_source(const LinearParams& P, const std::vector<DevFactor>& fac) {
   std::ostringstream term, sum, load;
@@ -334,7 +334,7 @@ bool load_spec(const std::string& name, const std::string& src, hipFunction_t* f
   std::string code, lowered;
   const bool have = !path.empty() && read_entry(path, key, &lowered, &code);
   if (!have) {
-    if (!compile(src, name, arch, &code, &lowered, err)) return false;
+    if (!spec_compile(src, name, arch, &code, &lowered, err)) return false;
     if (!path.empty()) {
       make_dirs(dir);
       write_entry(path, key, lowered, code);
@@ -346,7 +346,7 @@ bool load_spec(const std::string& name, const std::string& src, hipFunction_t* f
     // an entry that does not load (written by another runtime version, or
     // damaged in place): compile afresh and replace it
     (void)hipGetLastError();
-    if (!compile(src, name, arch, &code, &lowered, err)) return false;
+    if (!spec_compile(src, name, arch, &code, &lowered, err)) return false;
     e = hipModuleLoadData(&mod, code.data());
     if (e == hipSuccess) write_entry(path, key, lowered, code);
   }
@@ -367,21 +367,32 @@ bool load_spec(const std::string& name, const std::string& src, hipFunction_t* f
 
 }  // namespace
 
-bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc, int layout, bool adjoint,
-                      hipFunction_t* fn, std::string* err) {
+std::string spec_walk_name(bool fp32, int dim, int dfc, int layout, bool adjoint) {
   std::ostringstream nm;
   nm << "pdd::k_walk<" << (fp32 ? "float" : "double") << ", " << dim << ", " << dfc << ", " << layout << ", true, "
      << (adjoint ? "true" : "false") << ", false, pdd_spec::SpecTerms>";
-  const std::string name = nm.str();
-  return load_spec(name, "#include \"walk_kernels.hpp\"\n" + terms_src, fn, err);
+  return nm.str();
 }
 
-bool spec_branch_kernel(const std::string& psi_src, bool fp32, int dim, int layout, bool boundary,
-                        hipFunction_t* fn, std::string* err) {
+std::string spec_walk_source(const std::string& terms_src) { return "#include \"walk_kernels.hpp\"\n" + terms_src; }
+
+bool spec_walk_kernel(const std::string& terms_src, bool fp32, int dim, int dfc, int layout, bool adjoint,
+                      hipFunction_t* fn, std::string* err) {
+  return load_spec(spec_walk_name(fp32, dim, dfc, layout, adjoint), spec_walk_source(terms_src), fn, err);
+}
+
+std::string spec_branch_name(bool fp32, int dim, int layout, bool boundary) {
   std::ostringstream nm;
   nm << "pdd::" << (boundary ? "k_branch_bvp<" : "k_branch<") << (fp32 ? "float" : "double") << ", " << dim << ", "
      << layout << ", pdd_spec::SpecPsi>";
-  return load_spec(nm.str(), "#include \"branch_kernels.hpp\"\n" + psi_src, fn, err);
+  return nm.str();
+}
+
+std::string spec_branch_source(const std::string& psi_src) { return "#include \"branch_kernels.hpp\"\n" + psi_src; }
+
+bool spec_branch_kernel(const std::string& psi_src, bool fp32, int dim, int layout, bool boundary,
+                        hipFunction_t* fn, std::string* err) {
+  return load_spec(spec_branch_name(fp32, dim, layout, boundary), spec_branch_source(psi_src), fn, err);
 }
 
 }  // namespace pdd
