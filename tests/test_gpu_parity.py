@@ -560,12 +560,43 @@ def _same_trees(a, b, what):
         assert torch.equal(a[k], b[k]), (what, k)
 
 
+def _poly_cases():
+    """psi and g with generic terms and a dense polynomial part (whose degree
+    and offset the specialised kernel has written in): free 2-D, and 3-D
+    with a boundary."""
+    from workloads.problem import BranchingBoundary
+    psi2 = make_fun([(0.3, []), (0.2, [factor("cos", 1)])], poly_degree=2,
+                    poly=[0.05, 0.1, -0.08, 0.02, -0.03, 0.04])
+    free2 = (BranchingProblem(2, 1.0, 1.0, 0.8, (0.5, 0, 0.5, 0, 0), (0.5, 0, 0.5, 0, 0), psi2, 0.8),
+             np.array([[0.1, -0.2], [0.4, 0.3]]))
+    psi3 = make_fun([(0.2, [factor("tanh", 2, a=0.5)])], poly_degree=1, poly=[0.3, 0.05, -0.05, 0.02])
+    g3 = make_fun([(0.25, [factor("cos", 3, a=2.0)]), (0.1, [factor("sin", 0)])], poly_degree=2,
+                  poly=[0.2, 0.01, 0.02, -0.03, 0.04, 0.0, 0.01, -0.02, 0.0, 0.03])
+    B3 = BranchingProblem(3, 1.0, 1.1, 0.8, (0.2, 0.0, 0.8, 0.0, 0.0), (0.3, 0.0, 0.7, 0.0, 0.0), psi3, 0.6,
+                          max_segments=200)
+    Bd3 = BranchingBoundary(box((-0.6, -0.6, -0.6), (0.6, 0.6, 0.6)), g3, 0.8, 0.05, (0.0, 0.4, 0.8))
+    return free2, (B3, Bd3, np.array([[0.0, 0.1, -0.2], [0.45, -0.3, 0.2]]))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_specialised_branching_matches_table_kernel_per_tree(pdd, precision):
     """psi (and g) compiled in at run time: the same operations in the same
     order as the table-driven kernels, so the same segments and bit for bit
     the same value for every tree and the same statistics, with and without a
-    boundary, in 1-3 dimensions."""
+    boundary, in 1-3 dimensions, with and without dense polynomial parts."""
+    (B2, p2), (B3, Bd3, p3) = _poly_cases()
+    kw = dict(precision=precision, dump=True, chunk_paths=200)
+    log(f"specialised vs table branching: psi with a polynomial part {precision}")
+    a = pdd.branching_eval(B2, p2, 600, 4, specialize="on", **kw)
+    b = pdd.branching_eval(B2, p2, 600, 4, specialize="off", **kw)
+    torch.cuda.synchronize()
+    _same_trees(a, b, "psi with a polynomial part")
+    kw = dict(precision=precision, dump=True, chunk_paths=100)
+    log(f"specialised vs table branching with a boundary: psi and g with polynomial parts {precision}")
+    a = pdd.branching_bvp(B3, Bd3, p3, 300, 4, specialize="on", **kw)
+    b = pdd.branching_bvp(B3, Bd3, p3, 300, 4, specialize="off", **kw)
+    torch.cuda.synchronize()
+    _same_trees(a, b, "psi and g with polynomial parts")
     for case in sorted(BR_CASES):
         B, pts = BR_CASES[case]()
         kw = dict(precision=precision, dump=True, chunk_paths=200)
