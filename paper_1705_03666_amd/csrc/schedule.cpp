@@ -122,9 +122,12 @@ Entry defaults(int kernel, bool fp32, int dim) {
   // the adjoint / value+Jacobian walk: the autotuner's choice on C5 (items of
   // 32768 paths, 0.3-1% ahead of 16384)
   if (kernel == PDD_KERNEL_WALK_ADJOINT && fp32) return Entry{32768, 8, 3};
-  // the heterogeneous batch: the autotuner's choice on the C3 batch (items of
-  // 4096 paths, 6 blocks per CU; 37 ms against 47 ms at 16384 / 8)
-  if (kernel == PDD_KERNEL_WALK_BATCH || kernel == PDD_KERNEL_WOS_BATCH) return Entry{4096, fp32 ? 6 : 4, 4};
+  // the heterogeneous batch: items of 4096 paths, 6 blocks per CU (C3, Euler:
+  // 27.3 ms against 28.7 with 2048 and 27.8 with 8192), refills every 6 step
+  // groups for Euler (27.9 ms with 4, 29.3 with 2), every 2 for walk on
+  // spheres, whose paths are short (3.83 ms against 4.04 with 4, 4.47 with 6)
+  if (kernel == PDD_KERNEL_WALK_BATCH) return Entry{4096, fp32 ? 6 : 4, 6};
+  if (kernel == PDD_KERNEL_WOS_BATCH) return Entry{4096, fp32 ? 6 : 4, 2};
   return Entry{16384, fp32 ? 8 : 4, 3};
 }
 

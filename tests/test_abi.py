@@ -375,7 +375,7 @@ def test_schedule_table_set_get_save_load_and_item_size(abi, tmp_path):
     # built-in defaults of the other kernels
     for kernel, dim, want in ((abi.PDD_KERNEL_WALK_ADJOINT, 3, (32768, 8, 3)), (abi.PDD_KERNEL_BRANCH, 1, (16384, 4, 1)),
                               (abi.PDD_KERNEL_BRANCH, 3, (16384, 4, 1)), (abi.PDD_KERNEL_BRANCH_BVP, 1, (8192, 4, 1)),
-                              (abi.PDD_KERNEL_WALK_BATCH, 0, (4096, 6, 4))):
+                              (abi.PDD_KERNEL_WALK_BATCH, 0, (4096, 6, 6)), (abi.PDD_KERNEL_WOS_BATCH, 0, (4096, 6, 2))):
         assert lib.pdd_set_schedule(kernel, dim, FP32, None) == 0
         assert lib.pdd_get_schedule(kernel, dim, FP32, C.byref(out), C.byref(tuned)) == 0
         assert (out.chunk_paths, out.blocks_per_cu, out.refill_groups, tuned.value) == want + (0,), (kernel, dim)
