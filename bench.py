@@ -70,9 +70,9 @@ OPS_PER_PS_ADJ_SURVEY = 230.0
 # kernel sources and the schedule they were counted on: otherwise the bench
 # reports null.
 TRAFFIC_SOURCES = ['paper_1705_03666_amd/csrc/walk_kernels.hpp', 'paper_1705_03666_amd/csrc/pdd_device.hpp', 'paper_1705_03666_amd/csrc/pdd_internal.hpp', 'paper_1705_03666_amd/csrc/walk_adj_f32.hip']
-TRAFFIC_SHA256 = "0da4b453361811ca76c80c56fb7cd615eb25269d18cdd1336590644071a9a7d2"
+TRAFFIC_SHA256 = "2be92012d1389510fa494e35ddad7e11c09923fcce68f3ddbc21ac6344958726"
 TRAFFIC_SCHEDULE = {"chunk_paths": 32768, "blocks_per_cu": 8, "refill_groups": 3}
-TRAFFIC_BYTES = 61.10e6 + 238.48e6
+TRAFFIC_BYTES = 60.83e6 + 238.86e6
 
 
 def traffic_bytes(schedule=None):

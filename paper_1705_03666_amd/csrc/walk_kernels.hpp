@@ -528,18 +528,33 @@ k_walk(const LinearParams P, const WorkItem* __restrict__ items, int n_items, ui
         for (int s = 0; s < GS::G; ++s) {
           if constexpr (WOS) {
             // walk on spheres: jump by the distance to the boundary in the
-            // direction of this jump's Gaussians, or stop inside the eps shell
-            if (alive && n < max_steps) {
-              const R r = boundary_distance<R, DIM>(D, X);
-              if (!(r >= dt)) {
-                alive = false;
-                fin = true;
-              } else {
-                const R z2 = sum_squares<R, DIM>(&z[s * DIM]);
-                jump_sphere<R, DIM>(X, r, z2, &z[s * DIM]);
-                ++n;
-              }
-            }
+            // direction of this jump's Gaussians, or stop inside the eps
+            // shell.  Predicated, not branched (the branch's exec-mask
+            // bookkeeping is scalar work, and the scalar unit bounds these
+            // short steps): a lane that stops or is inactive jumps by a
+            // radius of 0, an active one by the same operations.
+            const bool act = alive && n < max_steps;
+            const R r = boundary_distance<R, DIM>(D, X);
+            const bool stop = act && !(r >= dt);
+            const bool jump = act && (r >= dt);
+            const R z2 = sum_squares<R, DIM>(&z[s * DIM]);
+            jump_sphere<R, DIM>(X, jump ? r : (R)0, z2, &z[s * DIM]);
+            n += jump ? 1u : 0u;
+            alive = alive && !stop;
+            fin = fin || stop;
+            continue;
+          }
+          if constexpr (DFC < 0 && !TERMS && !ADJ) {
+            // b = c = f = 0 (no polynomial, no terms): the pure-diffusion
+            // step, predicated the same way (an inactive lane adds 0 z)
+            const bool act = alive && n < max_steps;
+            const R m = act ? sdt : (R)0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) X[k] = X[k] + m * z[s * DIM + k];
+            n += act ? 1u : 0u;
+            const bool out = act && !inside<R, DIM>(Dt, X);
+            alive = alive && !out;
+            fin = fin || out;
             continue;
           }
           if (alive && n < max_steps) {
