@@ -591,6 +591,14 @@ def test_specialised_branching_matches_table_kernel_per_tree(pdd, precision):
     b = pdd.branching_eval(B2, p2, 600, 4, specialize="off", **kw)
     torch.cuda.synchronize()
     _same_trees(a, b, "psi with a polynomial part")
+    # psi without generic terms (a polynomial only): nothing to specialise,
+    # so "on" runs the table-driven kernel instead of failing
+    psi_poly = make_fun([], poly_degree=2, poly=[0.3, 0.05, -0.04, 0.02, 0.01, -0.03])
+    Bp = BranchingProblem(2, 1.0, 1.0, 0.8, (0.5, 0, 0.5, 0, 0), (0.5, 0, 0.5, 0, 0), psi_poly, 0.6)
+    a = pdd.branching_eval(Bp, p2, 300, 4, specialize="on", **kw)
+    b = pdd.branching_eval(Bp, p2, 300, 4, specialize="off", **kw)
+    torch.cuda.synchronize()
+    _same_trees(a, b, "psi without terms")
     kw = dict(precision=precision, dump=True, chunk_paths=100)
     log(f"specialised vs table branching with a boundary: psi and g with polynomial parts {precision}")
     a = pdd.branching_bvp(B3, Bd3, p3, 300, 4, specialize="on", **kw)
