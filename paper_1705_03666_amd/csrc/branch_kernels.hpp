@@ -108,6 +108,59 @@ __device__ __forceinline__ void br_normals(uint64_t label, int attempt, uint32_t
   for (int k = 0; k < DIM; ++k) z[k] = tmp[k];
 }
 
+// Both Philox blocks of an FP32 segment (stream 1: lifetime and type
+// uniforms; stream 2: the Gaussians) computed round by round side by side:
+// the same two blocks as br_uniforms and br_normals, with four independent
+// products per round instead of two, and one key schedule for both (C4
+// 3.45 -> 3.37 ms, C7 2.09 -> 2.06 ms; the trees are bitwise unchanged).
+__device__ __forceinline__ void philox_pair(uint32_t* a, uint32_t* b, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t pa0 = (uint64_t)0xD2511F53u * (uint64_t)a[0];
+    const uint64_t pa1 = (uint64_t)0xCD9E8D57u * (uint64_t)a[2];
+    const uint64_t pb0 = (uint64_t)0xD2511F53u * (uint64_t)b[0];
+    const uint64_t pb1 = (uint64_t)0xCD9E8D57u * (uint64_t)b[2];
+    const uint32_t na0 = xor3((uint32_t)(pa1 >> 32), a[1], k0);
+    const uint32_t na2 = xor3((uint32_t)(pa0 >> 32), a[3], k1);
+    const uint32_t nb0 = xor3((uint32_t)(pb1 >> 32), b[1], k0);
+    const uint32_t nb2 = xor3((uint32_t)(pb0 >> 32), b[3], k1);
+    a[1] = (uint32_t)pa1;
+    a[3] = (uint32_t)pa0;
+    a[0] = na0;
+    a[2] = na2;
+    b[1] = (uint32_t)pb1;
+    b[3] = (uint32_t)pb0;
+    b[0] = nb0;
+    b[2] = nb2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// A segment's lifetime and type uniforms and its first DIM Gaussians.
+template <typename R, int DIM, int LAYOUT>
+__device__ __forceinline__ void br_draws(uint64_t label, int attempt, uint32_t tree, uint32_t point, uint32_t k0,
+                                         uint32_t k1, R& ulife, R& utype, R* z) {
+  if constexpr (sizeof(R) == 4 && LAYOUT == RNG_QUAD24) {
+    const uint32_t hi = ((uint32_t)attempt << 20) | (uint32_t)((label >> 32) & 0xFFFFu);
+    uint32_t a[4] = {(uint32_t)label, (1u << 24) | hi, tree, point};
+    uint32_t b[4] = {(uint32_t)label, (2u << 24) | hi, tree, point};
+    uint32_t ka = k0, kb = k1;
+    asm volatile("" : "+s"(ka), "+s"(kb));
+    philox_pair(a, b, ka, kb);
+    ulife = u24f(a[0]);
+    utype = u24f(a[1]);
+    float t[4];
+    box_muller_f(u24f(b[0]), u24f(b[1]), t[0], t[1]);
+    box_muller_f(u24f(b[2]), u24f(b[3]), t[2], t[3]);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) z[k] = t[k];
+  } else {
+    br_uniforms<R, LAYOUT>(label, attempt, tree, point, k0, k1, ulife, utype);
+    br_normals<R, DIM, LAYOUT>(label, attempt, tree, point, k0, k1, z);
+  }
+}
+
 // Offspring class of a branching particle with type uniform u: the index j
 // into the compact law (class size P.cls[j], mark P.mark[j]), i.e. the number
 // of class thresholds at or below u -- the first class whose cumulative
@@ -225,8 +278,7 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
         if (segs > P.max_segments) fail = true;
         if (!fail) {
           R ulife, utype, z[DIM];
-          br_uniforms<R, LAYOUT>(label, attempt, tree, (uint32_t)point, k0, k1, ulife, utype);
-          br_normals<R, DIM, LAYOUT>(label, attempt, tree, (uint32_t)point, k0, k1, z);
+          br_draws<R, DIM, LAYOUT>(label, attempt, tree, (uint32_t)point, k0, k1, ulife, utype, z);
           const R E = BrScalars<R>::lifetime(P, ulife);
           const R rem = Tend - tb;
           const R delta = E < rem ? E : rem;
