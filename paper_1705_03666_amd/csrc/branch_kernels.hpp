@@ -295,7 +295,8 @@ k_branch(const BranchParams P, const WorkItem* __restrict__ items, int n_items, 
               pop = true;
             } else {
               const uint64_t first = B * label;
-              if (label >= (1ull << 47) || first + (uint64_t)(I - 1) >= (1ull << 48) || sp + I - 1 > spill_entries + kLdsDepth) {
+              if (label >= (1ull << 47) || first + (uint64_t)(I - 1) >= (1ull << 48) ||
+                  sp + I - 1 > spill_entries + kLdsDepth) {
                 fail = true;
               } else {
                 const R tc = tb + E;
