@@ -416,12 +416,21 @@ def other_workloads(pdd, dev, tune=True):
     import torch
     from workloads import configs as CF
 
+    last_dev = [0.0]
+
     def timed(fn):
+        """Wall time of the second of two calls (host side included), and in
+        last_dev the device time between events recorded on the current
+        stream, the library's stream, around it."""
         fn()
         torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t = time.perf_counter()
+        e0.record()
         r = fn()
+        e1.record()
         torch.cuda.synchronize()
+        last_dev[0] = e0.elapsed_time(e1) / 1e3
         return r, time.perf_counter() - t
 
     res = {}
@@ -445,6 +454,7 @@ def other_workloads(pdd, dev, tune=True):
     nn = len(cb.paths)
     zmax, zrms = err_se(rb)
     res["c3_batch"] = {"nodes": nn, "paths": int(cb.paths.sum()), "path_steps": ps, "seconds": el,
+                       "device_seconds": last_dev[0],
                        "path_steps_per_s": ps / el, "nodes_per_s": nn / el, "launches": 1,
                        "schedule": pdd.get_schedule("walk_batch", 0, "fp32"),
                        "err_vs_exact_max_se": zmax, "err_vs_exact_rms_se": zrms}
@@ -475,7 +485,8 @@ def other_workloads(pdd, dev, tune=True):
     rw, elw = timed(run_c3_wos)
     jumps = float(rw["steps"].sum().item())
     zmax, zrms = err_se(rw)
-    res["c3_batch_walk_on_spheres"] = {"eps": 1e-4, "jumps": jumps, "seconds": elw, "jumps_per_s": jumps / elw,
+    res["c3_batch_walk_on_spheres"] = {"eps": 1e-4, "jumps": jumps, "seconds": elw, "device_seconds": last_dev[0],
+                                       "jumps_per_s": jumps / elw,
                                        "nodes_per_s": nn / elw, "launches": 1,
                                        "schedule": pdd.get_schedule("wos_batch", 0, "fp32"),
                                        "err_vs_exact_max_se": zmax, "err_vs_exact_rms_se": zrms}
@@ -495,7 +506,8 @@ def other_workloads(pdd, dev, tune=True):
     ps2 = float(r2["steps"].sum().item())
     z2 = np.abs(r2["mean"].cpu().numpy() - CF.c2_exact(c2.nodes)) / r2["se"].cpu().numpy()
     res["c2"] = {"nodes": len(c2.paths), "paths_per_node": int(c2.paths[0]), "dt": c2.dt, "path_steps": ps2,
-                 "seconds": el2, "path_steps_per_s": ps2 / el2, "nodes_per_s": len(c2.paths) / el2,
+                 "seconds": el2, "device_seconds": last_dev[0], "path_steps_per_s": ps2 / el2,
+                 "nodes_per_s": len(c2.paths) / el2,
                  "first_call_seconds_incl_kernel_compile": first2, "max_se": float(r2["se"].max().item()),
                  "err_vs_exact_max_se": float(z2.max()), "err_vs_exact_rms_se": float(np.sqrt(np.mean(z2 ** 2)))}
     log(f"bench: C2: {ps2:.3e} path-steps in {el2 * 1e3:.1f} ms, {ps2 / el2:.3e} path-steps/s (first call "
@@ -530,6 +542,7 @@ def other_workloads(pdd, dev, tune=True):
     segs = float(r4["steps"].sum().item())
     trees = float(len(c4.points) * c4.trees)
     res["c4"] = {"points": len(c4.points), "trees_per_point": c4.trees, "segments": segs, "seconds": el4,
+                 "device_seconds": last_dev[0],
                  "trees_per_s": trees / el4, "segments_per_s": segs / el4,
                  "schedule": pdd.get_schedule("branch", 3, "fp32")}
     log(f"bench: C4: {trees:.3e} trees, {segs:.3e} segments in {el4 * 1e3:.1f} ms")
@@ -546,7 +559,8 @@ def other_workloads(pdd, dev, tune=True):
     ref7 = CF.c7_reference(c7.points[:, 0])
     z7 = np.abs(scale7 * r7["mean"].cpu().numpy() - ref7) / (scale7 * r7["se"].cpu().numpy())
     res["c7_cva_marked"] = {"points": len(c7.points), "trees_per_point": c7.trees, "segments": segs7,
-                            "seconds": el7, "trees_per_s": len(c7.points) * c7.trees / el7,
+                            "seconds": el7, "device_seconds": last_dev[0],
+                            "trees_per_s": len(c7.points) * c7.trees / el7,
                             "segments_per_s": segs7 / el7, "err_vs_pde_max_se": float(z7.max()),
                             "err_vs_pde_rms_se": float(np.sqrt(np.mean(z7 ** 2)))}
     log(f"bench: C7 (CVA, marked signed quartic): {len(c7.points) * c7.trees:.3e} trees, {segs7:.3e} segments in "
@@ -564,7 +578,8 @@ def other_workloads(pdd, dev, tune=True):
     z6 = (np.abs(r6["mean"].cpu().numpy() - ex6) / np.maximum(r6["se"].cpu().numpy(), 1e-300))[1:]
     res["c6_branching_boundary"] = {"points": len(c6.points), "trees_per_point": c6.trees,
                                     "output_times": len(c6.boundary.times), "dt": c6.boundary.dt,
-                                    "particle_substeps": sub, "seconds": el6, "trees_per_s": tr6 / el6,
+                                    "particle_substeps": sub, "seconds": el6, "device_seconds": last_dev[0],
+                                    "trees_per_s": tr6 / el6,
                                     "substeps_per_s": sub / el6, "schedule": pdd.get_schedule("branch_bvp", 1, "fp32"),
                                     "err_vs_exact_max_se": float(z6.max()),
                                     "err_vs_exact_rms_se": float(np.sqrt(np.mean(z6 ** 2)))}
